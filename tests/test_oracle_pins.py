@@ -1,0 +1,287 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every check here is independent of the oracle's own formulas: the paper's
+worked example for the eigenbasis, the sector-size formula, exact brute-force
+contraction of small networks, closed-form solutions of the 2D Ising model
+(Onsager free energy and nearest-neighbour correlation, Yang magnetisation),
+a product state and basis covariance of the whole recursion.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+from oracle import basis, bruteforce, ctmrg
+from paper_2410_11596_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- basis ----
+def _read_rows(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+def test_basis_matches_paper_example():
+    """Sec. II B: the D = 2 eigenbasis of S, order and signs as printed."""
+    rows = _read_rows("hermitian_basis_D2.txt")
+    # paper's plain order (1 1b), (2 1b), (1 2b), (2 2b): (ket, bra), 1-based
+    paper_states = [(1, 1), (2, 1), (1, 2), (2, 2)]
+    r2 = 1.0 / np.sqrt(2.0)
+    U = basis.hermitian_basis(2)
+    par = basis.leg_parity(2)
+    assert len(rows) == 4
+    for i, row in enumerate(rows):
+        coeff = [{"sqrt2": r2, "-sqrt2": -r2}.get(c, None) for c in row[2:]]
+        coeff = [float(c) if v is None else v for c, v in zip(row[2:], coeff)]
+        vec = np.zeros(4)
+        for (k, kb), c in zip(paper_states, coeff):
+            vec[(k - 1) * 2 + (kb - 1)] = c   # our index: ket-major
+        assert np.array_equal(U[i], vec), (i, U[i], vec)
+        assert par[i] == (0 if row[0] == "even" else 1)
+
+
+def test_sector_dims_formula_and_spectrum_of_S():
+    """dim(even) = D + (D^2-D)/2, dim(odd) = (D^2-D)/2 (Sec. II B)."""
+    for row in _read_rows("sector_dims.txt"):
+        D, ne, no = (int(x) for x in row)
+        assert basis.sector_dims(D) == (ne, no)
+        ev = np.linalg.eigvalsh(basis.swap_matrix(D))
+        assert int(np.sum(ev > 0)) == ne and int(np.sum(ev < 0)) == no
+
+
+@pytest.mark.parametrize("D", range(1, 9))
+def test_U_orthogonal_and_diagonalises_S(D):
+    U = basis.hermitian_basis(D)
+    S = basis.swap_matrix(D)
+    ne, no = basis.sector_dims(D)
+    assert np.allclose(U @ U.T, np.eye(D * D), atol=1e-15, rtol=0)
+    target = np.diag([1.0] * ne + [-1.0] * no)
+    assert np.allclose(U @ S @ U.T, target, atol=1e-15, rtol=0)
+    assert np.allclose(S @ S, np.eye(D * D), atol=0, rtol=0)
+
+
+@pytest.mark.parametrize("D,seed", [(2, 0), (3, 1), (4, 2)])
+def test_double_layer_is_swap_invariant_bitwise(D, seed):
+    """Fig. 1e: for real A, a is invariant under swapping every bra and ket leg."""
+    A = inputs.iid_tensor(2, D, seed)
+    a = basis.double_layer(A)
+    a8 = a.reshape((D,) * 8)
+    swapped = a8.transpose(1, 0, 3, 2, 5, 4, 7, 6).reshape(a.shape)
+    assert np.array_equal(a, swapped)
+
+
+@pytest.mark.parametrize("D,seed", [(2, 0), (3, 1), (4, 2)])
+def test_rotated_double_layer_is_parity_even(D, seed):
+    """In the eigenbasis of S only blocks of even total parity survive."""
+    A = inputs.iid_tensor(2, D, seed)
+    a = basis.double_layer(A)
+    at = basis.rotate(a, basis.hermitian_basis(D))
+    p = basis.leg_parity(D)
+    odd = ~basis.parity_mask([p] * 4)
+    assert np.linalg.norm(at[odd]) <= 1e-15 * np.linalg.norm(a)
+    # the stored half is the whole tensor: 2x memory reduction (Sec. II B)
+    ne, no = basis.sector_dims(D)
+    kept = int(np.sum(~odd))
+    assert kept == sum(
+        np.prod([ne if x == 0 else no for x in pp]) for pp in itertools.product((0, 1), repeat=4) if sum(pp) % 2 == 0
+    )
+
+
+def test_heisenberg_bond_spectrum():
+    """S.S has the singlet at -3/4 and the triplet at +1/4."""
+    ev = np.sort(np.linalg.eigvalsh(ctmrg.heisenberg_bond()))
+    assert np.allclose(ev, [-0.75, 0.25, 0.25, 0.25], atol=1e-15)
+
+
+# --------------------------------------------------------- brute force ----
+def _ising_free_boundary_pair_corr(beta, rows, cols, p1, p2):
+    """<s_p1 s_p2> of the classical Ising model with free boundary, by enumeration."""
+    n = rows * cols
+    num = den = 0.0
+    for bits in range(1 << n):
+        s = np.array([1 if (bits >> k) & 1 == 0 else -1 for k in range(n)]).reshape(rows, cols)
+        e = np.sum(s[:, :-1] * s[:, 1:]) + np.sum(s[:-1, :] * s[1:, :])
+        w = np.exp(beta * e)
+        den += w
+        num += w * s[p1] * s[p2]
+    return num / den
+
+
+def test_bruteforce_contractor_against_enumeration():
+    """The row-transfer contractor reproduces an explicit sum over spins."""
+    beta = 0.35
+    A = inputs.ising_peps(beta)
+    a = basis.double_layer(A)
+    b = np.eye(2).reshape(-1)          # traced boundary = free Ising boundary
+    rho = bruteforce.rdm2_h(a, A, b, 3, 4)
+    zz = np.kron(np.diag([1.0, -1.0]), np.diag([1.0, -1.0]))
+    ref = _ising_free_boundary_pair_corr(beta, 3, 4, (1, 1), (1, 2))
+    assert abs(np.trace(rho @ zz) - ref) < 1e-13
+    # off-diagonal (s != s') entries of an Ising PEPS RDM vanish? no: check trace one
+    assert abs(np.trace(rho) - 1.0) < 1e-14
+
+
+def _rotate_site(A):
+    """Virtual legs [u,l,d,r] -> new up is old right (written out independently)."""
+    return A.transpose(0, 4, 1, 2, 3)
+
+
+@pytest.mark.parametrize("form", ["dense", "z2"])
+@pytest.mark.parametrize("which", ["iid1", "iid2", "ising0.30"])
+def test_first_iteration_is_exact(form, which):
+    """With chi >= the bond growth, one iteration represents the 5x5 patch exactly."""
+    if which.startswith("iid"):
+        A = inputs.iid_tensor(2, 2, int(which[3:]))
+    else:
+        A = inputs.ising_peps(float(which[5:]))
+    a = basis.double_layer(A)
+    b = np.eye(2).reshape(-1)
+    run = ctmrg.Run(16, form, A=A)
+    run.step(1)
+    eps_bf = bruteforce.epsilon(a, b, 5)
+    assert np.abs(run.epsilon() - eps_bf).max() <= 1e-10 * np.abs(eps_bf).max()
+    assert np.abs(run.rho1() - bruteforce.rdm1(a, A, b, 5)).max() < 1e-11
+    assert np.abs(run.rho2("h") - bruteforce.rdm2_h(a, A, b, 5, 6)).max() < 1e-11
+    Ar = _rotate_site(A)
+    rho_v = bruteforce.rdm2_h(basis.double_layer(Ar), Ar, b, 5, 6)
+    assert np.abs(run.rho2("v") - rho_v).max() < 1e-11
+
+
+def test_initial_environment_is_3x3_patch():
+    A = inputs.iid_tensor(2, 2, 3)
+    a = basis.double_layer(A)
+    run = ctmrg.Run(16, "dense", A=A)
+    eps_bf = bruteforce.epsilon(a, np.eye(2).reshape(-1), 3)
+    assert np.abs(run.epsilon() - eps_bf).max() <= 1e-13 * np.abs(eps_bf).max()
+
+
+# -------------------------------------------------------- closed forms ----
+def onsager_log_z(beta):
+    """-beta f of the square-lattice Ising model (Onsager 1944), one-integral form."""
+    k = 2.0 * np.sinh(2 * beta) / np.cosh(2 * beta) ** 2
+    f = lambda th: np.log((1.0 + np.sqrt(1.0 - k * k * np.sin(th) ** 2)) / 2.0)
+    return np.log(2.0 * np.cosh(2 * beta)) + integrate.quad(f, 0, np.pi / 2, epsabs=1e-14, limit=200)[0] / np.pi
+
+
+def onsager_log_z_double(beta):
+    """Same quantity from the double-integral form."""
+    c2, s2 = np.cosh(2 * beta) ** 2, np.sinh(2 * beta)
+    f = lambda t1, t2: np.log(c2 - s2 * (np.cos(t1) + np.cos(t2)))
+    val = integrate.dblquad(f, 0, np.pi, 0, np.pi, epsabs=1e-13)[0]
+    return np.log(2.0) + val / (2.0 * np.pi ** 2)
+
+
+def ising_nn_corr(beta):
+    """<s_i s_j> for nearest neighbours (Onsager), K with modulus k = 2 sinh 2b / cosh^2 2b."""
+    k = 2.0 * np.sinh(2 * beta) / np.cosh(2 * beta) ** 2
+    return 0.5 / np.tanh(2 * beta) * (1.0 + 2.0 / np.pi * (2.0 * np.tanh(2 * beta) ** 2 - 1.0) * special.ellipk(k * k))
+
+
+def yang_m(beta):
+    """Spontaneous magnetisation (Yang 1952), zero above the critical temperature."""
+    x = 1.0 - np.sinh(2 * beta) ** -4
+    return x ** 0.125 if x > 0 else 0.0
+
+
+def test_closed_forms_self_consistent():
+    for beta in (0.40, 0.45):
+        assert abs(onsager_log_z(beta) - onsager_log_z_double(beta)) < 1e-12
+    bc = 0.5 * np.log(1 + np.sqrt(2))
+    assert yang_m(bc - 1e-3) == 0.0 and yang_m(bc + 1e-3) > 0.0
+
+
+@pytest.mark.parametrize("beta", [0.40, 0.45])
+def test_onsager_classical_tensor(beta):
+    """Generic 4-leg CTMRG on the bond-2 classical Ising tensor, chi = 16."""
+    run = ctmrg.Run(16, "dense", a=inputs.ising_classical(beta), boundary=np.ones(2))
+    run.run(250, tol=1e-12)
+    assert abs(run.log_kappa() - onsager_log_z(beta)) < 1e-8
+
+
+@pytest.mark.parametrize("beta", [0.40, 0.45])
+def test_ising_peps_z2_against_onsager_and_yang(beta):
+    """Ising PEPS (D = d = 2) through the Z2 form: ln kappa, <ss>, m."""
+    A = inputs.ising_peps(beta)
+    bnd = inputs.ising_up_boundary(beta) if beta > 0.44 else None
+    run = ctmrg.Run(16, "z2", A=A, boundary=bnd)
+    run.run(400, tol=1e-13)
+    assert abs(run.log_kappa() - onsager_log_z(beta)) < 1e-9
+    zz = np.kron(np.diag([1.0, -1.0]), np.diag([1.0, -1.0]))
+    assert abs(np.trace(run.rho2("h") @ zz) - ising_nn_corr(beta)) < 1e-8
+    assert abs(np.trace(run.rho2("v") @ zz) - ising_nn_corr(beta)) < 1e-8
+    r1 = run.rho1()
+    assert abs((r1[0, 0] - r1[1, 1]) - yang_m(beta)) < 1e-6
+    # this PEPS populates only the even sector of the environment
+    assert all(rec["kept"][1] == 0 for rec in run.records)
+
+
+@pytest.mark.parametrize("form", ["dense", "z2"])
+def test_product_state(form):
+    """A = v x e0 x e0 x e0 x e0: rank-1 environment, rho1 = v v^T / |v|^2."""
+    v = np.array([0.6, -0.8])
+    A = inputs.product_state(v, 3)
+    run = ctmrg.Run(8, form, A=A)
+    run.step(3)
+    assert all(rec["kept"] == (1, 0) for rec in run.records)
+    r1 = run.rho1()
+    assert np.allclose(r1, np.outer(v, v) / (v @ v), atol=1e-14)
+    assert np.allclose(run.rho2("h"), np.kron(r1, r1), atol=1e-14)
+    assert np.allclose(run.rho2("v"), np.kron(r1, r1), atol=1e-14)
+    # E per site = 2 bonds x <S.S> of the product of two identical spins
+    sz = 0.5 * (v[0] ** 2 - v[1] ** 2)
+    sx = v[0] * v[1]
+    assert abs(run.energy() - 2 * (sx * sx + sz * sz)) < 1e-14
+
+
+# ---------------------------------------------------- basis covariance ----
+@pytest.mark.parametrize("D,chi", [(2, 16), (3, 20)])
+def test_rotation_commutes_with_the_recursion(D, chi):
+    """Running the plain form on (U a, U b) and rotating back = running it on (a, b).
+
+    The two runs differ only in rounding; the projectors divide by singular
+    values down to 1e-12 of the largest, so rounding is amplified to ~1e-10.
+    A structural mistake shows up at O(1).
+    """
+    A = inputs.iid_tensor(2, D, 5)
+    a = basis.double_layer(A)
+    U = basis.hermitian_basis(D)
+    ref = ctmrg.Run(chi, "dense", A=A).step(3)
+    at = basis.rotate(a, U)
+    rot = ctmrg.Run(chi, "dense", A=A, a=at, boundary=U @ np.eye(D).reshape(-1)).step(3)
+    eps_rot = ctmrg.epsilon_of(rot.env)
+    eps_rot = basis.unrotate(eps_rot, U)
+    eps_rot = eps_rot / np.sum(eps_rot * a)
+    assert np.abs(eps_rot - ref.epsilon()).max() <= 1e-8 * np.abs(ref.epsilon()).max()
+    for r1, r2 in zip(ref.records, rot.records):
+        k = min(len(r1["spectrum"]), len(r2["spectrum"]), chi)
+        assert np.allclose(r1["spectrum"][:k], r2["spectrum"][:k], rtol=1e-7, atol=1e-13)
+
+
+# ------------------------------------------------------ dense vs Z2 ----
+@pytest.mark.parametrize("D,chi,iters", [(2, 16, 50), (3, 24, 6), (4, 32, 3)])
+def test_dense_and_z2_forms_agree(D, chi, iters):
+    """The Z2 form reaches the plain form's result; its RDMs are exactly symmetric."""
+    A = inputs.iid_tensor(2, D, 0)
+    dense = ctmrg.Run(chi, "dense", A=A).step(iters)
+    z2 = ctmrg.Run(chi, "z2", A=A).step(iters)
+    for rd, rz in zip(dense.records, z2.records):
+        k = sum(rz["kept"])
+        assert rd["kept"][0] == k
+        # small values carry the absolute error eps * s_max of any SVD
+        assert np.allclose(rd["spectrum"][:k], rz["spectrum"][:k], rtol=1e-6, atol=1e-13)
+    assert np.abs(dense.rho1() - z2.rho1()).max() < 1e-11
+    assert np.abs(dense.rho2("h") - z2.rho2("h")).max() < 1e-11
+    assert abs(dense.energy() - z2.energy()) < 1e-11 * max(1.0, abs(dense.energy()))
+    assert abs(dense.log_kappa() - z2.log_kappa()) < 1e-11
+    assert np.array_equal(z2.rho1(), z2.rho1().T)
+    assert np.array_equal(z2.rho2("h"), z2.rho2("h").T)
+    assert z2.s_err() <= 1e-15
