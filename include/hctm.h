@@ -1,0 +1,159 @@
+/*
+ * hctm.h -- C ABI of the Hermitian-symmetric CTMRG library (libhctm.so).
+ *
+ * Method: arXiv:2410.11596, "Exploiting the Hermitian symmetry in tensor
+ * network algorithms".  A real iPEPS tensor A (Sec. II A) defines the double
+ * layer a = sum_s A (x) A (Fig. 1b).  Joining each ket leg with its bra leg
+ * gives a leg of dimension D^2 on which the bra-ket swap S acts; for real A
+ * the double layer is invariant under S on all four legs (Fig. 1e-f), so in
+ * the eigenbasis of S (Sec. II B) the double layer, the corners C and the
+ * edges T of the CTMRG environment (Fig. 1d) are Z2 block sparse.  The
+ * library runs directional CTMRG in that basis, block by block, on one
+ * AMD Instinct MI355X (gfx950), in FP64.  CTM_FORM_DENSE runs the same code
+ * on the unrotated, one-sector network (the non-symmetric reference form).
+ *
+ * Conventions shared by all calls
+ *  - Every call returns CTM_OK (0) or an error code; no exception crosses the
+ *    ABI.  ctm_last_error() gives a message for the last failing call.
+ *  - After an error raised while work was running on the GPU, the context is
+ *    poisoned: every call except ctm_free/ctm_last_error returns CTM_E_STATE.
+ *  - Host arrays are plain row-major FP64 buffers owned by the caller; the
+ *    library copies inputs at the call and writes outputs before returning.
+ *  - Device memory: the context owns all device memory it allocates.  If
+ *    ctm_opts.workspace is set, the library carves its buffers out of that
+ *    caller-owned device allocation (at least ctm_workspace_size bytes) and
+ *    allocates nothing else of that size; the caller keeps it alive until
+ *    ctm_free.
+ *  - Streams: work is issued on ctm_opts.stream (a hipStream_t) or on a
+ *    stream owned by the context.  Calls that return host data synchronise
+ *    that stream.
+ *  - One context may be used by one host thread at a time.
+ *
+ * Tensor layout: A is d x D x D x D x D, legs [s, u, l, d, r] (physical,
+ * up, left, down, right).  A joined bra-ket leg index is K = k*D + kbar
+ * (ket index k, bra index kbar).
+ */
+#ifndef HCTM_H
+#define HCTM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ctm_ctx ctm_ctx;
+
+enum {
+  CTM_OK = 0,
+  CTM_E_ARG = 1,     /* invalid argument (sizes, pointers, options) */
+  CTM_E_NOMEM = 2,   /* device allocation failed or workspace too small */
+  CTM_E_HIP = 3,     /* HIP runtime error */
+  CTM_E_NUMERIC = 4, /* non-finite input, or a factorisation that broke down */
+  CTM_E_STATE = 5    /* context poisoned by an earlier error */
+};
+
+enum { CTM_FORM_Z2 = 0, CTM_FORM_DENSE = 1 };
+
+typedef struct {
+  int form;                    /* CTM_FORM_Z2 (default) or CTM_FORM_DENSE */
+  const double* boundary;      /* host, D*D vector b[K] tracing the open boundary
+                                  legs of the initial 3x3 patch; NULL selects
+                                  b = sum_k |k k> (the open boundary).  In the Z2
+                                  form b must be swap symmetric, b[k*D+l] = b[l*D+k]. */
+  double svd_rel_cutoff;       /* keep singular values > cutoff * largest (default 1e-12) */
+  int svd_iters;               /* subspace iterations per truncated SVD (default 16) */
+  unsigned long long seed;     /* seed of the subspace-iteration start blocks */
+  void* stream;                /* hipStream_t or NULL */
+  void* workspace;             /* caller-owned device memory or NULL */
+  size_t workspace_bytes;
+} ctm_opts;
+
+/* Fill *o with the defaults above. */
+int ctm_opts_default(ctm_opts* o);
+
+/* Device bytes a context with these sizes needs (for ctm_opts.workspace). */
+int ctm_workspace_size(int d, int D, int chi, const ctm_opts* o, size_t* bytes);
+
+/*
+ * Create a context: copies A (host, d*D^4 doubles, legs [s,u,l,d,r]), forms
+ * the double layer in the eigenbasis of the swap (Sec. II B) and the initial
+ * environment of boundary dimension D^2 (the 3x3 patch traced with the
+ * boundary vector).  chi >= 1 is the boundary dimension kept after each
+ * truncation (Sec. II A).  Requires d >= 1, 1 <= D <= 8, finite A.
+ */
+int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, const ctm_opts* o);
+
+/*
+ * Run n_iter CTMRG iterations; one iteration is a left, right, top and
+ * bottom move, each absorbing a column or row of double-layer tensors and
+ * truncating the grown bond back to chi with per-sector SVD projectors.
+ * After every iteration the corner spectra are compared with the previous
+ * ones (see ctm_converged).
+ */
+int ctm_step(ctm_ctx* c, int n_iter);
+
+/*
+ * delta = max over the four corners of || s_new - s_old ||_2, s the singular
+ * values of a corner divided by their sum and padded with zeros to chi,
+ * between the last two iterations (+inf before the second).  converged =
+ * (delta < tol).  Synchronises.
+ */
+int ctm_converged(ctm_ctx* c, double tol, int* converged, double* delta);
+
+/* One-site reduced density matrix rho[s][s'] (host, d*d), trace one. */
+int ctm_rdm_1site(ctm_ctx* c, double* rho);
+
+/*
+ * Two-site RDM of a nearest-neighbour pair, rho[(s1 s2)][(s1' s2')] (host,
+ * d^4), trace one.  dir 0: horizontal pair (left site first), 1: vertical
+ * pair (upper site first).  In the Z2 form both RDMs are symmetric by
+ * construction: only the even (symmetric) part of an impurity couples to the
+ * even environment, and pairs of odd (antisymmetric) parts are combined so
+ * that the result is invariant under the joint ket-bra swap.
+ */
+int ctm_rdm_2site(ctm_ctx* c, int dir, double* rho);
+
+/* E = Tr(rho_h h) + Tr(rho_v h) for a bond operator h (host, d^2 x d^2). */
+int ctm_energy(ctm_ctx* c, const double* h, double* e);
+
+/* Release everything; NULL is accepted. */
+void ctm_free(ctm_ctx* c);
+
+/* Message of the last error on this context (never NULL). */
+const char* ctm_last_error(const ctm_ctx* c);
+
+/* ---- diagnostics used by the tests ------------------------------------ */
+
+/* One-site environment with the centre removed (Sec. III A), back in the
+ * plain basis, normalised so that <eps, a> = 1; host, D^8 doubles ordered
+ * [U, L, Dn, R] with joined indices K = k*D + kbar. */
+int ctm_env_epsilon(ctm_ctx* c, double* eps);
+
+/* Hermitian symmetry error S_err = ||e - e^dag|| / ||e + e^dag|| (Sec. III A). */
+int ctm_s_err(ctm_ctx* c, double* s_err);
+
+/* ln of the partition function per site, kappa = Z11 Z00 / (Z10 Z01). */
+int ctm_log_kappa(ctm_ctx* c, double* ln_kappa);
+
+/* Number of moves run so far. */
+int ctm_num_moves(ctm_ctx* c, int* n);
+
+/*
+ * Record of move m (0-based): the kept singular values of the decomposed
+ * matrix, merged over both sectors in descending order and divided by the
+ * largest, and the kept sector sizes.  s: host array of at least cap doubles.
+ */
+int ctm_move_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, int* k_odd);
+
+/* Current boundary bond of side 0..3 (top, right, bottom, left): its sizes. */
+int ctm_sector_dims(ctm_ctx* c, int side, int* chi_even, int* chi_odd);
+
+/* Seconds of GPU time of the last ctm_step call, per phase (see hctm.cpp). */
+int ctm_timing(ctm_ctx* c, double* t, int cap, int* n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HCTM_H */

@@ -1,0 +1,295 @@
+"""ctypes binding of libhctm.so (argument marshalling only).
+
+Every step of the computation runs in the library's HIP kernels; this module
+only converts arguments, takes device memory and the stream from PyTorch, and
+raises on error codes.  If the library is missing the import of `lib()` fails
+loudly; there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhctm.so")
+
+CTM_OK, CTM_E_ARG, CTM_E_NOMEM, CTM_E_HIP, CTM_E_NUMERIC, CTM_E_STATE = range(6)
+CTM_FORM_Z2, CTM_FORM_DENSE = 0, 1
+ERROR_NAMES = {1: "CTM_E_ARG", 2: "CTM_E_NOMEM", 3: "CTM_E_HIP", 4: "CTM_E_NUMERIC", 5: "CTM_E_STATE"}
+
+# every C symbol that include/hctm.h and include/hctm_testing.h declare
+EXPORTS = [
+    "ctm_opts_default", "ctm_workspace_size", "ctm_init", "ctm_step", "ctm_converged",
+    "ctm_rdm_1site", "ctm_rdm_2site", "ctm_energy", "ctm_free", "ctm_last_error",
+    "ctm_env_epsilon", "ctm_s_err", "ctm_log_kappa", "ctm_num_moves", "ctm_move_record",
+    "ctm_sector_dims", "ctm_timing",
+    "hctm_dev_gemm", "hctm_dev_copy", "hctm_dev_chol_inv", "hctm_dev_jacobi",
+]
+
+
+class CtmOpts(ctypes.Structure):
+    _fields_ = [
+        ("form", ctypes.c_int),
+        ("boundary", ctypes.POINTER(ctypes.c_double)),
+        ("svd_rel_cutoff", ctypes.c_double),
+        ("svd_iters", ctypes.c_int),
+        ("seed", ctypes.c_ulonglong),
+        ("stream", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class HctmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_LIB = None
+
+
+def lib():
+    """Load libhctm.so (built in place by __graft_entry__.build())."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2410_11596_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    dp, ip, vp = P(ctypes.c_double), P(ctypes.c_int), ctypes.c_void_p
+    ctx = vp
+    sig = {
+        "ctm_opts_default": ([P(CtmOpts)], ctypes.c_int),
+        "ctm_workspace_size": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, P(CtmOpts), P(ctypes.c_size_t)], ctypes.c_int),
+        "ctm_init": ([P(vp), dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(CtmOpts)], ctypes.c_int),
+        "ctm_step": ([ctx, ctypes.c_int], ctypes.c_int),
+        "ctm_converged": ([ctx, ctypes.c_double, ip, dp], ctypes.c_int),
+        "ctm_rdm_1site": ([ctx, dp], ctypes.c_int),
+        "ctm_rdm_2site": ([ctx, ctypes.c_int, dp], ctypes.c_int),
+        "ctm_energy": ([ctx, dp, dp], ctypes.c_int),
+        "ctm_free": ([ctx], None),
+        "ctm_last_error": ([ctx], ctypes.c_char_p),
+        "ctm_env_epsilon": ([ctx, dp], ctypes.c_int),
+        "ctm_s_err": ([ctx, dp], ctypes.c_int),
+        "ctm_log_kappa": ([ctx, dp], ctypes.c_int),
+        "ctm_num_moves": ([ctx, ip], ctypes.c_int),
+        "ctm_move_record": ([ctx, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip], ctypes.c_int),
+        "ctm_sector_dims": ([ctx, ctypes.c_int, ip, ip], ctypes.c_int),
+        "ctm_timing": ([ctx, dp, ctypes.c_int, ip], ctypes.c_int),
+        "hctm_dev_gemm": ([vp, vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.c_double, vp, vp], ctypes.c_int),
+        "hctm_dev_copy": ([vp, vp, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_longlong), P(ctypes.c_longlong), vp],
+                          ctypes.c_int),
+        "hctm_dev_chol_inv": ([vp, vp, ctypes.c_int, ctypes.c_double, vp, vp], ctypes.c_int),
+        "hctm_dev_jacobi": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp],
+                            ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _LIB = L
+    return L
+
+
+def _check(code, ctx=None):
+    if code != CTM_OK:
+        msg = lib().ctm_last_error(ctx).decode(errors="replace")
+        raise HctmError(code, msg)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _torch():
+    import torch  # noqa: PLC0415 (device memory and streams only)
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("libhctm needs a HIP GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def workspace_size(d, D, chi, form="z2"):
+    o = CtmOpts()
+    _check(lib().ctm_opts_default(ctypes.byref(o)))
+    o.form = CTM_FORM_Z2 if form == "z2" else CTM_FORM_DENSE
+    n = ctypes.c_size_t()
+    _check(lib().ctm_workspace_size(d, D, chi, ctypes.byref(o), ctypes.byref(n)))
+    return n.value
+
+
+class CTMRG:
+    """One CTMRG solve on the GPU (Z2 or plain form), 1x1 unit cell.
+
+    A: real array (d, D, D, D, D), legs [s, u, l, d, r].  Device memory is a
+    torch uint8 tensor handed to the library as its workspace; work runs on
+    torch's current HIP stream.
+    """
+
+    def __init__(self, A, chi, form="z2", boundary=None, svd_rel_cutoff=1e-12, svd_iters=16, seed=0x5EED,
+                 stream=None, torch_workspace=True):
+        torch = _torch()
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        if A.ndim != 5 or len(set(A.shape[1:])) != 1:
+            raise ValueError("A must have shape (d, D, D, D, D)")
+        self.d, self.D, self.chi = A.shape[0], A.shape[1], int(chi)
+        self.form = form
+        o = CtmOpts()
+        _check(lib().ctm_opts_default(ctypes.byref(o)))
+        o.form = CTM_FORM_Z2 if form == "z2" else CTM_FORM_DENSE
+        o.svd_rel_cutoff = svd_rel_cutoff
+        o.svd_iters = svd_iters
+        o.seed = seed
+        self._b = None
+        if boundary is not None:
+            self._b = np.ascontiguousarray(boundary, dtype=np.float64).reshape(-1)
+            o.boundary = _dptr(self._b)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        o.stream = ctypes.c_void_p(stream.cuda_stream)
+        self._ws = None
+        if torch_workspace:
+            nbytes = ctypes.c_size_t()
+            _check(lib().ctm_workspace_size(self.d, self.D, self.chi, ctypes.byref(o), ctypes.byref(nbytes)))
+            self._ws = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+            o.workspace = ctypes.c_void_p(self._ws.data_ptr())
+            o.workspace_bytes = nbytes.value
+        ctx = ctypes.c_void_p()
+        _check(lib().ctm_init(ctypes.byref(ctx), _dptr(A), self.d, self.D, self.chi, ctypes.byref(o)))
+        self._ctx = ctx
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().ctm_free(self._ctx)
+            self._ctx = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def step(self, n=1):
+        _check(lib().ctm_step(self._ctx, int(n)), self._ctx)
+        return self
+
+    def converged(self, tol):
+        c = ctypes.c_int()
+        dl = ctypes.c_double()
+        _check(lib().ctm_converged(self._ctx, tol, ctypes.byref(c), ctypes.byref(dl)), self._ctx)
+        return bool(c.value), dl.value
+
+    def run(self, max_iter, tol=None):
+        for _ in range(max_iter):
+            self.step(1)
+            if tol is not None and self.converged(tol)[0]:
+                break
+        return self
+
+    def rdm1(self):
+        rho = np.zeros((self.d, self.d))
+        _check(lib().ctm_rdm_1site(self._ctx, _dptr(rho)), self._ctx)
+        return rho
+
+    def rdm2(self, direction="h"):
+        n = self.d * self.d
+        rho = np.zeros((n, n))
+        _check(lib().ctm_rdm_2site(self._ctx, 0 if direction == "h" else 1, _dptr(rho)), self._ctx)
+        return rho
+
+    def energy(self, h):
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        e = ctypes.c_double()
+        _check(lib().ctm_energy(self._ctx, _dptr(h), ctypes.byref(e)), self._ctx)
+        return e.value
+
+    def epsilon(self):
+        q = self.D * self.D
+        eps = np.zeros((q, q, q, q))
+        _check(lib().ctm_env_epsilon(self._ctx, _dptr(eps)), self._ctx)
+        return eps
+
+    def s_err(self):
+        s = ctypes.c_double()
+        _check(lib().ctm_s_err(self._ctx, ctypes.byref(s)), self._ctx)
+        return s.value
+
+    def log_kappa(self):
+        s = ctypes.c_double()
+        _check(lib().ctm_log_kappa(self._ctx, ctypes.byref(s)), self._ctx)
+        return s.value
+
+    def num_moves(self):
+        n = ctypes.c_int()
+        _check(lib().ctm_num_moves(self._ctx, ctypes.byref(n)), self._ctx)
+        return n.value
+
+    def move_record(self, m):
+        cap = 8192
+        s = np.zeros(cap)
+        n, ke, ko = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().ctm_move_record(self._ctx, m, _dptr(s), cap, ctypes.byref(n), ctypes.byref(ke),
+                                     ctypes.byref(ko)), self._ctx)
+        return {"spectrum": s[: n.value].copy(), "kept": (ke.value, ko.value)}
+
+    def records(self):
+        return [self.move_record(m) for m in range(self.num_moves())]
+
+    def sector_dims(self, side):
+        e, o = ctypes.c_int(), ctypes.c_int()
+        _check(lib().ctm_sector_dims(self._ctx, side, ctypes.byref(e), ctypes.byref(o)), self._ctx)
+        return e.value, o.value
+
+    def timing(self):
+        t = np.zeros(16)
+        n = ctypes.c_int()
+        _check(lib().ctm_timing(self._ctx, _dptr(t), 16, ctypes.byref(n)), self._ctx)
+        return t[: n.value].copy()
+
+
+# ------------------------------------------------------------ test hooks ----
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def dev_gemm(A, B, C, M, N, K, lda, ldb, ldc, ta=0, tb=0, alpha=1.0, beta=0.0, cscale=None):
+    torch = _torch()
+    cs = _ptr(cscale) if cscale is not None else None
+    _check(lib().hctm_dev_gemm(_ptr(A), _ptr(B), _ptr(C), M, N, K, lda, ldb, ldc, ta, tb, alpha, beta, cs,
+                               _stream_ptr(torch)))
+
+
+def dev_copy(src, dst, dims, istr, ostr, in_offset=0, out_offset=0):
+    torch = _torch()
+    r = len(dims)
+    d = (ctypes.c_int * r)(*dims)
+    i = (ctypes.c_longlong * r)(*istr)
+    o = (ctypes.c_longlong * r)(*ostr)
+    ip = ctypes.c_void_p(src.data_ptr() + 8 * in_offset)
+    op = ctypes.c_void_p(dst.data_ptr() + 8 * out_offset)
+    _check(lib().hctm_dev_copy(ip, op, r, d, i, o, _stream_ptr(torch)))
+
+
+def dev_chol_inv(G, Rinv, n, rel, info):
+    torch = _torch()
+    _check(lib().hctm_dev_chol_inv(_ptr(G), _ptr(Rinv), n, rel, _ptr(info), _stream_ptr(torch)))
+
+
+def dev_jacobi(X, m, n, tol, max_sweeps, sv, perm, sweeps):
+    torch = _torch()
+    _check(lib().hctm_dev_jacobi(_ptr(X), m, n, tol, max_sweeps, _ptr(sv), _ptr(perm), _ptr(sweeps),
+                                 _stream_ptr(torch)))

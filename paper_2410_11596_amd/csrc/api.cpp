@@ -1,0 +1,317 @@
+// C ABI of libhctm.so (declared in include/hctm.h and include/hctm_testing.h).
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "ctm.hpp"
+#include "hctm.h"
+#include "hctm_testing.h"
+#include "linalg.hpp"
+
+struct ctm_ctx {
+  std::unique_ptr<hctm::Ctm> ctm;
+  std::string err;
+  bool poisoned = false;
+  int d = 0, D = 0, chi = 0, form = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+template <class F>
+int guarded(ctm_ctx* c, F f) {
+  if (c && c->poisoned) {
+    c->err = "context poisoned by an earlier error: " + c->err;
+    return CTM_E_STATE;
+  }
+  try {
+    f();
+    return CTM_OK;
+  } catch (const hctm::Error& e) {
+    (c ? c->err : g_err) = e.what();
+    if (c && (e.code == CTM_E_HIP || e.code == CTM_E_NUMERIC)) c->poisoned = true;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    (c ? c->err : g_err) = "host allocation failed";
+    return CTM_E_NOMEM;
+  } catch (const std::exception& e) {
+    (c ? c->err : g_err) = e.what();
+    if (c) c->poisoned = true;
+    return CTM_E_HIP;
+  }
+}
+
+hctm::Options to_options(const ctm_opts* o, int D) {
+  hctm::Options opt;
+  ctm_opts def;
+  ctm_opts_default(&def);
+  if (!o) o = &def;
+  if (o->form != CTM_FORM_Z2 && o->form != CTM_FORM_DENSE) throw hctm::Error(CTM_E_ARG, "unknown form");
+  opt.form = o->form == CTM_FORM_Z2 ? 0 : 1;
+  if (!(o->svd_rel_cutoff >= 0.0) || o->svd_rel_cutoff >= 1.0) throw hctm::Error(CTM_E_ARG, "svd_rel_cutoff out of range");
+  opt.tau = o->svd_rel_cutoff;
+  if (o->svd_iters < 1 || o->svd_iters > 1000) throw hctm::Error(CTM_E_ARG, "svd_iters out of range");
+  opt.svd_iters = o->svd_iters;
+  opt.seed = o->seed;
+  if (o->boundary) {
+    const int q = D * D;
+    opt.boundary.assign(o->boundary, o->boundary + q);
+    double mx = 0.0;
+    for (double v : opt.boundary) {
+      if (!std::isfinite(v)) throw hctm::Error(CTM_E_NUMERIC, "boundary vector is not finite");
+      mx = std::max(mx, std::fabs(v));
+    }
+    if (mx == 0.0) throw hctm::Error(CTM_E_ARG, "boundary vector is zero");
+    if (opt.form == 0) {
+      for (int k = 0; k < D; ++k)
+        for (int l = 0; l < D; ++l)
+          if (std::fabs(opt.boundary[k * D + l] - opt.boundary[l * D + k]) > 1e-14 * mx)
+            throw hctm::Error(CTM_E_ARG, "boundary vector is not swap symmetric (required in the Z2 form)");
+    }
+  }
+  return opt;
+}
+
+void check_sizes(int d, int D, int chi) {
+  if (d < 1 || d > 16) throw hctm::Error(CTM_E_ARG, "d must be in [1, 16]");
+  if (D < 1 || D > 8) throw hctm::Error(CTM_E_ARG, "D must be in [1, 8]");
+  if (chi < 1 || chi > 4096) throw hctm::Error(CTM_E_ARG, "chi must be in [1, 4096]");
+}
+
+}  // namespace
+
+extern "C" {
+
+int ctm_opts_default(ctm_opts* o) {
+  if (!o) return CTM_E_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->form = CTM_FORM_Z2;
+  o->boundary = nullptr;
+  o->svd_rel_cutoff = 1e-12;
+  o->svd_iters = 16;
+  o->seed = 0x5eedull;
+  return CTM_OK;
+}
+
+int ctm_workspace_size(int d, int D, int chi, const ctm_opts* o, size_t* bytes) {
+  return guarded(nullptr, [&] {
+    if (!bytes) throw hctm::Error(CTM_E_ARG, "bytes is NULL");
+    check_sizes(d, D, chi);
+    hctm::Options opt = to_options(o, D);
+    *bytes = hctm::Ctm::workspace_bytes(d, D, chi, opt);
+  });
+}
+
+int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, const ctm_opts* o) {
+  if (out) *out = nullptr;
+  return guarded(nullptr, [&] {
+    if (!out || !A) throw hctm::Error(CTM_E_ARG, "NULL argument");
+    check_sizes(d, D, chi);
+    const long long n = (long long)d * D * D * D * D;
+    for (long long i = 0; i < n; ++i)
+      if (!std::isfinite(A[i])) throw hctm::Error(CTM_E_NUMERIC, "A has a non-finite entry");
+    hctm::Options opt = to_options(o, D);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) throw hctm::Error(CTM_E_HIP, "no HIP device");
+    std::unique_ptr<ctm_ctx> c(new ctm_ctx);
+    c->d = d;
+    c->D = D;
+    c->chi = chi;
+    c->form = opt.form;
+    void* stream = o ? o->stream : nullptr;
+    void* ws = o ? o->workspace : nullptr;
+    const size_t wsb = o ? o->workspace_bytes : 0;
+    c->ctm.reset(new hctm::Ctm(A, d, D, chi, opt, reinterpret_cast<hipStream_t>(stream), ws, wsb));
+    *out = c.release();
+  });
+}
+
+int ctm_step(ctm_ctx* c, int n_iter) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    if (n_iter < 0) throw hctm::Error(CTM_E_ARG, "n_iter < 0");
+    c->ctm->step(n_iter);
+  });
+}
+
+int ctm_converged(ctm_ctx* c, double tol, int* converged, double* delta) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    const double dl = c->ctm->delta();
+    if (delta) *delta = dl >= 1e299 ? INFINITY : dl;
+    if (converged) *converged = dl < tol ? 1 : 0;
+  });
+}
+
+int ctm_rdm_1site(ctm_ctx* c, double* rho) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    if (!rho) throw hctm::Error(CTM_E_ARG, "rho is NULL");
+    c->ctm->rdm1(rho);
+  });
+}
+
+int ctm_rdm_2site(ctm_ctx* c, int dir, double* rho) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    if (!rho) throw hctm::Error(CTM_E_ARG, "rho is NULL");
+    if (dir != 0 && dir != 1) throw hctm::Error(CTM_E_ARG, "dir must be 0 or 1");
+    c->ctm->rdm2(dir, rho);
+  });
+}
+
+int ctm_energy(ctm_ctx* c, const double* h, double* e) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    if (!h || !e) throw hctm::Error(CTM_E_ARG, "NULL argument");
+    *e = c->ctm->energy(h);
+  });
+}
+
+void ctm_free(ctm_ctx* c) { delete c; }
+
+const char* ctm_last_error(const ctm_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+int ctm_env_epsilon(ctm_ctx* c, double* eps) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    if (!eps) throw hctm::Error(CTM_E_ARG, "eps is NULL");
+    c->ctm->epsilon_plain(eps);
+  });
+}
+
+int ctm_s_err(ctm_ctx* c, double* s) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    if (!s) throw hctm::Error(CTM_E_ARG, "NULL argument");
+    *s = c->ctm->s_err();
+  });
+}
+
+int ctm_log_kappa(ctm_ctx* c, double* lk) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    if (!lk) throw hctm::Error(CTM_E_ARG, "NULL argument");
+    *lk = c->ctm->log_kappa();
+  });
+}
+
+int ctm_num_moves(ctm_ctx* c, int* n) {
+  if (!c || !n) return CTM_E_ARG;
+  *n = (int)c->ctm->records().size();
+  return CTM_OK;
+}
+
+int ctm_move_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, int* k_odd) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    const auto& r = c->ctm->records();
+    if (m < 0 || m >= (int)r.size()) throw hctm::Error(CTM_E_ARG, "move index out of range");
+    const auto& rec = r[m];
+    const int ns = (int)rec.spectrum.size();
+    if (n) *n = ns;
+    if (k_even) *k_even = rec.k_even;
+    if (k_odd) *k_odd = rec.k_odd;
+    if (s)
+      for (int i = 0; i < ns && i < cap; ++i) s[i] = rec.spectrum[i];
+  });
+}
+
+int ctm_sector_dims(ctm_ctx* c, int side, int* chi_even, int* chi_odd) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    if (side < 0 || side > 3) throw hctm::Error(CTM_E_ARG, "side must be 0..3");
+    const hctm::Leg l = c->ctm->side(side);
+    if (chi_even) *chi_even = l.e;
+    if (chi_odd) *chi_odd = l.o;
+  });
+}
+
+int ctm_timing(ctm_ctx* c, double* t, int cap, int* n) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    const auto& tm = c->ctm->timing;
+    if (n) *n = (int)tm.size();
+    if (t)
+      for (int i = 0; i < (int)tm.size() && i < cap; ++i) t[i] = tm[i];
+  });
+}
+
+// ---------------------------------------------------------- test hooks ----
+int hctm_dev_gemm(const double* A, const double* B, double* C, int M, int N, int K, int lda, int ldb, int ldc, int ta,
+                  int tb, double alpha, double beta, const double* cscale, void* stream) {
+  return guarded(nullptr, [&] {
+    if (M < 0 || N < 0 || K < 0) throw hctm::Error(CTM_E_ARG, "negative size");
+    hctm::GemmDesc d{};
+    d.A = A;
+    d.B = B;
+    d.C = C;
+    d.M = M;
+    d.N = N;
+    d.K = K;
+    d.lda = lda;
+    d.ldb = ldb;
+    d.ldc = ldc;
+    d.ta = ta;
+    d.tb = tb;
+    d.alpha = alpha;
+    d.beta = beta;
+    d.cscale = cscale;
+    d.rscale = nullptr;
+    hctm::gemm({d}, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int hctm_dev_copy(const double* in, double* out, int r, const int* dims, const long long* istr, const long long* ostr,
+                  void* stream) {
+  return guarded(nullptr, [&] {
+    if (r < 1 || r > hctm::kMaxRank) throw hctm::Error(CTM_E_ARG, "rank out of range");
+    hctm::CopyJob j{};
+    j.in = in;
+    j.out = out;
+    j.r = r;
+    for (int i = 0; i < r; ++i) {
+      j.dims[i] = dims[i];
+      j.istr[i] = istr[i];
+      j.ostr[i] = ostr[i];
+    }
+    hctm::copy_jobs({j}, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int hctm_dev_chol_inv(double* G, double* Rinv, int n, double rel, int* info, void* stream) {
+  return guarded(nullptr, [&] {
+    if (n < 1) throw hctm::Error(CTM_E_ARG, "n < 1");
+    hctm::SmallProb p{};
+    p.a = G;
+    p.b = Rinv;
+    p.m = p.n = n;
+    p.lda = p.ldb = n;
+    p.rel = rel;
+    p.info = info;
+    hctm::chol_inv({p}, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int hctm_dev_jacobi(double* X, int m, int n, double tol, int max_sweeps, double* sv, int* perm, int* sweeps,
+                    void* stream) {
+  return guarded(nullptr, [&] {
+    if (m < 1 || n < 1 || n > 1024) throw hctm::Error(CTM_E_ARG, "size out of range");
+    hctm::SmallProb p{};
+    p.a = X;
+    p.m = m;
+    p.n = n;
+    p.lda = n;
+    p.rel = tol;
+    p.max_sweeps = max_sweeps;
+    p.info = sweeps;
+    p.sv = sv;
+    p.perm = perm;
+    hctm::jacobi({p}, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+}  // extern "C"

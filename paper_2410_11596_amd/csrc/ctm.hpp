@@ -1,0 +1,161 @@
+// Directional CTMRG engine in the Z2 (Hermitian) basis.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "blocks.hpp"
+#include "hctm_internal.hpp"
+#include "linalg.hpp"
+#include "tensor.hpp"
+
+namespace hctm {
+
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  bool counting = false;
+  double* take(size_t n) {
+    const size_t b = ((n * sizeof(double)) + 255) & ~size_t(255);
+    if (!counting && used + b > cap) throw Error(2, "workspace too small");
+    double* p = counting ? nullptr : reinterpret_cast<double*>(base + used);
+    used += b;
+    return p;
+  }
+};
+
+struct MoveRecord {
+  std::vector<double> spectrum;  // kept values, merged, descending, / largest
+  int k_even = 0, k_odd = 0;
+};
+
+struct Options {
+  int form = 0;  // 0 Z2, 1 dense
+  std::vector<double> boundary;
+  double tau = 1e-12;
+  int svd_iters = 16;
+  unsigned long long seed = 0x5eed;
+};
+
+// per-sector state of the truncated SVD
+struct SvdSector {
+  int n = 0, l = 0, kg = 0, trusted = 0, k = 0;
+  bool direct = false;
+  const double* Mp = nullptr;  // sector block of M (n x n, ld = n)
+  double *Qr = nullptr, *Ql = nullptr, *Y = nullptr, *Tm = nullptr;
+  double *G = nullptr, *Ri = nullptr, *B = nullptr, *Bj = nullptr;
+  double *Ub = nullptr, *Vb = nullptr, *Wbuf = nullptr, *Vbuf = nullptr;
+  const double *W = nullptr, *V = nullptr;  // kept vectors (n x k) of M_P
+  double *sv = nullptr, *isq = nullptr, *isv = nullptr;
+  int *perm = nullptr, *info = nullptr;
+};
+
+class Ctm {
+ public:
+  struct CountTag {};
+  Ctm(CountTag, int d, int D, int chi);
+  Ctm(const double* A_host, int d, int D, int chi, const Options& o, hipStream_t stream, void* workspace,
+      size_t ws_bytes);
+  ~Ctm();
+  static size_t workspace_bytes(int d, int D, int chi, const Options& o);
+
+  void step(int n_iter);
+  double delta() const { return delta_; }
+  void rdm1(double* rho);
+  void rdm2(int dir, double* rho);
+  void epsilon_plain(double* eps_host);
+  double s_err();
+  double log_kappa();
+  double energy(const double* h_host);
+  const std::vector<MoveRecord>& records() const { return records_; }
+  Leg side(int s) const { return side_[s]; }
+  hipStream_t stream() const { return st_; }
+  std::vector<double> timing;  // per-phase seconds of the last step() call
+
+ private:
+  void plan_memory(bool counting);
+  void setup(const double* A_host);
+  void launch_copies(std::vector<CopyJob>& jobs);
+  void launch_gemms(std::vector<GemmDesc>& g);
+  void permute(const BT& in, BT& out, std::initializer_list<int> perm, int nr_out);
+  void contract(const BT& A, const BT& B, BT& C);
+  void normalise(BT& t);
+  void quadrant(int j);
+  void move(int r);
+  void truncated_svd(BT& M, int chi);
+  void orth(std::vector<SvdSector*>& ss, bool ql, int passes);
+  void corner_spectra();
+  void compute_epsilon_rot();  // eps~ into eps_ (layout [U L | Dn R])
+  BT left_half(int frame, const BT& imp);
+  BT right_half(int frame, const BT& imp);
+  BT pack_impurity(int s, int sp, int kind, int frame);  // kind 0 plain, 1 sym, 2 anti
+  void sync();
+  void top_bottom(BT& top, BT& bot);  // TOP[a U | c], BOT[c' Dn | e] (frame 0)
+
+  int d_, D_, chi_, q_, cc_;
+  Leg lq_;
+  Options opt_;
+  hipStream_t st_ = nullptr;
+  bool own_stream_ = false;
+  void* mem_ = nullptr;
+  bool own_mem_ = false;
+  Arena ar_;
+
+  // device tables and inputs
+  int* tab_idx_ = nullptr;   // basis U: row -> up to two plain indices
+  double* tab_c_ = nullptr;
+  int* tabT_idx_ = nullptr;  // U^T
+  double* tabT_c_ = nullptr;
+  double* A_ = nullptr;
+  double* b_ = nullptr;
+  double* a_plain_ = nullptr;  // q^4, rotated basis, frame 0
+  double* plain_tmp_ = nullptr;  // q^4 scratch
+  double* plain_tmp2_ = nullptr;
+  BT a_rot_[4];
+
+  BT env_[8];
+  Leg side_[4];
+  BT quad_[4];
+  bool quad_ok_[4] = {false, false, false, false};
+
+  // scratch
+  double *big1_ = nullptr, *big2_ = nullptr;
+  long long big_cap_ = 0;
+  double *mid1_ = nullptr, *mid2_ = nullptr, *mid3_ = nullptr;
+  long long mid_cap_ = 0;
+  BT Hu_, Hd_, M_;
+  BT Pa_, Pb_;
+  long long proj_cap_ = 0;
+  SvdSector sec_[2];
+  int l_cap_ = 0;
+  double* misc_ = nullptr;  // small device scalars
+  int* kdev_ = nullptr;
+  int* host_k_ = nullptr;   // pinned
+  double* host_d_ = nullptr;
+  double* part_ = nullptr;
+  // corner spectra
+  double* cspec_ = nullptr;     // 4 corners x chi (current, normalised)
+  double* cspec_old_ = nullptr;
+  double* csv_ = nullptr;       // scratch singular values
+  int* cperm_ = nullptr;
+  double* cmat_ = nullptr;      // scratch copies of corner blocks
+  bool have_old_spec_ = false;
+  double delta_ = 1e300;
+  // observables
+  BT eps_;
+  bool eps_ok_ = false;
+  uint64_t move_count_ = 0;
+  std::vector<MoveRecord> records_;
+  std::vector<hipEvent_t> ev_;
+  int ev_index_ = 0;
+  double* halves_ = nullptr;
+  long long halves_cap_ = 0;
+  int halves_used_ = 0;
+  int halves_max_ = 0;
+  double* dots_ = nullptr;     // dot-product results
+  double* dpart_ = nullptr;    // dot-product partial sums (64 per job)
+  double* rho_ = nullptr;      // device RDM output (d^4)
+  double* hdev_ = nullptr;     // bond operator (d^4)
+  MoveRecord pending_;
+};
+
+}  // namespace hctm

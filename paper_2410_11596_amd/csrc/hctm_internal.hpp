@@ -1,0 +1,57 @@
+// Internal interfaces of the HIP implementation (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace hctm {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HCTM_HIP(x)                                                                     \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      throw ::hctm::Error(3, std::string(#x) + " failed: " + hipGetErrorString(e_));    \
+  } while (0)
+
+// ----------------------------------------------------------------- GEMM ----
+// C = alpha * op(A) op(B) * diag(cscale) + beta * C, all FP64, row-major
+// storage with leading dimensions.  ta = 0: A[m*lda + k]; ta = 1: A[k*lda + m].
+// tb = 0: B[k*ldb + n]; tb = 1: B[n*ldb + k].  cscale may be null.
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  int M, N, K;
+  int lda, ldb, ldc;
+  int ta, tb;
+  double alpha, beta;
+  const double* cscale;
+  const double* rscale;  // optional per-row scale of the product
+};
+void gemm(const std::vector<GemmDesc>& probs, hipStream_t s);
+
+// -------------------------------------------------------------- permute ----
+// Strided copy of one dense block: out[sum_j x_j ostr_j] = in[sum_j x_j istr_j]
+// for x in the box dims[0..r).  Used for every leg permutation of a
+// block-sparse tensor (one job per parity block).
+constexpr int kMaxRank = 6;
+struct CopyJob {
+  const double* in;
+  double* out;
+  int r;
+  int dims[kMaxRank];
+  long long istr[kMaxRank];
+  long long ostr[kMaxRank];
+};
+void copy_jobs(const std::vector<CopyJob>& jobs, hipStream_t s);
+
+}  // namespace hctm

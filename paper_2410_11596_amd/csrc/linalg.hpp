@@ -1,0 +1,64 @@
+// Small dense FP64 linear algebra used by the per-sector truncated SVD.
+#pragma once
+#include "hctm_internal.hpp"
+
+namespace hctm {
+
+struct SmallProb {
+  double* a;       // matrix operated on (row-major, leading dim lda)
+  double* b;       // Cholesky: R^-1 (ld ldb); Jacobi: accumulated right vectors (n x n) or null
+  int m, n, lda, ldb;
+  double rel;      // Cholesky: relative diagonal shift; Jacobi: orthogonality tolerance
+  int max_sweeps;  // Jacobi only
+  int* info;       // Cholesky: first failing pivot (1-based) or 0; Jacobi: sweeps (<0: no convergence)
+  double* sv;      // Jacobi: singular values, descending
+  int* perm;       // Jacobi: column of the j-th largest
+  int flags;       // Cholesky: 1 = factor the unit-diagonal Gram D^-1 G D^-1 (D = sqrt diag G);
+                   // Rinv is then D^-1 R^-1 (sv must point to n doubles of scratch)
+};
+
+constexpr int kMaxSmall = 16;
+struct SmallBatch {
+  SmallProb p[kMaxSmall];
+  int n;
+};
+
+struct SelectArgs {
+  const double* sv0;
+  const double* sv1;
+  int n0, n1;    // trusted values per sector
+  int chi;
+  double tau;
+  int* out_k;    // [k_even, k_odd]
+  double* out_s; // [s_max]
+  double* isq0;  // 1/sqrt(s) of the kept values, sector 0
+  double* isq1;
+  double* isv0;  // 1/s of the kept values
+  double* isv1;
+};
+
+// corner spectra: merge the two sector spectra of each corner, divide by the
+// sum, pad to len; delta = max_c || new_c - old_c ||_2 (if have_old)
+struct SpecArgs {
+  const double* sv[8];  // corner c sector P at sv[2c+P]
+  int nsv[8];
+  double* spec_new;     // 4 x len
+  const double* spec_old;
+  int len;
+  int have_old;
+  double* delta;
+};
+void corner_spectra_delta(const SpecArgs& a, hipStream_t s);
+
+void fill(double* p, double v, size_t n, hipStream_t s);
+void random_fill(double* p, size_t n, uint64_t seed, hipStream_t s);
+void norm2(const double* p, size_t n, double* out, double* part, hipStream_t s);
+void sumsq(const double* p, size_t n, double* out, double* part, hipStream_t s);
+void scale_inv(double* p, size_t n, const double* nrm, hipStream_t s);
+void chol_inv(const std::vector<SmallProb>& probs, hipStream_t s);
+void jacobi(const std::vector<SmallProb>& probs, hipStream_t s);
+void gather_cols(const double* X, int ldx, const int* perm, const double* sv, int m, int k, double* U, int ldu,
+                 hipStream_t s);
+void select_states(const SelectArgs& a, hipStream_t s);
+
+}  // namespace hctm

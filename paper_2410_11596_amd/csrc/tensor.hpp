@@ -1,0 +1,52 @@
+// Construction kernels (double layer, basis change, initial environment, dots).
+#pragma once
+#include "hctm_internal.hpp"
+
+namespace hctm {
+
+constexpr int kMaxPairs = 16;
+struct DLArgs {
+  const double* A;        // d x D^4 single-layer tensors, [s,u,l,d,r]
+  double* out;            // q^4 plain, rotated basis
+  const int* tab_idx;     // basis table: row a -> (K0, K1), -1 if absent
+  const double* tab_c;    // coefficients
+  int d, D;
+  int npairs;
+  int ket[kMaxPairs], bra[kMaxPairs];
+  double w[kMaxPairs];
+};
+void double_layer_basis(const DLArgs& g, hipStream_t s);
+void basis4(const double* in, double* out, int q, const int* tab_idx, const double* tab_c, hipStream_t s);
+void init_env(const double* a, int q, int rot, const double* b, const int* tab_idx, const double* tab_c, double* C,
+              double* T, hipStream_t s);
+
+struct DotJob {
+  const double* x;
+  const double* y;
+  long long n;
+  double* out;
+};
+constexpr int kMaxDots = 32;
+struct DotBatch {
+  DotJob j[kMaxDots];
+  int n;
+};
+// scratch: 64 doubles per job of a batch (64 * kMaxDots)
+void dots(const std::vector<DotJob>& jobs, double* scratch, hipStream_t s);
+
+// rho (n x n) from precomputed dot products, divided by its trace.
+// mode 0: rho1, dots[s*d + s'] (dense) ; mode 1: rho1 Z2, dots over s <= s'
+// mode 2: rho2 dense, dots[(s1 d + s1') d^2 + (s2 d + s2')]
+// mode 3: rho2 Z2, dots of sym-sym and anti-anti pairs (see tensor.hip)
+void assemble_rho(const double* dots, int d, int mode, double* rho, hipStream_t s);
+// e = sum_k Tr(rho_k h), k over nrho matrices of size n x n
+void trace_products(const double* rho, int nrho, const double* h, int n, double* e, hipStream_t s);
+// num = ||x - S x||^2, den = ||x + S x||^2 with S the bra-ket swap on every
+// leg of a plain q^4 tensor (q = D^2); out = sqrt(num / den)
+void swap_asym(const double* x, int D, double* part, double* out, hipStream_t s);
+// out = sum of the diagonals of a list of square blocks
+void trace_blocks(const double* const* p, const int* n, const int* ld, int nb, double* out, hipStream_t s);
+// out = ln|z[0]| + ln|z[1]| - ln|z[2]| - ln|z[3]|
+void log_ratio(const double* z, double* out, hipStream_t s);
+
+}  // namespace hctm

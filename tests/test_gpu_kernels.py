@@ -1,0 +1,116 @@
+"""GPU checks of the building blocks of the move, each against a plain numpy
+FP64 computation of the same operation (ragged sizes, every operand layout)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_11596_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 33, 5), (130, 129, 257), (256, 384, 128), (300, 7, 1000)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_matches_numpy(hc, M, N, K, ta, tb):
+    rng = np.random.default_rng(M * 1000 + N * 10 + K + 7 * ta + 3 * tb)
+    A = rng.standard_normal((K, M) if ta else (M, K))
+    B = rng.standard_normal((N, K) if tb else (K, N))
+    C0 = rng.standard_normal((M, N))
+    cs = rng.standard_normal(N)
+    ref = 1.5 * (A.T if ta else A) @ (B.T if tb else B) * cs[None, :] - 0.5 * C0
+    dA, dB, dC, dcs = _dev(A), _dev(B), _dev(C0), _dev(cs)
+    hc.dev_gemm(dA, dB, dC, M, N, K, A.shape[1], B.shape[1], N, ta, tb, 1.5, -0.5, dcs)
+    torch.cuda.synchronize()
+    out = dC.cpu().numpy()
+    scale = np.abs(A).max() * np.abs(B).max() * K * np.abs(cs).max() + np.abs(C0).max()
+    assert np.abs(out - ref).max() <= 1e-14 * scale
+
+
+def test_gemm_leading_dims_and_zero_k(hc):
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((70, 90))
+    B = rng.standard_normal((60, 80))
+    C = rng.standard_normal((70, 100))
+    dA, dB, dC = _dev(A), _dev(B), _dev(C)
+    # sub-block product with leading dimensions larger than the sizes
+    hc.dev_gemm(dA, dB, dC, 50, 40, 60, 90, 80, 100, 0, 0, 1.0, 0.0)
+    torch.cuda.synchronize()
+    ref = C.copy()
+    ref[:50, :40] = A[:50, :60] @ B[:60, :40]
+    assert np.abs(dC.cpu().numpy() - ref).max() < 1e-12
+    # K = 0: C = beta C
+    hc.dev_gemm(dA, dB, dC, 70, 100, 0, 90, 80, 100, 0, 0, 1.0, 0.5)
+    torch.cuda.synchronize()
+    assert np.array_equal(dC.cpu().numpy(), 0.5 * ref)
+
+
+@pytest.mark.parametrize("shape,perm", [((3, 40, 5, 33), (0, 3, 2, 1)), ((64, 64), (1, 0)), ((7, 1, 9, 2, 5), (4, 2, 0, 1, 3)),
+                                         ((50, 3, 70), (0, 1, 2))])
+def test_copy_is_exact_permutation(hc, shape, perm):
+    rng = np.random.default_rng(len(shape))
+    X = rng.standard_normal(shape)
+    Y = np.ascontiguousarray(X.transpose(perm))
+    dX = _dev(X)
+    dY = torch.zeros(Y.size, dtype=torch.float64, device="cuda")
+    istr = [X.strides[p] // 8 for p in perm]
+    ostr = [s // 8 for s in Y.strides]
+    hc.dev_copy(dX, dY, list(Y.shape), istr, ostr)
+    torch.cuda.synchronize()
+    assert np.array_equal(dY.cpu().numpy().reshape(Y.shape), Y)
+
+
+@pytest.mark.parametrize("n", [1, 12, 100, 142, 160])
+def test_cholesky_inverse(hc, n):
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((n + 30, n))
+    G = X.T @ X
+    dG, dR = _dev(G), torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    info = torch.zeros(4, dtype=torch.int32, device="cuda")
+    hc.dev_chol_inv(dG, dR, n, 0.0, info)
+    torch.cuda.synchronize()
+    Ri = dR.cpu().numpy()
+    assert int(info[0].item()) == 0
+    assert np.allclose(np.tril(Ri, -1), 0.0)
+    # Q = X R^-1 has orthonormal columns
+    Q = X @ Ri
+    assert np.abs(Q.T @ Q - np.eye(n)).max() < 1e-11 * np.linalg.cond(X) ** 2
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (8, 5), (40, 40), (120, 97), (150, 150), (201, 180)])
+def test_jacobi_svd(hc, m, n):
+    rng = np.random.default_rng(m + n)
+    # graded singular values, as in the CTMRG spectra
+    U, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    k = min(m, n)
+    s = np.logspace(0, -9, k)
+    X = (U[:, :k] * s) @ V[:, :k].T
+    dX = _dev(X)
+    sv = torch.zeros(n, dtype=torch.float64, device="cuda")
+    perm = torch.zeros(n, dtype=torch.int32, device="cuda")
+    sw = torch.zeros(4, dtype=torch.int32, device="cuda")
+    hc.dev_jacobi(dX, m, n, 1.1e-16 * m, 60, sv, perm, sw)
+    torch.cuda.synchronize()
+    assert int(sw[0].item()) >= 0
+    got = sv.cpu().numpy()
+    assert np.all(np.diff(got) <= 0)
+    assert np.abs(got[:k] - s).max() < 1e-13
+    assert np.abs(got[k:]).max(initial=0.0) < 1e-13
+    Y = dX.cpu().numpy()[:, perm.cpu().numpy()[:k]]
+    Un = Y / got[None, :k]
+    # left vectors of the well separated leading values are orthonormal
+    top = s > 1e-6
+    assert np.abs(Un[:, top].T @ Un[:, top] - np.eye(int(top.sum()))).max() < 1e-9
