@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""CTMRG iterations per second on one MI355X: Z2 (Hermitian) form vs plain form.
+
+Workload: directional CTMRG on a 1x1 unit cell, real iPEPS with d = 2, D = 6
+(joined bra-ket leg 36 = 21 even + 15 odd), chi = 144, FP64, i.i.d. N(0,1)
+tensor (seed 0, max-abs normalised).  One step = one CTMRG iteration = four
+directional moves.  Both forms start from the same traced-boundary
+environment; W untimed iterations bring every bond to chi, then K iterations
+are timed between two device synchronisations.
+
+Printed: one JSON line with the Z2 throughput as `value`, the plain-form
+throughput and their ratio, the live MFMA roofline of the FP64 GEMM kernel
+(algorithmic block-product flops over the summed HIP-event durations of its
+launches in the timed Z2 region) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CTMRG steps/s Z2 vs dense (FP64 vs mixed) at D=6 χ=144; p50/p99 solve latency"
+FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (datasheet)
+
+
+def time_form(A, chi, form, steps, warmup, profile):
+    import torch
+
+    from paper_2410_11596_amd import CTMRG
+
+    g = CTMRG(A, chi, form=form, profile=profile)
+    g.step(warmup)
+    torch.cuda.synchronize()
+    g.gemm_stats(reset=True)
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = g.gemm_stats()
+    phases = g.timing()
+    split = g.sector_dims(3)
+    g.close()
+    return (t1 - t0), stats, phases, split
+
+
+def cpu_baseline(D, chi, split, seed=0):
+    """The oracle's Z2 left move on a random saturated environment (timed once)."""
+    from oracle import basis, ctmrg
+
+    from paper_2410_11596_amd import inputs
+
+    A = inputs.iid_tensor(2, D, seed)
+    run = ctmrg.Run(chi, "z2", A=A)            # builds a~ and the masks
+    rng = np.random.default_rng(seed + 1)
+    pq = run.par_q
+    pb = np.array([0] * split[0] + [1] * split[1])
+    q = D * D
+    shapes_par = [
+        ((chi, chi), [pb, pb]), ((chi, q, chi), [pb, pq, pb]),
+    ] * 4
+    ts = []
+    for shape, pars in shapes_par:
+        x = rng.standard_normal(shape)
+        ts.append(np.where(basis.parity_mask(pars), x, 0.0))
+    env = ctmrg.Env(ts, [pb.copy() for _ in range(4)])
+    threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    ctmrg.left_move(env, run.a, chi, run.tau, pq)
+    t = time.perf_counter() - t0
+    return {
+        "value": 1.0 / (4.0 * t),
+        "unit": "CTMRG iterations/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"one left move of the oracle's Z2 form (numpy/OpenBLAS, FP64) on a random saturated "
+                  f"D={D}, chi={chi} environment split {split[0]}+{split[1]}, {t:.1f} s, scaled x4 to one iteration",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--dense-steps", type=int, default=3)
+    ap.add_argument("--D", type=int, default=6)
+    ap.add_argument("--chi", type=int, default=144)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
+              "DESIGN.md and is not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2410_11596_amd import inputs
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    A = inputs.iid_tensor(2, args.D, 0)
+    tz, stats, phases, split = time_form(A, args.chi, "z2", args.steps, args.warmup, profile=True)
+    z2_rate = args.steps / tz
+    out = {
+        "metric": METRIC,
+        "value": z2_rate,
+        "unit": "CTMRG iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * tz / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"Z2 directional CTMRG, 1x1 cell, real iPEPS d=2 D={args.D}, chi={args.chi}, "
+                        f"i.i.d. N(0,1) tensor seed 0, FP64",
+            "form": "z2",
+            "D": args.D,
+            "chi": args.chi,
+            "precision": "fp64",
+        },
+        "sector_split": list(split),
+        "phases_ms_per_step": {k: 1e3 * v / args.steps for k, v in
+                               zip(["corners", "halves", "svd", "renormalise"], phases.tolist())},
+    }
+    if stats["launches"] > 0 and stats["seconds"] > 0:
+        achieved = stats["flops"] / stats["seconds"] / 1e12
+        out["roofline"] = {
+            "bound": "mfma",
+            "kernel": "gemm_f64_kernel",
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": None,
+            "launches": stats["launches"],
+            "gemm_share_of_step": stats["seconds"] / tz,
+        }
+    if not args.no_dense:
+        td, dstats, dphases, _ = time_form(A, args.chi, "dense", args.dense_steps, args.warmup, profile=False)
+        dense_rate = args.dense_steps / td
+        out["dense_value"] = dense_rate
+        out["dense_ms_per_step"] = 1e3 * td / args.dense_steps
+        out["z2_over_dense"] = z2_rate / dense_rate
+        out["dense_phases_ms_per_step"] = {k: 1e3 * v / args.dense_steps for k, v in
+                                           zip(["corners", "halves", "svd", "renormalise"], dphases.tolist())}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.D, args.chi, (84, 60))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -62,8 +62,9 @@ typedef struct {
                                   b = sum_k |k k> (the open boundary).  In the Z2
                                   form b must be swap symmetric, b[k*D+l] = b[l*D+k]. */
   double svd_rel_cutoff;       /* keep singular values > cutoff * largest (default 1e-12) */
-  int svd_iters;               /* subspace iterations per truncated SVD (default 16) */
+  int svd_iters;               /* subspace iterations per truncated SVD (default 12) */
   unsigned long long seed;     /* seed of the subspace-iteration start blocks */
+  int profile;                 /* 1: time every GEMM launch with HIP events (ctm_gemm_stats) */
   void* stream;                /* hipStream_t or NULL */
   void* workspace;             /* caller-owned device memory or NULL */
   size_t workspace_bytes;
@@ -149,8 +150,16 @@ int ctm_move_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, 
 /* Current boundary bond of side 0..3 (top, right, bottom, left): its sizes. */
 int ctm_sector_dims(ctm_ctx* c, int side, int* chi_even, int* chi_odd);
 
-/* Seconds of GPU time of the last ctm_step call, per phase (see hctm.cpp). */
+/* GPU seconds of the last ctm_step call per phase of the moves:
+ * t[0] enlarged corners, t[1] half-system products and M, t[2] truncated SVD
+ * (subspace iteration, Jacobi, selection), t[3] projectors, renormalisation
+ * and normalisation.  *n = 4. */
 int ctm_timing(ctm_ctx* c, double* t, int cap, int* n);
+
+/* Profile mode only (ctm_opts.profile = 1): algorithmic FP64 GEMM flops
+ * (2*M*N*K per block product), summed GEMM launch durations in seconds and
+ * the number of launches since the last reset; reset != 0 clears them. */
+int ctm_gemm_stats(ctm_ctx* c, double* flops, double* seconds, long long* launches, int reset);
 
 #ifdef __cplusplus
 }

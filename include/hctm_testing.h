@@ -15,9 +15,11 @@ extern "C" {
 /* C = alpha * op(A) op(B) * diag(cscale) + beta * C, FP64 on the matrix
  * cores (the block products of Sec. II B).  Row-major storage: ta = 0 means
  * A[m*lda + k], ta = 1 means A[k*lda + m]; tb = 0 means B[k*ldb + n], tb = 1
- * means B[n*ldb + k].  cscale may be NULL. */
+ * means B[n*ldb + k].  cscale may be NULL.  scratch (may be NULL): device
+ * doubles the kernel may use to split a long K over several workgroups. */
 int hctm_dev_gemm(const double* A, const double* B, double* C, int M, int N, int K, int lda, int ldb, int ldc,
-                  int ta, int tb, double alpha, double beta, const double* cscale, void* stream);
+                  int ta, int tb, double alpha, double beta, const double* cscale, double* scratch,
+                  long long scratch_doubles, void* stream);
 
 /* Strided copy of a dense box of rank r <= 6: out[sum x_j ostr_j] =
  * in[sum x_j istr_j] (the permute-and-reshape step between block products). */
@@ -30,9 +32,15 @@ int hctm_dev_chol_inv(double* G, double* Rinv, int n, double rel, int* info, voi
 
 /* One-sided Jacobi SVD of X (m x n, row-major, overwritten by U*Sigma in
  * column order); sv = singular values descending, perm = their columns,
- * sweeps[0] = sweeps used (negative: no convergence within max_sweeps). */
+ * sweeps[0] = sweeps used (negative: no convergence within max_sweeps).
+ * If V is not NULL (X square), V (n x n, row-major) receives the product of
+ * the rotations, so that X_in V = X_out; vlog then needs
+ * hctm_dev_jacobi_log_doubles(n, max_sweeps) doubles of scratch. */
 int hctm_dev_jacobi(double* X, int m, int n, double tol, int max_sweeps, double* sv, int* perm, int* sweeps,
-                    void* stream);
+                    double* V, double* vlog, void* stream);
+
+/* Scratch doubles needed by hctm_dev_jacobi's rotation log. */
+long long hctm_dev_jacobi_log_doubles(int n, int max_sweeps);
 
 #ifdef __cplusplus
 }

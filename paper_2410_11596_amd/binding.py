@@ -22,8 +22,8 @@ EXPORTS = [
     "ctm_opts_default", "ctm_workspace_size", "ctm_init", "ctm_step", "ctm_converged",
     "ctm_rdm_1site", "ctm_rdm_2site", "ctm_energy", "ctm_free", "ctm_last_error",
     "ctm_env_epsilon", "ctm_s_err", "ctm_log_kappa", "ctm_num_moves", "ctm_move_record",
-    "ctm_sector_dims", "ctm_timing",
-    "hctm_dev_gemm", "hctm_dev_copy", "hctm_dev_chol_inv", "hctm_dev_jacobi",
+    "ctm_sector_dims", "ctm_timing", "ctm_gemm_stats",
+    "hctm_dev_gemm", "hctm_dev_copy", "hctm_dev_chol_inv", "hctm_dev_jacobi", "hctm_dev_jacobi_log_doubles",
 ]
 
 
@@ -34,6 +34,7 @@ class CtmOpts(ctypes.Structure):
         ("svd_rel_cutoff", ctypes.c_double),
         ("svd_iters", ctypes.c_int),
         ("seed", ctypes.c_ulonglong),
+        ("profile", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
@@ -78,12 +79,15 @@ def lib():
         "ctm_move_record": ([ctx, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip], ctypes.c_int),
         "ctm_sector_dims": ([ctx, ctypes.c_int, ip, ip], ctypes.c_int),
         "ctm_timing": ([ctx, dp, ctypes.c_int, ip], ctypes.c_int),
-        "hctm_dev_gemm": ([vp, vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.c_double, vp, vp], ctypes.c_int),
+        "ctm_gemm_stats": ([ctx, dp, dp, P(ctypes.c_longlong), ctypes.c_int], ctypes.c_int),
+        "hctm_dev_gemm": ([vp, vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.c_double, vp, vp,
+                                                               ctypes.c_longlong, vp], ctypes.c_int),
         "hctm_dev_copy": ([vp, vp, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_longlong), P(ctypes.c_longlong), vp],
                           ctypes.c_int),
         "hctm_dev_chol_inv": ([vp, vp, ctypes.c_int, ctypes.c_double, vp, vp], ctypes.c_int),
-        "hctm_dev_jacobi": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp],
+        "hctm_dev_jacobi": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp, vp, vp],
                             ctypes.c_int),
+        "hctm_dev_jacobi_log_doubles": ([ctypes.c_int, ctypes.c_int], ctypes.c_longlong),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -128,8 +132,8 @@ class CTMRG:
     torch's current HIP stream.
     """
 
-    def __init__(self, A, chi, form="z2", boundary=None, svd_rel_cutoff=1e-12, svd_iters=16, seed=0x5EED,
-                 stream=None, torch_workspace=True):
+    def __init__(self, A, chi, form="z2", boundary=None, svd_rel_cutoff=1e-12, svd_iters=12, seed=0x5EED,
+                 stream=None, torch_workspace=True, profile=False):
         torch = _torch()
         A = np.ascontiguousarray(A, dtype=np.float64)
         if A.ndim != 5 or len(set(A.shape[1:])) != 1:
@@ -142,6 +146,7 @@ class CTMRG:
         o.svd_rel_cutoff = svd_rel_cutoff
         o.svd_iters = svd_iters
         o.seed = seed
+        o.profile = 1 if profile else 0
         self._b = None
         if boundary is not None:
             self._b = np.ascontiguousarray(boundary, dtype=np.float64).reshape(-1)
@@ -250,6 +255,12 @@ class CTMRG:
         _check(lib().ctm_sector_dims(self._ctx, side, ctypes.byref(e), ctypes.byref(o)), self._ctx)
         return e.value, o.value
 
+    def gemm_stats(self, reset=False):
+        f, t, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_longlong()
+        _check(lib().ctm_gemm_stats(self._ctx, ctypes.byref(f), ctypes.byref(t), ctypes.byref(n), 1 if reset else 0),
+               self._ctx)
+        return {"flops": f.value, "seconds": t.value, "launches": n.value}
+
     def timing(self):
         t = np.zeros(16)
         n = ctypes.c_int()
@@ -266,10 +277,12 @@ def _stream_ptr(torch):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def dev_gemm(A, B, C, M, N, K, lda, ldb, ldc, ta=0, tb=0, alpha=1.0, beta=0.0, cscale=None):
+def dev_gemm(A, B, C, M, N, K, lda, ldb, ldc, ta=0, tb=0, alpha=1.0, beta=0.0, cscale=None, scratch=None):
     torch = _torch()
     cs = _ptr(cscale) if cscale is not None else None
-    _check(lib().hctm_dev_gemm(_ptr(A), _ptr(B), _ptr(C), M, N, K, lda, ldb, ldc, ta, tb, alpha, beta, cs,
+    sp = _ptr(scratch) if scratch is not None else None
+    sn = scratch.numel() if scratch is not None else 0
+    _check(lib().hctm_dev_gemm(_ptr(A), _ptr(B), _ptr(C), M, N, K, lda, ldb, ldc, ta, tb, alpha, beta, cs, sp, sn,
                                _stream_ptr(torch)))
 
 
@@ -289,7 +302,13 @@ def dev_chol_inv(G, Rinv, n, rel, info):
     _check(lib().hctm_dev_chol_inv(_ptr(G), _ptr(Rinv), n, rel, _ptr(info), _stream_ptr(torch)))
 
 
-def dev_jacobi(X, m, n, tol, max_sweeps, sv, perm, sweeps):
+def dev_jacobi(X, m, n, tol, max_sweeps, sv, perm, sweeps, V=None, vlog=None):
     torch = _torch()
-    _check(lib().hctm_dev_jacobi(_ptr(X), m, n, tol, max_sweeps, _ptr(sv), _ptr(perm), _ptr(sweeps),
+    vp = _ptr(V) if V is not None else None
+    lp = _ptr(vlog) if vlog is not None else None
+    _check(lib().hctm_dev_jacobi(_ptr(X), m, n, tol, max_sweeps, _ptr(sv), _ptr(perm), _ptr(sweeps), vp, lp,
                                  _stream_ptr(torch)))
+
+
+def jacobi_log_doubles(n, max_sweeps):
+    return int(lib().hctm_dev_jacobi_log_doubles(n, max_sweeps))

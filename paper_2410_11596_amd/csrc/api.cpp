@@ -56,6 +56,7 @@ hctm::Options to_options(const ctm_opts* o, int D) {
   if (o->svd_iters < 1 || o->svd_iters > 1000) throw hctm::Error(CTM_E_ARG, "svd_iters out of range");
   opt.svd_iters = o->svd_iters;
   opt.seed = o->seed;
+  opt.profile = o->profile ? 1 : 0;
   if (o->boundary) {
     const int q = D * D;
     opt.boundary.assign(o->boundary, o->boundary + q);
@@ -91,7 +92,7 @@ int ctm_opts_default(ctm_opts* o) {
   o->form = CTM_FORM_Z2;
   o->boundary = nullptr;
   o->svd_rel_cutoff = 1e-12;
-  o->svd_iters = 16;
+  o->svd_iters = 12;
   o->seed = 0x5eedull;
   return CTM_OK;
 }
@@ -240,9 +241,21 @@ int ctm_timing(ctm_ctx* c, double* t, int cap, int* n) {
   });
 }
 
+int ctm_gemm_stats(ctm_ctx* c, double* flops, double* seconds, long long* launches, int reset) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    const hctm::GemmStats& g = c->ctm->gemm_stats;
+    if (flops) *flops = g.flops;
+    if (seconds) *seconds = g.seconds;
+    if (launches) *launches = g.launches;
+    if (reset) c->ctm->reset_stats();
+  });
+}
+
 // ---------------------------------------------------------- test hooks ----
 int hctm_dev_gemm(const double* A, const double* B, double* C, int M, int N, int K, int lda, int ldb, int ldc, int ta,
-                  int tb, double alpha, double beta, const double* cscale, void* stream) {
+                  int tb, double alpha, double beta, const double* cscale, double* scratch, long long scratch_doubles,
+                  void* stream) {
   return guarded(nullptr, [&] {
     if (M < 0 || N < 0 || K < 0) throw hctm::Error(CTM_E_ARG, "negative size");
     hctm::GemmDesc d{};
@@ -261,7 +274,7 @@ int hctm_dev_gemm(const double* A, const double* B, double* C, int M, int N, int
     d.beta = beta;
     d.cscale = cscale;
     d.rscale = nullptr;
-    hctm::gemm({d}, reinterpret_cast<hipStream_t>(stream));
+    hctm::gemm({d}, reinterpret_cast<hipStream_t>(stream), scratch, scratch_doubles);
   });
 }
 
@@ -297,7 +310,7 @@ int hctm_dev_chol_inv(double* G, double* Rinv, int n, double rel, int* info, voi
 }
 
 int hctm_dev_jacobi(double* X, int m, int n, double tol, int max_sweeps, double* sv, int* perm, int* sweeps,
-                    void* stream) {
+                    double* V, double* vlog, void* stream) {
   return guarded(nullptr, [&] {
     if (m < 1 || n < 1 || n > 1024) throw hctm::Error(CTM_E_ARG, "size out of range");
     hctm::SmallProb p{};
@@ -310,8 +323,13 @@ int hctm_dev_jacobi(double* X, int m, int n, double tol, int max_sweeps, double*
     p.info = sweeps;
     p.sv = sv;
     p.perm = perm;
+    p.b = V;
+    p.vlog = vlog;
+    if (V && m != n) throw hctm::Error(CTM_E_ARG, "V needs a square X");
     hctm::jacobi({p}, reinterpret_cast<hipStream_t>(stream));
   });
 }
+
+long long hctm_dev_jacobi_log_doubles(int n, int max_sweeps) { return (long long)hctm::jacobi_log_doubles(n, max_sweeps); }
 
 }  // extern "C"

@@ -29,6 +29,7 @@ namespace hctm {
 
 namespace {
 constexpr int kDirectMax = 160;  // sectors up to this size are decomposed directly
+constexpr int kJacobiSweeps = 40;
 }
 
 // ------------------------------------------------------------- memory ----
@@ -109,6 +110,7 @@ void Ctm::plan_memory(bool counting) {
     S.isv = ar_.take((size_t)lcap);
     S.perm = ti(lcap);
     S.info = ti(8);
+    S.vlog = ar_.take(jacobi_log_doubles(160, kJacobiSweeps));
   }
   misc_ = ar_.take(64);
   kdev_ = ti(16);
@@ -128,6 +130,8 @@ void Ctm::plan_memory(bool counting) {
   dpart_ = ar_.take((size_t)(64 * kMaxDots));
   rho_ = ar_.take((size_t)(2 * d4 + 16));
   hdev_ = ar_.take((size_t)(d4 + 16));
+  gemm_scratch_cap_ = std::max<long long>(1 << 20, 24LL * lcap * lcap);
+  gemm_scratch_ = ar_.take((size_t)gemm_scratch_cap_);
 }
 
 // ------------------------------------------------------------- set-up ----
@@ -166,6 +170,7 @@ Ctm::Ctm(const double* A_host, int d, int D, int chi, const Options& o, hipStrea
 Ctm::~Ctm() {
   if (st_) (void)hipStreamSynchronize(st_);
   for (hipEvent_t e : ev_) (void)hipEventDestroy(e);
+  for (hipEvent_t e : gev_) (void)hipEventDestroy(e);
   if (host_k_) (void)hipHostFree(host_k_);
   if (host_d_) (void)hipHostFree(host_d_);
   if (own_mem_ && mem_) (void)hipFree(mem_);
@@ -180,8 +185,40 @@ void Ctm::launch_copies(std::vector<CopyJob>& jobs) {
 }
 
 void Ctm::launch_gemms(std::vector<GemmDesc>& g) {
-  gemm(g, st_);
+  if (!opt_.profile) {
+    gemm(g, st_, gemm_scratch_, gemm_scratch_cap_);
+    g.clear();
+    return;
+  }
+  double f = 0.0;
+  for (const GemmDesc& d : g)
+    if (d.M > 0 && d.N > 0 && d.K > 0) f += 2.0 * d.M * d.N * d.K;
+  while (gev_.size() < gev_used_ + 2) {
+    hipEvent_t e;
+    HCTM_HIP(hipEventCreate(&e));
+    gev_.push_back(e);
+  }
+  HCTM_HIP(hipEventRecord(gev_[gev_used_], st_));
+  gemm(g, st_, gemm_scratch_, gemm_scratch_cap_);
+  HCTM_HIP(hipEventRecord(gev_[gev_used_ + 1], st_));
+  gflops_.push_back(f);
+  gev_used_ += 2;
   g.clear();
+  if (gev_used_ >= 4096) flush_gemm_stats();
+}
+
+void Ctm::flush_gemm_stats() {
+  if (gev_used_ == 0) return;
+  sync();
+  for (size_t i = 0; i < gev_used_ / 2; ++i) {
+    float ms = 0.f;
+    HCTM_HIP(hipEventElapsedTime(&ms, gev_[2 * i], gev_[2 * i + 1]));
+    gemm_stats.seconds += ms * 1e-3;
+    gemm_stats.flops += gflops_[i];
+    gemm_stats.launches += 1;
+  }
+  gev_used_ = 0;
+  gflops_.clear();
 }
 
 void Ctm::permute(const BT& in, BT& out, std::initializer_list<int> perm, int nr_out) {
@@ -329,7 +366,7 @@ void Ctm::orth(std::vector<SvdSector*>& ss, bool ql, int passes) {
   // src = S.Y, dst = Ql or Qr, scratch Tm; 2 or 3 CholeskyQR passes, the
   // result always ends in dst (pass 0: src->dst, 1: dst->Tm, 2: Tm->dst;
   // with 2 passes the last product writes dst from Tm's predecessor).
-  if (passes != 2 && passes != 3) throw Error(1, "orth: passes must be 2 or 3");
+  if (passes < 1 || passes > 3) throw Error(1, "orth: passes must be 1, 2 or 3");
   for (int pass = 0; pass < passes; ++pass) {
     std::vector<GemmDesc> g;
     for (SvdSector* S : ss) {
@@ -360,7 +397,9 @@ void Ctm::orth(std::vector<SvdSector*>& ss, bool ql, int passes) {
       p.m = p.n = S->l;
       p.lda = p.ldb = S->l;
       // unit-diagonal (column-scaled) Gram; a small shift in the first pass
-      // keeps the factorisation defined while the columns are nearly parallel
+      // keeps the factorisation defined while the columns are nearly parallel.
+      // Inner iterations need only a well-conditioned basis (one pass); the
+      // last one is orthonormalised to rounding (three passes).
       p.rel = pass == 0 ? 1e-10 : 0.0;
       p.flags = 1;
       p.sv = S->isv;
@@ -441,7 +480,7 @@ void Ctm::truncated_svd(BT& M, int chi) {
           g.push_back(d);
         }
         launch_gemms(g);
-        orth(sub, true, last ? 3 : 2);  // Ql
+        orth(sub, true, last ? 3 : 1);  // Ql
         for (SvdSector* S : sub) {
           GemmDesc d{};
           d.A = S->Mp;
@@ -458,7 +497,7 @@ void Ctm::truncated_svd(BT& M, int chi) {
           g.push_back(d);
         }
         launch_gemms(g);
-        orth(sub, false, last ? 3 : 2);  // Qr; Y keeps Z = M^T Ql
+        orth(sub, false, last ? 3 : 1);  // Qr; Y keeps Z = M^T Ql
       }
       // B = Z^T Qr = Ql^T M Qr
       std::vector<GemmDesc> g;
@@ -491,7 +530,8 @@ void Ctm::truncated_svd(BT& M, int chi) {
       p.m = p.n = S->l;
       p.lda = S->l;
       p.rel = 1.1e-16 * S->l;
-      p.max_sweeps = 40;
+      p.max_sweeps = kJacobiSweeps;
+      p.vlog = S->vlog;
       p.info = S->info + 1;
       p.sv = S->sv;
       p.perm = S->perm;
@@ -766,6 +806,7 @@ void Ctm::step(int n_iter) {
   HCTM_HIP(hipMemcpyAsync(host_d_, misc_ + 16, sizeof(double), hipMemcpyDeviceToHost, st_));
   sync();
   delta_ = host_d_[0];
+  flush_gemm_stats();
   // phase times: quadrants, halves, svd, projectors + renormalisation
   timing.assign(4, 0.0);
   for (int i = 0; i + 4 < ev_index_ + 1 && i < (int)ev_.size(); i += 5) {

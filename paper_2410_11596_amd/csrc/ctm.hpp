@@ -32,8 +32,15 @@ struct Options {
   int form = 0;  // 0 Z2, 1 dense
   std::vector<double> boundary;
   double tau = 1e-12;
-  int svd_iters = 16;
+  int svd_iters = 12;
   unsigned long long seed = 0x5eed;
+  int profile = 0;  // 1: time every GEMM launch with HIP events
+};
+
+struct GemmStats {
+  double flops = 0.0;    // algorithmic 2*M*N*K summed over problems
+  double seconds = 0.0;  // summed launch durations
+  long long launches = 0;
 };
 
 // per-sector state of the truncated SVD
@@ -47,6 +54,7 @@ struct SvdSector {
   const double *W = nullptr, *V = nullptr;  // kept vectors (n x k) of M_P
   double *sv = nullptr, *isq = nullptr, *isv = nullptr;
   int *perm = nullptr, *info = nullptr;
+  double* vlog = nullptr;  // Jacobi rotation log
 };
 
 class Ctm {
@@ -70,6 +78,8 @@ class Ctm {
   Leg side(int s) const { return side_[s]; }
   hipStream_t stream() const { return st_; }
   std::vector<double> timing;  // per-phase seconds of the last step() call
+  GemmStats gemm_stats;        // accumulated since the last reset (profile mode)
+  void reset_stats() { gemm_stats = GemmStats(); }
 
  private:
   void plan_memory(bool counting);
@@ -151,11 +161,18 @@ class Ctm {
   long long halves_cap_ = 0;
   int halves_used_ = 0;
   int halves_max_ = 0;
+  double* gemm_scratch_ = nullptr;  // split-K partial tiles
+  long long gemm_scratch_cap_ = 0;
   double* dots_ = nullptr;     // dot-product results
   double* dpart_ = nullptr;    // dot-product partial sums (64 per job)
   double* rho_ = nullptr;      // device RDM output (d^4)
   double* hdev_ = nullptr;     // bond operator (d^4)
   MoveRecord pending_;
+  // profile mode: pending GEMM event pairs and their flops
+  std::vector<hipEvent_t> gev_;
+  std::vector<double> gflops_;
+  size_t gev_used_ = 0;
+  void flush_gemm_stats();
 };
 
 }  // namespace hctm

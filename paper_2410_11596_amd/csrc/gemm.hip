@@ -3,17 +3,23 @@
 // Every contraction of the method is a dense product of parity blocks (the
 // cost model of Sec. II B: two half-size block products instead of one full
 // product).  One launch takes a list of independent problems; the grid is the
-// concatenation of their output tiles.
+// concatenation of their output tiles (and K slices).
 //
-// Tile: 128 x 128 per workgroup of 256 threads (4 wave64), K step 16, each
-// wave owns a 64 x 64 sub-tile = 4 x 4 MFMA 16x16 accumulators.  Operands are
+// Tile: BM x BN per workgroup of 256 threads (4 wave64 in a 2 x 2 layout),
+// K step 16.  128 x 128 for the large block products; 64 x 64 when the
+// problems are too small to fill the 256 CUs; and for small outputs with a
+// long reduction (the l x l Gram matrices of the subspace iteration) the K
+// range is split over several workgroups whose partial tiles are summed in a
+// fixed order by a second kernel (deterministic, no atomics).  Operands are
 // staged through LDS in k-major order so that one MFMA fragment read is a
-// contiguous 128-byte row per 16 lanes.  Loads for step k+1 are issued into
-// registers before the MFMAs of step k.
+// contiguous row per 16 lanes; loads for step k+1 are issued into registers
+// before the MFMAs of step k.
 //
 // MFMA 16x16x4 f64 operand layout (measured on gfx950): lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; its four accumulator values are
 // D[l / 16 + 4 * v][l % 16], v = 0..3.
+#include <algorithm>
+
 #include "hctm_internal.hpp"
 
 namespace hctm {
@@ -21,10 +27,8 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int BK = 16;
 constexpr int NT = 256;
-constexpr int LDA_S = BM + 4;   // LDS row pitch (doubles), padded
-constexpr int LDB_S = BN + 4;
 constexpr int kMaxGroup = 16;
 
 struct Prob {
@@ -33,9 +37,10 @@ struct Prob {
   double* C;
   const double* cscale;
   const double* rscale;
+  double* part;  // split-K partial tiles (ksplit x M x N), null if ksplit == 1
   double alpha, beta;
   int M, N, K, lda, ldb, ldc, ta, tb;
-  int tiles_n, tile_start;
+  int tiles_m, tiles_n, ksplit, kchunk, tile_start;
 };
 
 struct Group {
@@ -44,67 +49,78 @@ struct Group {
   int total;
 };
 
-// Load a BK x BM slab of op(A) (k-major) into registers: 8 doubles per thread.
-__device__ __forceinline__ void load_tile(const double* __restrict__ X, int ld, int trans, int rows, int K,
-                                          int r0, int k0, double (&reg)[8]) {
+// Load a BK x ROWS slab of op(X) (k-major) into registers.
+template <int ROWS>
+__device__ __forceinline__ void load_tile(const double* __restrict__ X, int ld, int trans, int rows, int kend,
+                                          int r0, int k0, double (&reg)[ROWS * BK / NT]) {
+  constexpr int PER = ROWS * BK / NT;
   const int t = threadIdx.x;
   if (!trans) {
-    // X[r][k], k contiguous: thread -> row r0 + t/2, k = k0 + (t%2)*8 .. +8
-    const int r = r0 + (t >> 1);
-    const int kb = k0 + (t & 1) * 8;
+    // X[r][k], k contiguous
+    constexpr int TPR = BK / PER;
+    const int r = r0 + t / TPR;
+    const int kb = k0 + (t % TPR) * PER;
     const double* src = X + (long long)r * ld + kb;
     const bool rok = r < rows;
-    if (rok && kb + 8 <= K && ((((uintptr_t)src) & 15) == 0)) {
+    if (rok && kb + PER <= kend && ((((uintptr_t)src) & 15) == 0)) {
       const double2* s2 = reinterpret_cast<const double2*>(src);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < PER / 2; ++i) {
         double2 v = s2[i];
         reg[2 * i] = v.x;
         reg[2 * i + 1] = v.y;
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) reg[i] = (rok && kb + i < K) ? src[i] : 0.0;
+      for (int i = 0; i < PER; ++i) reg[i] = (rok && kb + i < kend) ? src[i] : 0.0;
     }
   } else {
-    // X[k][r], r contiguous: thread -> k = k0 + t/16, r = r0 + (t%16)*8 .. +8
-    const int k = k0 + (t >> 4);
-    const int rb = r0 + (t & 15) * 8;
+    // X[k][r], r contiguous: 16 threads per k row
+    const int k = k0 + t / 16;
+    const int rb = r0 + (t % 16) * PER;
     const double* src = X + (long long)k * ld + rb;
-    const bool kok = k < K;
-    if (kok && rb + 8 <= rows && ((((uintptr_t)src) & 15) == 0)) {
+    const bool kok = k < kend;
+    if (kok && rb + PER <= rows && ((((uintptr_t)src) & 15) == 0)) {
       const double2* s2 = reinterpret_cast<const double2*>(src);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < PER / 2; ++i) {
         double2 v = s2[i];
         reg[2 * i] = v.x;
         reg[2 * i + 1] = v.y;
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) reg[i] = (kok && rb + i < rows) ? src[i] : 0.0;
+      for (int i = 0; i < PER; ++i) reg[i] = (kok && rb + i < rows) ? src[i] : 0.0;
     }
   }
 }
 
-__device__ __forceinline__ void store_tile(double* __restrict__ S, int pitch, int trans, const double (&reg)[8]) {
+template <int ROWS>
+__device__ __forceinline__ void store_tile(double* __restrict__ S, int trans, const double (&reg)[ROWS * BK / NT]) {
+  constexpr int PER = ROWS * BK / NT;
+  constexpr int PITCH = ROWS + 4;
   const int t = threadIdx.x;
   if (!trans) {
-    const int r = t >> 1;
-    const int kb = (t & 1) * 8;
+    constexpr int TPR = BK / PER;
+    const int r = t / TPR;
+    const int kb = (t % TPR) * PER;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) S[(kb + i) * pitch + r] = reg[i];
+    for (int i = 0; i < PER; ++i) S[(kb + i) * PITCH + r] = reg[i];
   } else {
-    const int k = t >> 4;
-    const int rb = (t & 15) * 8;
+    const int k = t / 16;
+    const int rb = (t % 16) * PER;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) S[k * pitch + rb + i] = reg[i];
+    for (int i = 0; i < PER; ++i) S[k * PITCH + rb + i] = reg[i];
   }
 }
 
+template <int BM, int BN>
 __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(Group g) {
-  __shared__ double As[BK * LDA_S];
-  __shared__ double Bs[BK * LDB_S];
+  constexpr int PA = BM + 4, PB = BN + 4;
+  constexpr int WM = BM / 2, WN = BN / 2;  // per-wave sub-tile
+  constexpr int TI = WM / 16, TJ = WN / 16;
+  __shared__ double As[BK * PA];
+  __shared__ double Bs[BK * PB];
 
   // XCD-aware order: blocks are dealt to the 8 XCDs round robin; give each
   // XCD a contiguous range of tiles so that neighbouring tiles share its L2.
@@ -118,62 +134,82 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(Group g) {
   for (int i = 1; i < g.n; ++i)
     if (b >= g.p[i].tile_start) pi = i;
   const Prob& P = g.p[pi];
-  const int tile = b - P.tile_start;
+  int tile = b - P.tile_start;
+  const int ks = tile % P.ksplit;
+  tile /= P.ksplit;
   const int tm = tile / P.tiles_n, tn = tile % P.tiles_n;
   const int m0 = tm * BM, n0 = tn * BN;
+  const int kbeg = ks * P.kchunk;
+  const int kend = min(P.K, kbeg + P.kchunk);
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
   const int li = lane & 15, lk = lane >> 4;
 
-  v4d acc[4][4];
+  v4d acc[TI][TJ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < TJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  double ra[8], rb[8];
-  load_tile(P.A, P.lda, P.ta, P.M, P.K, m0, 0, ra);
+  double ra[BM * BK / NT], rb[BN * BK / NT];
+  load_tile<BM>(P.A, P.lda, P.ta, P.M, kend, m0, kbeg, ra);
   // B is stored [k][n] (tb=0, n contiguous) or [n][k] (tb=1): the roles of
   // the two layouts are swapped with respect to A.
-  load_tile(P.B, P.ldb, !P.tb, P.N, P.K, n0, 0, rb);
-  store_tile(As, LDA_S, P.ta, ra);
-  store_tile(Bs, LDB_S, !P.tb, rb);
+  load_tile<BN>(P.B, P.ldb, !P.tb, P.N, kend, n0, kbeg, rb);
+  store_tile<BM>(As, P.ta, ra);
+  store_tile<BN>(Bs, !P.tb, rb);
   __syncthreads();
 
 #pragma unroll 1
-  for (int k0 = 0; k0 < P.K; k0 += BK) {
-    const bool more = k0 + BK < P.K;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
     if (more) {
-      load_tile(P.A, P.lda, P.ta, P.M, P.K, m0, k0 + BK, ra);
-      load_tile(P.B, P.ldb, !P.tb, P.N, P.K, n0, k0 + BK, rb);
+      load_tile<BM>(P.A, P.lda, P.ta, P.M, kend, m0, k0 + BK, ra);
+      load_tile<BN>(P.B, P.ldb, !P.tb, P.N, kend, n0, k0 + BK, rb);
     }
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      double af[4], bf[4];
+      double af[TI], bf[TJ];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) af[i] = As[(kk + lk) * LDA_S + wm + i * 16 + li];
+      for (int i = 0; i < TI; ++i) af[i] = As[(kk + lk) * PA + wm + i * 16 + li];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bf[j] = Bs[(kk + lk) * LDB_S + wn + j * 16 + li];
+      for (int j = 0; j < TJ; ++j) bf[j] = Bs[(kk + lk) * PB + wn + j * 16 + li];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
     if (more) {
-      store_tile(As, LDA_S, P.ta, ra);
-      store_tile(Bs, LDB_S, !P.tb, rb);
+      store_tile<BM>(As, P.ta, ra);
+      store_tile<BN>(Bs, !P.tb, rb);
     }
     __syncthreads();
   }
 
   // epilogue: lane holds D[lk + 4*v][li] of every 16x16 tile
+  if (P.ksplit > 1) {
+    double* part = P.part + (long long)ks * P.M * P.N;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < TJ; ++j) {
+        const int col = n0 + wn + j * 16 + li;
+        if (col >= P.N) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = m0 + wm + i * 16 + lk + 4 * v;
+          if (row < P.M) part[(long long)row * P.N + col] = acc[i][j][v];
+        }
+      }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < TI; ++i) {
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
       const int col = n0 + wn + j * 16 + li;
       if (col >= P.N) continue;
       const double cs = P.cscale ? P.cscale[col] : 1.0;
@@ -191,6 +227,24 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(Group g) {
   }
 }
 
+// Sum the K slices of split problems in slice order and apply the epilogue.
+__global__ void splitk_reduce_kernel(Group g) {
+  const Prob& P = g.p[blockIdx.y];
+  if (P.ksplit <= 1) return;
+  const long long n = (long long)P.M * P.N;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < P.ksplit; ++k) s += P.part[(long long)k * n + e];
+    const int row = (int)(e / P.N), col = (int)(e % P.N);
+    double val = P.alpha * s;
+    if (P.cscale) val *= P.cscale[col];
+    if (P.rscale) val *= P.rscale[row];
+    double* c = P.C + (long long)row * P.ldc + col;
+    if (P.beta != 0.0) val += P.beta * *c;
+    *c = val;
+  }
+}
+
 // C = beta * C for problems with K == 0 (nothing to multiply).
 __global__ void scale_c_kernel(double* C, int M, int N, int ldc, double beta) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -200,18 +254,44 @@ __global__ void scale_c_kernel(double* C, int M, int N, int ldc, double beta) {
   *p = beta == 0.0 ? 0.0 : beta * *p;
 }
 
+long long tiles(const GemmDesc& d, int bm, int bn) {
+  return (long long)((d.M + bm - 1) / bm) * ((d.N + bn - 1) / bn);
+}
+
 }  // namespace
 
-void gemm(const std::vector<GemmDesc>& probs, hipStream_t s) {
+void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch, long long scratch_cap) {
+  // tile shape for the whole call, from how many workgroups it yields
+  constexpr long long kFill = 240;  // about one workgroup per CU
+  long long t128 = 0, t64 = 0;
+  for (const GemmDesc& d : probs)
+    if (d.M > 0 && d.N > 0 && d.K > 0) {
+      t128 += tiles(d, 128, 128);
+      t64 += tiles(d, 64, 64);
+    }
+  const int cfg = t128 >= kFill ? 0 : 1;  // 0: 128x128, 1: 64x64
+  const int bm = cfg == 0 ? 128 : 64, bn = bm;
+  long long part_used = 0;
+
   Group g;
   g.n = 0;
   g.total = 0;
+  bool any_split = false;
   auto flush = [&]() {
     if (g.n == 0) return;
-    hipLaunchKernelGGL(gemm_f64_kernel, dim3(g.total), dim3(NT), 0, s, g);
+    if (cfg == 0)
+      hipLaunchKernelGGL((gemm_f64_kernel<128, 128>), dim3(g.total), dim3(NT), 0, s, g);
+    else
+      hipLaunchKernelGGL((gemm_f64_kernel<64, 64>), dim3(g.total), dim3(NT), 0, s, g);
     HCTM_HIP(hipGetLastError());
+    if (any_split) {
+      hipLaunchKernelGGL(splitk_reduce_kernel, dim3(64, g.n), dim3(256), 0, s, g);
+      HCTM_HIP(hipGetLastError());
+    }
     g.n = 0;
     g.total = 0;
+    part_used = 0;
+    any_split = false;
   };
   for (const GemmDesc& d : probs) {
     if (d.M <= 0 || d.N <= 0) continue;
@@ -239,9 +319,28 @@ void gemm(const std::vector<GemmDesc>& probs, hipStream_t s) {
     p.ldc = d.ldc;
     p.ta = d.ta;
     p.tb = d.tb;
-    p.tiles_n = (d.N + BN - 1) / BN;
+    p.tiles_m = (d.M + bm - 1) / bm;
+    p.tiles_n = (d.N + bn - 1) / bn;
+    // split K when the call has too few output tiles and this K is long
+    int ks = 1;
+    if (cfg == 1 && t64 < kFill && scratch) {
+      const long long want = (2 * kFill + t64 - 1) / t64;
+      const long long maxk = d.K / 256;  // at least 256 of K per slice
+      ks = (int)std::max<long long>(1, std::min(want, maxk));
+      while (ks > 1 && part_used + (long long)ks * d.M * d.N > scratch_cap) --ks;
+    }
+    p.ksplit = ks;
+    p.kchunk = ks > 1 ? (((d.K + ks - 1) / ks + BK - 1) / BK) * BK : d.K;
+    if (ks > 1) {
+      p.ksplit = (d.K + p.kchunk - 1) / p.kchunk;
+      p.part = scratch + part_used;
+      part_used += (long long)p.ksplit * d.M * d.N;
+      any_split = true;
+    } else {
+      p.part = nullptr;
+    }
     p.tile_start = g.total;
-    g.total += ((d.M + BM - 1) / BM) * p.tiles_n;
+    g.total += p.tiles_m * p.tiles_n * p.ksplit;
     g.n++;
   }
   flush();

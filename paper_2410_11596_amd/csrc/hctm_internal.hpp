@@ -37,7 +37,8 @@ struct GemmDesc {
   const double* cscale;
   const double* rscale;  // optional per-row scale of the product
 };
-void gemm(const std::vector<GemmDesc>& probs, hipStream_t s);
+// scratch (optional): device doubles for split-K partial tiles.
+void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch = nullptr, long long scratch_cap = 0);
 
 // -------------------------------------------------------------- permute ----
 // Strided copy of one dense block: out[sum_j x_j ostr_j] = in[sum_j x_j istr_j]

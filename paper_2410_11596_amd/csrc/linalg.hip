@@ -6,6 +6,7 @@
 //   * the merge of the two parity spectra and the truncation to chi.
 // Each small problem is owned by one workgroup; several independent problems
 // (the two parity sectors, the four corners) go in one launch.
+#include <algorithm>
 #include <cmath>
 
 #include "hctm_internal.hpp"
@@ -218,6 +219,223 @@ __device__ void chol_inv_body(const SmallProb& P, double* Lp, double* Xp) {
   }
 }
 
+// Register-resident version for n <= 32 R: thread (ty, tx) of a 32 x 32 grid
+// owns rows i = ty + 32 a and columns k = tx + 32 c (a, c < R) of the matrix.
+// Factorisation: at step j the pivot column j is read from a double-buffered
+// LDS vector written by its owners during step j-1 (one barrier per step).
+// Inverse: right-looking forward substitution for all right-hand sides at
+// once, X = L^-1, with row j of X broadcast the same way.
+template <int R>
+__device__ void chol_inv_regs(const SmallProb& P, double* Lpk, double* buf) {
+  const int n = P.n, ld = P.lda, ldr = P.ldb;
+  const double* G = P.a;
+  double* Ri = P.b;
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  __shared__ double red[16];
+  __shared__ int bad_s;
+  const bool scale = (P.flags & 1) != 0;
+  double* dsc = P.sv;
+  if (scale)
+    for (int i = tid; i < n; i += NT) {
+      const double g = G[(long long)i * ld + i];
+      dsc[i] = g > 0.0 ? sqrt(g) : 1.0;
+    }
+  if (tid == 0) bad_s = 0;
+  __syncthreads();
+  double dmax = 0.0;
+  for (int i = tid; i < n; i += NT) {
+    const double g = G[(long long)i * ld + i];
+    dmax = fmax(dmax, scale ? g / (dsc[i] * dsc[i]) : g);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = dmax;
+  __syncthreads();
+  dmax = 0.0;
+  for (int i = 0; i < NT / 64; ++i) dmax = fmax(dmax, red[i]);
+  const double shift = P.rel * dmax;
+  const double thresh = 1e-27 * dmax;
+
+  double a[R][R];
+#pragma unroll
+  for (int u = 0; u < R; ++u)
+#pragma unroll
+    for (int v = 0; v < R; ++v) {
+      const int i = ty + 32 * u, k = tx + 32 * v;
+      double x = 0.0;
+      if (i < n && k <= i) {
+        x = G[(long long)i * ld + k];
+        if (scale) x /= dsc[i] * dsc[k];
+        if (i == k) x += shift;
+      }
+      a[u][v] = x;
+    }
+  // column 0 to the buffer
+  if (tx == 0)
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = ty + 32 * u;
+      if (i < n) buf[i] = a[u][0];
+    }
+  __syncthreads();
+
+  for (int j = 0; j < n; ++j) {
+    const double* cur = buf + (j & 1) * 32 * R;
+    double* nxt = buf + ((j + 1) & 1) * 32 * R;
+    const double djj = cur[j];
+    const double inv = djj > thresh ? 1.0 / djj : 0.0;
+    double ci[R], ck[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = ty + 32 * u;
+      ci[u] = (i > j && i < n) ? cur[i] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < R; ++v) {
+      const int k = tx + 32 * v;
+      ck[v] = (k > j && k < n && 32 * v + 31 > j) ? cur[k] * inv : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      if (32 * u + 31 <= j) continue;  // whole row block finished (uniform)
+#pragma unroll
+      for (int v = 0; v < R; ++v) {
+        if (32 * v + 31 <= j || v > u) continue;  // finished or above the diagonal
+        a[u][v] -= ci[u] * ck[v];                 // zero outside j < k <= i
+      }
+    }
+    // owners of column j keep its final values (rows >= j) in the packed store
+#pragma unroll
+    for (int v = 0; v < R; ++v) {
+      if (tx + 32 * v != j) continue;
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int i = ty + 32 * u;
+        if (i >= j && i < n) Lpk[i * (i + 1) / 2 + j] = (i == j) ? djj : cur[i];
+      }
+    }
+    // owners of column j+1 publish it (final after this update)
+#pragma unroll
+    for (int v = 0; v < R; ++v) {
+      if (tx + 32 * v != j + 1) continue;
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int i = ty + 32 * u;
+        if (i >= j + 1 && i < n) nxt[i] = a[u][v];
+      }
+    }
+    __syncthreads();
+  }
+  // L = column / sqrt(pivot); dropped columns (pivot <= thresh) become zero
+  for (int e = tid; e < n * (n + 1) / 2; e += NT) {
+    int i, k;
+    tri_decode(e, i, k);
+    if (i == k) continue;
+    const double dk = Lpk[k * (k + 1) / 2 + k];
+    Lpk[e] = dk > thresh ? Lpk[e] / sqrt(dk) : 0.0;
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += NT) {
+    const double dj = Lpk[j * (j + 1) / 2 + j];
+    if (!(dj > thresh)) atomicAdd(&bad_s, 1);
+    Lpk[j * (j + 1) / 2 + j] = dj > thresh ? sqrt(dj) : 0.0;
+  }
+  __syncthreads();
+  if (tid == 0 && P.info) *P.info = bad_s;
+
+  // X = L^-1: b holds B (identity minus the applied updates) for (i, c), c <= i
+  double (&b)[R][R] = a;
+#pragma unroll
+  for (int u = 0; u < R; ++u)
+#pragma unroll
+    for (int v = 0; v < R; ++v) b[u][v] = (ty + 32 * u == tx + 32 * v) ? 1.0 : 0.0;
+  // row 0 of X
+  if (ty == 0)
+#pragma unroll
+    for (int v = 0; v < R; ++v) {
+      const int c = tx + 32 * v;
+      const double l00 = Lpk[0];
+      if (c == 0) {
+        const double x = l00 > 0.0 ? b[0][v] / l00 : 0.0;
+        b[0][v] = x;
+        buf[0] = x;
+      }
+    }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double* xr = buf + (j & 1) * 32 * R;
+    double* nxt = buf + ((j + 1) & 1) * 32 * R;
+    double lij[R], xc[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = ty + 32 * u;
+      lij[u] = (i > j && i < n) ? Lpk[i * (i + 1) / 2 + j] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < R; ++v) {
+      const int c = tx + 32 * v;
+      xc[v] = (c <= j) ? xr[c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      if (32 * u + 31 <= j) continue;  // rows <= j are final (uniform)
+#pragma unroll
+      for (int v = 0; v < R; ++v) {
+        if (32 * v > j || v > u) continue;  // only columns c <= j change
+        b[u][v] -= lij[u] * xc[v];
+      }
+    }
+    // owners of row j+1 finalise it and publish
+    if (j + 1 < n) {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int i = ty + 32 * u;
+        if (i != j + 1) continue;
+        const double lii = Lpk[i * (i + 1) / 2 + i];
+#pragma unroll
+        for (int v = 0; v < R; ++v) {
+          const int c = tx + 32 * v;
+          if (c <= i) {
+            const double x = lii > 0.0 ? b[u][v] / lii : 0.0;
+            b[u][v] = x;
+            nxt[c] = x;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // Rinv[c][i] = X[i][c] / d[c] (upper), zero below the diagonal
+#pragma unroll
+  for (int u = 0; u < R; ++u)
+#pragma unroll
+    for (int v = 0; v < R; ++v) {
+      const int i = ty + 32 * u, c = tx + 32 * v;
+      if (i < n && c < n) {
+        double x = c <= i ? b[u][v] : 0.0;
+        if (scale && c <= i) x /= dsc[c];
+        Ri[(long long)c * ldr + i] = x;
+      }
+    }
+}
+
+__global__ __launch_bounds__(NT) void chol_inv_regs_kernel(SmallBatch b) {
+  __shared__ double Lpk[160 * 161 / 2];
+  __shared__ double buf[2 * 32 * 5];
+  const SmallProb& P = b.p[blockIdx.x];
+  const int R = (P.n + 31) / 32;
+  if (R <= 1)
+    chol_inv_regs<1>(P, Lpk, buf);
+  else if (R == 2)
+    chol_inv_regs<2>(P, Lpk, buf);
+  else if (R == 3)
+    chol_inv_regs<3>(P, Lpk, buf);
+  else if (R == 4)
+    chol_inv_regs<4>(P, Lpk, buf);
+  else
+    chol_inv_regs<5>(P, Lpk, buf);
+}
+
 __global__ __launch_bounds__(NT) void chol_inv_kernel(SmallBatch b) {
   __shared__ double Lp[kLdsTri];
   __shared__ double Xp[kLdsTri];
@@ -332,6 +550,177 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(SmallBatch b) {
     }
     P.sv[rank] = v;
     P.perm[rank] = j;
+  }
+}
+
+// LDS-resident one-sided Jacobi for m * n <= kJacLds: X is held column-major
+// in LDS; 16 lanes work on one column pair (a wave on four pairs at a time).
+// The plane rotations of every round are logged (cos, sin per pair) so that
+// the right vectors can be rebuilt in parallel afterwards (jacobi_v_kernel).
+constexpr int kJacLds = 19968;  // doubles of LDS for X (n = m <= 141)
+
+__device__ __forceinline__ double sum16(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+  return v;
+}
+
+__device__ __forceinline__ void rr_pair(int r, int pp, int n2, int& i, int& j) {
+  const int mr = n2 - 1;
+  if (pp == 0) {
+    i = r;
+    j = n2 - 1;
+  } else {
+    i = (r + pp) % mr;
+    j = (r - pp + mr) % mr;
+  }
+  if (i > j) {
+    const int t = i;
+    i = j;
+    j = t;
+  }
+}
+
+__global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
+  __shared__ double Xs[kJacLds];
+  __shared__ int any_rot;
+  __shared__ double red[16];
+  __shared__ double nrm[160];
+  const SmallProb& P = b.p[blockIdx.x];
+  const int m = P.m, n = P.n, ld = P.lda;
+  double* X = P.a;
+  double* rlog = P.b;  // (max_sweeps x (n2-1) x n2/2) pairs of (c, s)
+  const int tid = threadIdx.x;
+  for (int e = tid; e < m * n; e += NT) {
+    const int r = e / n, c = e % n;
+    Xs[c * m + r] = X[(long long)r * ld + c];
+  }
+  double f2 = 0.0;
+  for (int e = tid; e < m * n; e += NT) {
+    const double x = X[(long long)(e / n) * ld + (e % n)];
+    f2 += x * x;
+  }
+  f2 = block_sum(f2, red);  // includes barriers
+  const double small2 = f2 * (2.3e-16 * m) * (2.3e-16 * m);
+  const double tol = P.rel;
+  const int n2 = n + (n & 1), npairs = n2 / 2, rounds = n2 - 1;
+  const int sub = tid & 15, grp = tid >> 4, ngrp = NT / 16;
+  int sweep = 0;
+  for (sweep = 0; sweep < P.max_sweeps; ++sweep) {
+    if (tid == 0) any_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < rounds; ++r) {
+      double2* lg = rlog ? reinterpret_cast<double2*>(rlog) + ((long long)sweep * rounds + r) * npairs : nullptr;
+      for (int pp = grp; pp < npairs; pp += ngrp) {
+        int i, j;
+        rr_pair(r, pp, n2, i, j);
+        double c = 1.0, sn = 0.0;
+        if (j < n) {
+          double* xi = Xs + i * m;
+          double* xj = Xs + j * m;
+          double a = 0.0, bb = 0.0, g = 0.0;
+          for (int k = sub; k < m; k += 16) {
+            const double u = xi[k], v = xj[k];
+            a += u * u;
+            bb += v * v;
+            g += u * v;
+          }
+          a = sum16(a);
+          bb = sum16(bb);
+          g = sum16(g);
+          if (fmin(a, bb) > small2 && fabs(g) > tol * sqrt(a) * sqrt(bb)) {
+            const double zeta = (bb - a) / (2.0 * g);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = c * t;
+            for (int k = sub; k < m; k += 16) {
+              const double u = xi[k], v = xj[k];
+              xi[k] = c * u - sn * v;
+              xj[k] = sn * u + c * v;
+            }
+            if (sub == 0) any_rot = 1;
+          }
+        }
+        if (sub == 0 && rlog) lg[pp] = make_double2(c, sn);
+      }
+      __syncthreads();
+    }
+    const int rot = any_rot;
+    __syncthreads();
+    if (!rot) {
+      ++sweep;  // the converged sweep is logged too (identity rotations)
+      break;
+    }
+  }
+  if (tid == 0 && P.info) *P.info = (sweep <= P.max_sweeps && !any_rot) ? sweep : -sweep;
+  for (int j = tid; j < n; j += NT) {
+    double s = 0.0;
+    for (int k = 0; k < m; ++k) s += Xs[j * m + k] * Xs[j * m + k];
+    nrm[j] = sqrt(s);
+  }
+  for (int e = tid; e < m * n; e += NT) {
+    const int r = e / n, c = e % n;
+    X[(long long)r * ld + c] = Xs[c * m + r];
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += NT) {
+    const double v = nrm[j];
+    int rank = 0;
+    for (int i = 0; i < n; ++i) {
+      const double w = nrm[i];
+      rank += (w > v) || (w == v && i < j);
+    }
+    P.sv[rank] = v;
+    P.perm[rank] = j;
+  }
+}
+
+// Rebuild V (n x n, row-major, written to P.a) from the rotation log in
+// P.b: rows are independent, 32 rows per workgroup held column-major in LDS;
+// the log is staged 16 rounds at a time so that each round reads LDS only.
+constexpr int kVChunk = 16;
+__global__ __launch_bounds__(256) void jacobi_v_kernel(SmallBatch b) {
+  __shared__ double Vs[160 * 32];
+  __shared__ double2 Ls[kVChunk * 80];
+  const SmallProb& P = b.p[blockIdx.y];
+  const int n = P.n;
+  const int sweeps = P.info ? abs(*P.info) : 0;
+  const double2* lg = reinterpret_cast<const double2*>(P.b);
+  double* V = P.a;
+  const int r0 = blockIdx.x * 32;
+  if (r0 >= n) return;
+  const int rows = min(32, n - r0);
+  for (int e = threadIdx.x; e < 32 * n; e += 256) {
+    const int c = e / 32, rr = e % 32;
+    Vs[c * 32 + rr] = (r0 + rr == c) ? 1.0 : 0.0;
+  }
+  const int n2 = n + (n & 1), npairs = n2 / 2, rounds = n2 - 1;
+  const long long total = (long long)sweeps * rounds;
+  for (long long t0 = 0; t0 < total; t0 += kVChunk) {
+    const int nr = (int)min<long long>(kVChunk, total - t0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * npairs; e += 256) Ls[e] = lg[t0 * npairs + e];
+    __syncthreads();
+    for (int q = 0; q < nr; ++q) {
+      const int r = (int)((t0 + q) % rounds);
+      for (int e = threadIdx.x; e < npairs * 32; e += 256) {
+        const int pp = e / 32, rr = e % 32;
+        const double2 cs = Ls[q * npairs + pp];
+        if (cs.y == 0.0 || rr >= rows) continue;
+        int i, j;
+        rr_pair(r, pp, n2, i, j);
+        if (j >= n) continue;
+        const double u = Vs[i * 32 + rr], v = Vs[j * 32 + rr];
+        Vs[i * 32 + rr] = cs.x * u - cs.y * v;
+        Vs[j * 32 + rr] = cs.y * u + cs.x * v;
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < rows * n; e += 256) {
+    const int rr = e / n, c = e % n;
+    V[(long long)(r0 + rr) * n + c] = Vs[c * 32 + rr];
   }
 }
 
@@ -470,23 +859,65 @@ void scale_inv(double* p, size_t n, const double* nrm, hipStream_t s) {
 }
 
 void chol_inv(const std::vector<SmallProb>& probs, hipStream_t s) {
-  for (size_t i = 0; i < probs.size(); i += kMaxSmall) {
-    SmallBatch b;
-    b.n = 0;
-    for (size_t j = i; j < probs.size() && b.n < kMaxSmall; ++j) b.p[b.n++] = probs[j];
-    hipLaunchKernelGGL(chol_inv_kernel, dim3(b.n), dim3(NT), 0, s, b);
-    HCTM_HIP(hipGetLastError());
+  // register-resident kernel for n <= 160, the LDS/global one above that
+  std::vector<SmallProb> small, large;
+  for (const SmallProb& p : probs) (p.n <= 160 ? small : large).push_back(p);
+  for (int pass = 0; pass < 2; ++pass) {
+    const std::vector<SmallProb>& v = pass == 0 ? small : large;
+    for (size_t i = 0; i < v.size(); i += kMaxSmall) {
+      SmallBatch b;
+      b.n = 0;
+      for (size_t j = i; j < v.size() && b.n < kMaxSmall; ++j) b.p[b.n++] = v[j];
+      if (pass == 0)
+        hipLaunchKernelGGL(chol_inv_regs_kernel, dim3(b.n), dim3(NT), 0, s, b);
+      else
+        hipLaunchKernelGGL(chol_inv_kernel, dim3(b.n), dim3(NT), 0, s, b);
+      HCTM_HIP(hipGetLastError());
+    }
   }
 }
 
+size_t jacobi_log_doubles(int n, int max_sweeps) {
+  const size_t n2 = n + (n & 1);
+  return (size_t)max_sweeps * (n2 - 1) * n2;  // (c, s) per pair per round
+}
+
 void jacobi(const std::vector<SmallProb>& probs, hipStream_t s) {
-  for (size_t i = 0; i < probs.size(); i += kMaxSmall) {
+  // LDS kernel (rotation log + parallel V rebuild) where X fits in LDS and a
+  // log buffer is given; global-memory kernel otherwise
+  std::vector<SmallProb> lds, glob;
+  for (const SmallProb& p : probs) {
+    if (p.n > 1024) throw Error(1, "jacobi: too many columns");
+    const bool fits = (long long)p.m * p.n <= kJacLds && p.n <= 160 && (!p.b || p.vlog);
+    (fits ? lds : glob).push_back(p);
+  }
+  for (size_t i = 0; i < lds.size(); i += kMaxSmall) {
+    SmallBatch b, bv;
+    b.n = bv.n = 0;
+    int nmax = 0;
+    for (size_t j = i; j < lds.size() && b.n < kMaxSmall; ++j) {
+      SmallProb p = lds[j];
+      p.b = lds[j].b ? p.vlog : nullptr;  // the Jacobi kernel writes the rotation log
+      b.p[b.n++] = p;
+      if (lds[j].b) {
+        SmallProb q = lds[j];
+        q.a = lds[j].b;  // V output
+        q.b = lds[j].vlog;
+        bv.p[bv.n++] = q;
+        nmax = std::max(nmax, q.n);
+      }
+    }
+    hipLaunchKernelGGL(jacobi_lds_kernel, dim3(b.n), dim3(NT), 0, s, b);
+    HCTM_HIP(hipGetLastError());
+    if (bv.n > 0) {
+      hipLaunchKernelGGL(jacobi_v_kernel, dim3((nmax + 31) / 32, bv.n), dim3(256), 0, s, bv);
+      HCTM_HIP(hipGetLastError());
+    }
+  }
+  for (size_t i = 0; i < glob.size(); i += kMaxSmall) {
     SmallBatch b;
     b.n = 0;
-    for (size_t j = i; j < probs.size() && b.n < kMaxSmall; ++j) {
-      if (probs[j].n > 1024) throw Error(1, "jacobi: too many columns");
-      b.p[b.n++] = probs[j];
-    }
+    for (size_t j = i; j < glob.size() && b.n < kMaxSmall; ++j) b.p[b.n++] = glob[j];
     hipLaunchKernelGGL(jacobi_kernel, dim3(b.n), dim3(NT), 0, s, b);
     HCTM_HIP(hipGetLastError());
   }

@@ -13,6 +13,7 @@ struct SmallProb {
   int* info;       // Cholesky: first failing pivot (1-based) or 0; Jacobi: sweeps (<0: no convergence)
   double* sv;      // Jacobi: singular values, descending
   int* perm;       // Jacobi: column of the j-th largest
+  double* vlog;    // Jacobi: rotation log (jacobi_log_doubles), enables the LDS kernel with V
   int flags;       // Cholesky: 1 = factor the unit-diagonal Gram D^-1 G D^-1 (D = sqrt diag G);
                    // Rinv is then D^-1 R^-1 (sv must point to n doubles of scratch)
 };
@@ -57,6 +58,7 @@ void sumsq(const double* p, size_t n, double* out, double* part, hipStream_t s);
 void scale_inv(double* p, size_t n, const double* nrm, hipStream_t s);
 void chol_inv(const std::vector<SmallProb>& probs, hipStream_t s);
 void jacobi(const std::vector<SmallProb>& probs, hipStream_t s);
+size_t jacobi_log_doubles(int n, int max_sweeps);
 void gather_cols(const double* X, int ldx, const int* perm, const double* sv, int m, int k, double* U, int ldu,
                  hipStream_t s);
 void select_states(const SelectArgs& a, hipStream_t s);

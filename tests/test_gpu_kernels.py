@@ -39,6 +39,22 @@ def test_gemm_matches_numpy(hc, M, N, K, ta, tb):
     assert np.abs(out - ref).max() <= 1e-14 * scale
 
 
+@pytest.mark.parametrize("M,N,K,ta", [(126, 126, 2600, 1), (60, 84, 5000, 0), (7, 300, 3000, 1)])
+def test_gemm_split_k(hc, M, N, K, ta):
+    """Small outputs with a long reduction are split over K (Gram matrices)."""
+    rng = np.random.default_rng(M + N + K)
+    A = rng.standard_normal((K, M) if ta else (M, K))
+    B = rng.standard_normal((K, N))
+    C0 = rng.standard_normal((M, N))
+    ref = 2.0 * (A.T if ta else A) @ B + 0.25 * C0
+    dA, dB, dC = _dev(A), _dev(B), _dev(C0)
+    scratch = torch.zeros(64 * M * N, dtype=torch.float64, device="cuda")
+    hc.dev_gemm(dA, dB, dC, M, N, K, A.shape[1], N, N, ta, 0, 2.0, 0.25, None, scratch)
+    torch.cuda.synchronize()
+    assert np.abs(scratch.cpu().numpy()).max() > 0.0  # the split path was taken
+    assert np.abs(dC.cpu().numpy() - ref).max() <= 1e-13 * np.sqrt(K) * 8
+
+
 def test_gemm_leading_dims_and_zero_k(hc):
     rng = np.random.default_rng(3)
     A = rng.standard_normal((70, 90))
@@ -72,7 +88,7 @@ def test_copy_is_exact_permutation(hc, shape, perm):
     assert np.array_equal(dY.cpu().numpy().reshape(Y.shape), Y)
 
 
-@pytest.mark.parametrize("n", [1, 12, 100, 142, 160])
+@pytest.mark.parametrize("n", [1, 12, 33, 64, 65, 100, 142, 160, 200])
 def test_cholesky_inverse(hc, n):
     rng = np.random.default_rng(n)
     X = rng.standard_normal((n + 30, n))
@@ -102,8 +118,15 @@ def test_jacobi_svd(hc, m, n):
     sv = torch.zeros(n, dtype=torch.float64, device="cuda")
     perm = torch.zeros(n, dtype=torch.int32, device="cuda")
     sw = torch.zeros(4, dtype=torch.int32, device="cuda")
-    hc.dev_jacobi(dX, m, n, 1.1e-16 * m, 60, sv, perm, sw)
+    V = torch.zeros((n, n), dtype=torch.float64, device="cuda") if m == n else None
+    vlog = torch.zeros(max(1, hc.jacobi_log_doubles(n, 60)), dtype=torch.float64, device="cuda") if m == n else None
+    hc.dev_jacobi(dX, m, n, 1.1e-16 * m, 60, sv, perm, sw, V, vlog)
     torch.cuda.synchronize()
+    if V is not None:
+        Vh = V.cpu().numpy()
+        # accumulated rotations: orthogonality to a few hundred ulps
+        assert np.abs(Vh.T @ Vh - np.eye(n)).max() < 1e-12
+        assert np.abs(X @ Vh - dX.cpu().numpy()).max() < 1e-12
     assert int(sw[0].item()) >= 0
     got = sv.cpu().numpy()
     assert np.all(np.diff(got) <= 0)
