@@ -148,44 +148,43 @@ def _select(svals, sec, chi, tau):
     return order[:k]
 
 
-def left_move(env, a, chi, tau=1e-12, par_q=None):
-    """One left move on a 1x1 cell (updates C1, T4, C4 in place).
+def _cut_parities(legpar_w, legpar_n, legpar_e, legpar_s, par_q):
+    """Parity of every index of the four cuts (chi leg major, q leg minor)."""
+    return [((p[:, None] + par_q[None, :]) % 2).reshape(-1) for p in (legpar_w, legpar_n, legpar_e, legpar_s)]
 
-    Returns a record with the merged spectrum of M (descending, divided by its
-    largest value) and the kept sector sizes (k_even, k_odd).
+
+def cut_projectors(Q1, Q2, Q3, Q4, chi, tau, pars=None):
+    """Projector pair for the cut between Q1 (above) and Q4 (below).
+
+    Q1..Q4 are the four enlarged corners around the cut (see `quadrants`);
+    pars = [pW, pN, pE, pS] gives the parity of every index of the west,
+    north, east and south cuts in the Z2 form (None: one sector).
+    Per sector: H_u = Q1 Q2, H_d = Q3 Q4, M = H_d H_u = W S V^T, and over the
+    merged spectrum the kept states give P_a = H_u V S^-1/2 (cut x k, taken
+    by objects below the cut) and P_b = S^-1/2 W^T H_d (k x cut, above).
+    Returns (Pa[chiW, q, k], Pb[k, chiW, q], (k_even, k_odd), record).
     """
-    z2 = env.par is not None
-    Q1, Q2, Q3, Q4 = quadrants(env, a)
+    z2 = pars is not None
     chiW, q = Q1.shape[0], Q1.shape[1]
-    chiE = Q2.shape[2]
     m1, m2, m3, m4 = (_as_matrix(Q) for Q in (Q1, Q2, Q3, Q4))
-    nW, nE = chiW * q, chiE * q
-
+    nW = chiW * q
     if z2:
-        top, right, bottom, left = env.par
-        pW = ((left[:, None] + par_q[None, :]) % 2).reshape(-1)
-        pN = ((top[:, None] + par_q[None, :]) % 2).reshape(-1)
-        pE = ((right[:, None] + par_q[None, :]) % 2).reshape(-1)
+        pW, pN, pE, pS = pars
         sectors = [0, 1]
     else:
         pW = np.zeros(nW, dtype=np.int64)
         pN = np.zeros(m1.shape[1], dtype=np.int64)
-        pE = np.zeros(nE, dtype=np.int64)
+        pE = np.zeros(m2.shape[1], dtype=np.int64)
+        pS = np.zeros(m3.shape[1], dtype=np.int64)
         sectors = [0]
 
     # per sector: H_u = Q1 Q2, H_d = Q3 Q4, M = H_d H_u and its SVD
     parts = []
     for P in sectors:
-        iW, iN, iE = (np.nonzero(p == P)[0] for p in (pW, pN, pE))
+        iW, iN, iE, iS = (np.nonzero(p == P)[0] for p in (pW, pN, pE, pS))
         if len(iW) == 0 or len(iE) == 0:
             continue
         Hu = m1[np.ix_(iW, iN)] @ m2[np.ix_(iN, iE)]
-        pS = None
-        if z2:
-            pS = ((bottom[:, None] + par_q[None, :]) % 2).reshape(-1)
-        else:
-            pS = np.zeros(m3.shape[1], dtype=np.int64)
-        iS = np.nonzero(pS == P)[0]
         Hd = m3[np.ix_(iE, iS)] @ m4[np.ix_(iS, iW)]
         M = Hd @ Hu
         Wm, s, Vt = np.linalg.svd(M)
@@ -212,30 +211,53 @@ def left_move(env, a, chi, tau=1e-12, par_q=None):
         Pa[np.ix_(iW, np.arange(col, col + kP))] = (Hu @ Vt[idx].T) * isq[None, :]
         Pb[np.ix_(np.arange(col, col + kP), iW)] = (Wm[:, idx].T @ Hd) * isq[:, None]
         col += kP
+    order = np.argsort(-svals)
+    spec = svals[order] / svals[order[0]]
+    rec = {"spectrum": spec, "kept": (kcount[0], kcount[1]) if z2 else (knew, 0)}
+    return Pa.reshape(chiW, q, knew), Pb.reshape(knew, chiW, q), kcount, rec
 
-    Pa3 = Pa.reshape(chiW, q, knew)
-    Pb3 = Pb.reshape(knew, chiW, q)
-    C1, T1, C2, T2, C3, T3, C4, T4 = env.t
+
+def absorb_c1(Pb3, C1, T1):
+    """C1'[k,r] = Pb[k,(c,u)] C1[c,x] T1[x,u,r]."""
+    return np.tensordot(Pb3, np.tensordot(C1, T1, ([1], [0])), ([1, 2], [0, 1]))
+
+
+def absorb_t4(Pa3, T4, a, Pb3):
+    """T4'[i,r,j] = Pa[(c,u),j] T4[w,l,c] a[u,l,e,r] Pb[i,(w,e)]."""
     td = np.tensordot
-    # C1'[k,r] = Pb[k,(c,u)] C1[c,x] T1[x,u,r]
-    C1n = td(Pb3, td(C1, T1, ([1], [0])), ([1, 2], [0, 1]))
-    # T4'[i,r,j] = Pa[(c,u),j] T4[w,l,c] a[u,l,e,r] Pb[i,(w,e)]
     z = td(td(T4, Pa3, ([2], [0])), a, ([1, 2], [1, 0]))       # [w,j,e,r]
-    T4n = td(Pb3, z, ([1, 2], [0, 2])).transpose(0, 2, 1)       # [i,j,r] -> [i,r,j]
-    # C4'[r,j] = T3[r,u,x] C4[x,c] Pa[(c,u),j]
-    C4n = td(td(T3, C4, ([2], [0])), Pa3, ([2, 1], [0, 1]))
-    env.t[0] = _fro_normalise(C1n)
-    env.t[7] = _fro_normalise(T4n)
-    env.t[6] = _fro_normalise(C4n)
+    return td(Pb3, z, ([1, 2], [0, 2])).transpose(0, 2, 1)      # [i,j,r] -> [i,r,j]
+
+
+def absorb_c4(T3, C4, Pa3):
+    """C4'[r,j] = T3[r,u,x] C4[x,c] Pa[(c,u),j]."""
+    return np.tensordot(np.tensordot(T3, C4, ([2], [0])), Pa3, ([2, 1], [0, 1]))
+
+
+def left_move(env, a, chi, tau=1e-12, par_q=None):
+    """One left move on a 1x1 cell (updates C1, T4, C4 in place).
+
+    Returns a record with the merged spectrum of M (descending, divided by its
+    largest value) and the kept sector sizes (k_even, k_odd).
+    """
+    z2 = env.par is not None
+    Q1, Q2, Q3, Q4 = quadrants(env, a)
+    pars = None
+    if z2:
+        top, right, bottom, left = env.par
+        pars = _cut_parities(left, top, right, bottom, par_q)
+    Pa3, Pb3, kcount, rec = cut_projectors(Q1, Q2, Q3, Q4, chi, tau, pars)
+    C1, T1, C2, T2, C3, T3, C4, T4 = env.t
+    env.t[0] = _fro_normalise(absorb_c1(Pb3, C1, T1))
+    env.t[7] = _fro_normalise(absorb_t4(Pa3, T4, a, Pb3))
+    env.t[6] = _fro_normalise(absorb_c4(T3, C4, Pa3))
     if z2:
         newpar = np.array([0] * kcount[0] + [1] * kcount[1], dtype=np.int64)
         env.par[3] = newpar
         env.t[0] = _mask(env.t[0], [newpar, top])
         env.t[7] = _mask(env.t[7], [newpar, par_q, newpar])
         env.t[6] = _mask(env.t[6], [bottom, newpar])
-    order = np.argsort(-svals)
-    spec = svals[order] / svals[order[0]]
-    return {"spectrum": spec, "kept": (kcount[0], kcount[1]) if z2 else (knew, 0)}
+    return rec
 
 
 # move order of one iteration: left, right, top, bottom as rotations of the frame
@@ -406,9 +428,16 @@ def rho1_of(eps, A):
     return rho / np.trace(rho)
 
 
-def rho2_h_of(env, A):
-    """Two-site RDM of a horizontal bond, rho[(s1 s2), (s1' s2')], trace one."""
+def rho2_h_of(env, A, env_r=None, A_r=None):
+    """Two-site RDM of a horizontal bond, rho[(s1 s2), (s1' s2')], trace one.
+
+    The left site is A with environment env; the right site is A_r with
+    environment env_r (both default to the left ones, the 1x1 cell).
+    """
+    env_r = env if env_r is None else env_r
+    A_r = A if A_r is None else A_r
     C1, T1, C2, T2, C3, T3, C4, T4 = env.t
+    _, R1, R2, U2, R3, U3, _, _ = env_r.t
     d, D = A.shape[0], A.shape[1]
 
     def split(T, leg):
@@ -416,7 +445,8 @@ def rho2_h_of(env, A):
         sh[leg:leg + 1] = [D, D]
         return T.reshape(sh)
 
-    T1s, T2s, T3s, T4s = split(T1, 1), split(T2, 1), split(T3, 1), split(T4, 1)
+    T1s, T3s, T4s = split(T1, 1), split(T3, 1), split(T4, 1)
+    R1s, U2s, U3s = split(R1, 1), split(U2, 1), split(U3, 1)
     # left half: C1 T1 / T4 [site 1] / C4 T3, open towards site 2.
     # ket legs u,l,e,g and bra legs v,m,f,h of site 1; y, z the top and
     # bottom environment bonds that continue to the right half.
@@ -428,11 +458,11 @@ def rho2_h_of(env, A):
     left = np.einsum("pysegtfh,zefp->ysgthz", k2, bl, **EINSUM)
     # right half: T1 C2 / [site 2] T2 / T3 C3; g, h are the ket and bra
     # legs shared by the two sites.
-    tr = np.einsum("yuvx,xc->yuvc", T1s, C2, **EINSUM)
-    rgt = np.einsum("yuvc,crwp->yuvrwp", tr, T2s, **EINSUM)
-    k1 = np.einsum("yuvrwp,suger->yvwpsge", rgt, A, **EINSUM)
-    k2 = np.einsum("yvwpsge,tvhfw->ypsgethf", k1, A, **EINSUM)
-    br = np.einsum("px,xefz->pefz", C3, T3s, **EINSUM)
+    tr = np.einsum("yuvx,xc->yuvc", R1s, R2, **EINSUM)
+    rgt = np.einsum("yuvc,crwp->yuvrwp", tr, U2s, **EINSUM)
+    k1 = np.einsum("yuvrwp,suger->yvwpsge", rgt, A_r, **EINSUM)
+    k2 = np.einsum("yvwpsge,tvhfw->ypsgethf", k1, A_r, **EINSUM)
+    br = np.einsum("px,xefz->pefz", R3, U3s, **EINSUM)
     right = np.einsum("ypsgethf,pefz->ysgthz", k2, br, **EINSUM)
     rho = np.einsum("yagbhz,ycgdhz->acbd", left, right, **EINSUM)
     rho = rho.reshape(d * d, d * d)
