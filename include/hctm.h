@@ -32,6 +32,13 @@
  * Tensor layout: A is d x D x D x D x D, legs [s, u, l, d, r] (physical,
  * up, left, down, right).  A joined bra-ket leg index is K = k*D + kbar
  * (ket index k, bra index kbar).
+ *
+ * Unit cell: the network may repeat an Lx x Ly cell of different tensors
+ * A(x, y), x = 0..Lx-1 to the right, y = 0..Ly-1 downwards (periodic).  The
+ * paper's method is stated for one tensor; on a cell every site keeps its own
+ * corners and edges, and a move sweeps the columns (or rows) of the cell in
+ * turn, each cut taking its projectors from the 2 x 2 block of sites next to
+ * it.  With Lx = Ly = 1 (the default) this is the one-site algorithm.
  */
 #ifndef HCTM_H
 #define HCTM_H
@@ -57,6 +64,7 @@ enum { CTM_FORM_Z2 = 0, CTM_FORM_DENSE = 1 };
 
 typedef struct {
   int form;                    /* CTM_FORM_Z2 (default) or CTM_FORM_DENSE */
+  int Lx, Ly;                  /* unit cell, each in [1, 4] (default 1 x 1) */
   const double* boundary;      /* host, D*D vector b[K] tracing the open boundary
                                   legs of the initial 3x3 patch; NULL selects
                                   b = sum_k |k k> (the open boundary).  In the Z2
@@ -77,45 +85,49 @@ int ctm_opts_default(ctm_opts* o);
 int ctm_workspace_size(int d, int D, int chi, const ctm_opts* o, size_t* bytes);
 
 /*
- * Create a context: copies A (host, d*D^4 doubles, legs [s,u,l,d,r]), forms
- * the double layer in the eigenbasis of the swap (Sec. II B) and the initial
- * environment of boundary dimension D^2 (the 3x3 patch traced with the
- * boundary vector).  chi >= 1 is the boundary dimension kept after each
- * truncation (Sec. II A).  Requires d >= 1, 1 <= D <= 8, finite A.
+ * Create a context: copies A (host, Lx*Ly tensors of d*D^4 doubles, legs
+ * [s,u,l,d,r], site (x, y) at offset (y*Lx + x)*d*D^4), forms the double
+ * layers in the eigenbasis of the swap (Sec. II B) and the initial
+ * environment of boundary dimension D^2 (every site's 3x3 patch traced with
+ * the boundary vector).  chi >= 1 is the boundary dimension kept after each
+ * truncation (Sec. II A).  Requires 1 <= d <= 16, 1 <= D <= 8,
+ * 1 <= chi <= 4096, finite A; *out is NULL on failure.
  */
 int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, const ctm_opts* o);
 
 /*
  * Run n_iter CTMRG iterations; one iteration is a left, right, top and
- * bottom move, each absorbing a column or row of double-layer tensors and
- * truncating the grown bond back to chi with per-sector SVD projectors.
- * After every iteration the corner spectra are compared with the previous
- * ones (see ctm_converged).
+ * bottom move, each absorbing the columns or rows of double-layer tensors of
+ * the cell and truncating every grown bond back to chi with per-sector SVD
+ * projectors.  After every iteration the corner spectra are compared with the
+ * previous ones (see ctm_converged).
  */
 int ctm_step(ctm_ctx* c, int n_iter);
 
 /*
- * delta = max over the four corners of || s_new - s_old ||_2, s the singular
- * values of a corner divided by their sum and padded with zeros to chi,
- * between the last two iterations (+inf before the second).  converged =
- * (delta < tol).  Synchronises.
+ * delta = max over the four corners of every site of || s_new - s_old ||_2,
+ * s the singular values of a corner divided by their sum and padded with
+ * zeros to chi, between the last two iterations (+inf before the second).
+ * converged = (delta < tol).  Synchronises.
  */
 int ctm_converged(ctm_ctx* c, double tol, int* converged, double* delta);
 
-/* One-site reduced density matrix rho[s][s'] (host, d*d), trace one. */
-int ctm_rdm_1site(ctm_ctx* c, double* rho);
+/* One-site reduced density matrix rho[s][s'] of site (x, y) of the cell
+ * (host, d*d), trace one. */
+int ctm_rdm_1site(ctm_ctx* c, int x, int y, double* rho);
 
 /*
  * Two-site RDM of a nearest-neighbour pair, rho[(s1 s2)][(s1' s2')] (host,
- * d^4), trace one.  dir 0: horizontal pair (left site first), 1: vertical
- * pair (upper site first).  In the Z2 form both RDMs are symmetric by
- * construction: only the even (symmetric) part of an impurity couples to the
- * even environment, and pairs of odd (antisymmetric) parts are combined so
- * that the result is invariant under the joint ket-bra swap.
+ * d^4), trace one.  dir 0: the pair (x, y)-(x+1, y), 1: the pair
+ * (x, y)-(x, y+1), the first site first.  In the Z2 form both RDMs are
+ * symmetric by construction: only the even (symmetric) part of an impurity
+ * couples to the even environment, and pairs of odd (antisymmetric) parts are
+ * combined so that the result is invariant under the joint ket-bra swap.
  */
-int ctm_rdm_2site(ctm_ctx* c, int dir, double* rho);
+int ctm_rdm_2site(ctm_ctx* c, int x, int y, int dir, double* rho);
 
-/* E = Tr(rho_h h) + Tr(rho_v h) for a bond operator h (host, d^2 x d^2). */
+/* E = mean over the sites of Tr(rho_h h) + Tr(rho_v h), for a bond operator
+ * h (host, d^2 x d^2). */
 int ctm_energy(ctm_ctx* c, const double* h, double* e);
 
 /* Release everything; NULL is accepted. */
@@ -126,29 +138,37 @@ const char* ctm_last_error(const ctm_ctx* c);
 
 /* ---- diagnostics used by the tests ------------------------------------ */
 
-/* One-site environment with the centre removed (Sec. III A), back in the
- * plain basis, normalised so that <eps, a> = 1; host, D^8 doubles ordered
- * [U, L, Dn, R] with joined indices K = k*D + kbar. */
-int ctm_env_epsilon(ctm_ctx* c, double* eps);
+/* One-site environment of site (x, y) with the centre removed (Sec. III A),
+ * back in the plain basis, normalised so that <eps, a> = 1; host, D^8
+ * doubles ordered [U, L, Dn, R] with joined indices K = k*D + kbar. */
+int ctm_env_epsilon(ctm_ctx* c, int x, int y, double* eps);
 
-/* Hermitian symmetry error S_err = ||e - e^dag|| / ||e + e^dag|| (Sec. III A). */
+/* Hermitian symmetry error S_err = ||e - e^dag|| / ||e + e^dag|| (Sec. III A),
+ * the largest over the sites. */
 int ctm_s_err(ctm_ctx* c, double* s_err);
 
-/* ln of the partition function per site, kappa = Z11 Z00 / (Z10 Z01). */
+/* ln of the partition function per site, kappa = Z11 Z00 / (Z10 Z01);
+ * 1 x 1 cell only (CTM_E_ARG otherwise). */
 int ctm_log_kappa(ctm_ctx* c, double* ln_kappa);
 
-/* Number of moves run so far. */
-int ctm_num_moves(ctm_ctx* c, int* n);
+/* Number of truncations run so far (one per cut: a move of an Lx x Ly cell
+ * truncates Lx*Ly cuts). */
+int ctm_num_records(ctm_ctx* c, int* n);
 
 /*
- * Record of move m (0-based): the kept singular values of the decomposed
- * matrix, merged over both sectors in descending order and divided by the
- * largest, and the kept sector sizes.  s: host array of at least cap doubles.
+ * Record of truncation m (0-based, in the order run): the kept singular
+ * values of the decomposed matrix, merged over both sectors in descending
+ * order and divided by the largest, and the kept sector sizes.  s: host array
+ * of at least cap doubles.  where (may be NULL): 3 ints, the frame of the
+ * move (0 left, 1 top, 2 right, 3 bottom), the column swept and the row of
+ * the cut, in the coordinates of that frame.
  */
-int ctm_move_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, int* k_odd);
+int ctm_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, int* k_odd, int* where);
 
-/* Current boundary bond of side 0..3 (top, right, bottom, left): its sizes. */
-int ctm_sector_dims(ctm_ctx* c, int side, int* chi_even, int* chi_odd);
+/* Current boundary bond on side 0..3 (top, right, bottom, left) of site
+ * (x, y): the bond of the edge tensor's first leg (T1's left, T2's up, T3's
+ * right, T4's down leg), its even and odd sizes. */
+int ctm_sector_dims(ctm_ctx* c, int x, int y, int side, int* chi_even, int* chi_odd);
 
 /* GPU seconds of the last ctm_step call per phase of the moves:
  * t[0] enlarged corners, t[1] half-system products and M, t[2] truncated SVD

@@ -21,7 +21,7 @@ ERROR_NAMES = {1: "CTM_E_ARG", 2: "CTM_E_NOMEM", 3: "CTM_E_HIP", 4: "CTM_E_NUMER
 EXPORTS = [
     "ctm_opts_default", "ctm_workspace_size", "ctm_init", "ctm_step", "ctm_converged",
     "ctm_rdm_1site", "ctm_rdm_2site", "ctm_energy", "ctm_free", "ctm_last_error",
-    "ctm_env_epsilon", "ctm_s_err", "ctm_log_kappa", "ctm_num_moves", "ctm_move_record",
+    "ctm_env_epsilon", "ctm_s_err", "ctm_log_kappa", "ctm_num_records", "ctm_record",
     "ctm_sector_dims", "ctm_timing", "ctm_gemm_stats",
     "hctm_dev_gemm", "hctm_dev_copy", "hctm_dev_chol_inv", "hctm_dev_jacobi", "hctm_dev_jacobi_log_doubles",
 ]
@@ -30,6 +30,8 @@ EXPORTS = [
 class CtmOpts(ctypes.Structure):
     _fields_ = [
         ("form", ctypes.c_int),
+        ("Lx", ctypes.c_int),
+        ("Ly", ctypes.c_int),
         ("boundary", ctypes.POINTER(ctypes.c_double)),
         ("svd_rel_cutoff", ctypes.c_double),
         ("svd_iters", ctypes.c_int),
@@ -67,17 +69,17 @@ def lib():
         "ctm_init": ([P(vp), dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(CtmOpts)], ctypes.c_int),
         "ctm_step": ([ctx, ctypes.c_int], ctypes.c_int),
         "ctm_converged": ([ctx, ctypes.c_double, ip, dp], ctypes.c_int),
-        "ctm_rdm_1site": ([ctx, dp], ctypes.c_int),
-        "ctm_rdm_2site": ([ctx, ctypes.c_int, dp], ctypes.c_int),
+        "ctm_rdm_1site": ([ctx, ctypes.c_int, ctypes.c_int, dp], ctypes.c_int),
+        "ctm_rdm_2site": ([ctx, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp], ctypes.c_int),
         "ctm_energy": ([ctx, dp, dp], ctypes.c_int),
         "ctm_free": ([ctx], None),
         "ctm_last_error": ([ctx], ctypes.c_char_p),
-        "ctm_env_epsilon": ([ctx, dp], ctypes.c_int),
+        "ctm_env_epsilon": ([ctx, ctypes.c_int, ctypes.c_int, dp], ctypes.c_int),
         "ctm_s_err": ([ctx, dp], ctypes.c_int),
         "ctm_log_kappa": ([ctx, dp], ctypes.c_int),
-        "ctm_num_moves": ([ctx, ip], ctypes.c_int),
-        "ctm_move_record": ([ctx, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip], ctypes.c_int),
-        "ctm_sector_dims": ([ctx, ctypes.c_int, ip, ip], ctypes.c_int),
+        "ctm_num_records": ([ctx, ip], ctypes.c_int),
+        "ctm_record": ([ctx, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, ip], ctypes.c_int),
+        "ctm_sector_dims": ([ctx, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ip], ctypes.c_int),
         "ctm_timing": ([ctx, dp, ctypes.c_int, ip], ctypes.c_int),
         "ctm_gemm_stats": ([ctx, dp, dp, P(ctypes.c_longlong), ctypes.c_int], ctypes.c_int),
         "hctm_dev_gemm": ([vp, vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.c_double, vp, vp,
@@ -115,34 +117,53 @@ def _torch():
     return torch
 
 
-def workspace_size(d, D, chi, form="z2"):
+def workspace_size(d, D, chi, form="z2", Lx=1, Ly=1):
     o = CtmOpts()
     _check(lib().ctm_opts_default(ctypes.byref(o)))
     o.form = CTM_FORM_Z2 if form == "z2" else CTM_FORM_DENSE
+    o.Lx, o.Ly = Lx, Ly
     n = ctypes.c_size_t()
     _check(lib().ctm_workspace_size(d, D, chi, ctypes.byref(o), ctypes.byref(n)))
     return n.value
 
 
-class CTMRG:
-    """One CTMRG solve on the GPU (Z2 or plain form), 1x1 unit cell.
+def _cell_array(A):
+    """(Ly, Lx, d, D, D, D, D) array from one tensor, a dict {(x, y): A} or such an array."""
+    if isinstance(A, dict):
+        Lx = 1 + max(x for x, _ in A)
+        Ly = 1 + max(y for _, y in A)
+        if len(A) != Lx * Ly:
+            raise ValueError("the dict must hold every site (x, y) of the cell")
+        A = np.stack([np.stack([np.asarray(A[(x, y)], dtype=np.float64) for x in range(Lx)]) for y in range(Ly)])
+    A = np.asarray(A, dtype=np.float64)
+    if A.ndim == 5:
+        A = A[None, None]
+    if A.ndim != 7 or len(set(A.shape[3:])) != 1 or A.shape[4] != A.shape[3]:
+        raise ValueError("A must have shape (d, D, D, D, D) or (Ly, Lx, d, D, D, D, D)")
+    return np.ascontiguousarray(A)
 
-    A: real array (d, D, D, D, D), legs [s, u, l, d, r].  Device memory is a
-    torch uint8 tensor handed to the library as its workspace; work runs on
-    torch's current HIP stream.
+
+class CTMRG:
+    """One CTMRG solve on the GPU (Z2 or plain form).
+
+    A: one real tensor (d, D, D, D, D), legs [s, u, l, d, r], for the 1x1
+    cell, or the tensors of an Lx x Ly cell as an array (Ly, Lx, d, D, D, D,
+    D) or a dict {(x, y): tensor}.  Device memory is a torch uint8 tensor
+    handed to the library as its workspace; work runs on torch's current HIP
+    stream.
     """
 
     def __init__(self, A, chi, form="z2", boundary=None, svd_rel_cutoff=1e-12, svd_iters=12, seed=0x5EED,
                  stream=None, torch_workspace=True, profile=False):
         torch = _torch()
-        A = np.ascontiguousarray(A, dtype=np.float64)
-        if A.ndim != 5 or len(set(A.shape[1:])) != 1:
-            raise ValueError("A must have shape (d, D, D, D, D)")
-        self.d, self.D, self.chi = A.shape[0], A.shape[1], int(chi)
+        A = _cell_array(A)
+        self.Ly, self.Lx = A.shape[0], A.shape[1]
+        self.d, self.D, self.chi = A.shape[2], A.shape[3], int(chi)
         self.form = form
         o = CtmOpts()
         _check(lib().ctm_opts_default(ctypes.byref(o)))
         o.form = CTM_FORM_Z2 if form == "z2" else CTM_FORM_DENSE
+        o.Lx, o.Ly = self.Lx, self.Ly
         o.svd_rel_cutoff = svd_rel_cutoff
         o.svd_iters = svd_iters
         o.seed = seed
@@ -201,15 +222,15 @@ class CTMRG:
                 break
         return self
 
-    def rdm1(self):
+    def rdm1(self, x=0, y=0):
         rho = np.zeros((self.d, self.d))
-        _check(lib().ctm_rdm_1site(self._ctx, _dptr(rho)), self._ctx)
+        _check(lib().ctm_rdm_1site(self._ctx, x, y, _dptr(rho)), self._ctx)
         return rho
 
-    def rdm2(self, direction="h"):
+    def rdm2(self, direction="h", x=0, y=0):
         n = self.d * self.d
         rho = np.zeros((n, n))
-        _check(lib().ctm_rdm_2site(self._ctx, 0 if direction == "h" else 1, _dptr(rho)), self._ctx)
+        _check(lib().ctm_rdm_2site(self._ctx, x, y, 0 if direction == "h" else 1, _dptr(rho)), self._ctx)
         return rho
 
     def energy(self, h):
@@ -218,10 +239,10 @@ class CTMRG:
         _check(lib().ctm_energy(self._ctx, _dptr(h), ctypes.byref(e)), self._ctx)
         return e.value
 
-    def epsilon(self):
+    def epsilon(self, x=0, y=0):
         q = self.D * self.D
         eps = np.zeros((q, q, q, q))
-        _check(lib().ctm_env_epsilon(self._ctx, _dptr(eps)), self._ctx)
+        _check(lib().ctm_env_epsilon(self._ctx, x, y, _dptr(eps)), self._ctx)
         return eps
 
     def s_err(self):
@@ -234,25 +255,27 @@ class CTMRG:
         _check(lib().ctm_log_kappa(self._ctx, ctypes.byref(s)), self._ctx)
         return s.value
 
-    def num_moves(self):
+    def num_records(self):
         n = ctypes.c_int()
-        _check(lib().ctm_num_moves(self._ctx, ctypes.byref(n)), self._ctx)
+        _check(lib().ctm_num_records(self._ctx, ctypes.byref(n)), self._ctx)
         return n.value
 
-    def move_record(self, m):
+    def record(self, m):
         cap = 8192
         s = np.zeros(cap)
         n, ke, ko = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(lib().ctm_move_record(self._ctx, m, _dptr(s), cap, ctypes.byref(n), ctypes.byref(ke),
-                                     ctypes.byref(ko)), self._ctx)
-        return {"spectrum": s[: n.value].copy(), "kept": (ke.value, ko.value)}
+        where = (ctypes.c_int * 3)()
+        _check(lib().ctm_record(self._ctx, m, _dptr(s), cap, ctypes.byref(n), ctypes.byref(ke), ctypes.byref(ko),
+                                where), self._ctx)
+        return {"spectrum": s[: n.value].copy(), "kept": (ke.value, ko.value), "frame": where[0],
+                "column": where[1], "row": where[2]}
 
     def records(self):
-        return [self.move_record(m) for m in range(self.num_moves())]
+        return [self.record(m) for m in range(self.num_records())]
 
-    def sector_dims(self, side):
+    def sector_dims(self, side, x=0, y=0):
         e, o = ctypes.c_int(), ctypes.c_int()
-        _check(lib().ctm_sector_dims(self._ctx, side, ctypes.byref(e), ctypes.byref(o)), self._ctx)
+        _check(lib().ctm_sector_dims(self._ctx, x, y, side, ctypes.byref(e), ctypes.byref(o)), self._ctx)
         return e.value, o.value
 
     def gemm_stats(self, reset=False):

@@ -51,6 +51,10 @@ hctm::Options to_options(const ctm_opts* o, int D) {
   if (!o) o = &def;
   if (o->form != CTM_FORM_Z2 && o->form != CTM_FORM_DENSE) throw hctm::Error(CTM_E_ARG, "unknown form");
   opt.form = o->form == CTM_FORM_Z2 ? 0 : 1;
+  if (o->Lx < 1 || o->Lx > hctm::kMaxCell || o->Ly < 1 || o->Ly > hctm::kMaxCell)
+    throw hctm::Error(CTM_E_ARG, "Lx and Ly must be in [1, 4]");
+  opt.Lx = o->Lx;
+  opt.Ly = o->Ly;
   if (!(o->svd_rel_cutoff >= 0.0) || o->svd_rel_cutoff >= 1.0) throw hctm::Error(CTM_E_ARG, "svd_rel_cutoff out of range");
   opt.tau = o->svd_rel_cutoff;
   if (o->svd_iters < 1 || o->svd_iters > 1000) throw hctm::Error(CTM_E_ARG, "svd_iters out of range");
@@ -90,6 +94,8 @@ int ctm_opts_default(ctm_opts* o) {
   if (!o) return CTM_E_ARG;
   std::memset(o, 0, sizeof(*o));
   o->form = CTM_FORM_Z2;
+  o->Lx = 1;
+  o->Ly = 1;
   o->boundary = nullptr;
   o->svd_rel_cutoff = 1e-12;
   o->svd_iters = 12;
@@ -111,10 +117,10 @@ int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, const ctm_op
   return guarded(nullptr, [&] {
     if (!out || !A) throw hctm::Error(CTM_E_ARG, "NULL argument");
     check_sizes(d, D, chi);
-    const long long n = (long long)d * D * D * D * D;
+    hctm::Options opt = to_options(o, D);
+    const long long n = (long long)d * D * D * D * D * opt.Lx * opt.Ly;
     for (long long i = 0; i < n; ++i)
       if (!std::isfinite(A[i])) throw hctm::Error(CTM_E_NUMERIC, "A has a non-finite entry");
-    hctm::Options opt = to_options(o, D);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) throw hctm::Error(CTM_E_HIP, "no HIP device");
     std::unique_ptr<ctm_ctx> c(new ctm_ctx);
@@ -147,20 +153,26 @@ int ctm_converged(ctm_ctx* c, double tol, int* converged, double* delta) {
   });
 }
 
-int ctm_rdm_1site(ctm_ctx* c, double* rho) {
+static void check_site(const ctm_ctx* c, int x, int y) {
+  if (x < 0 || y < 0 || x >= c->ctm->Lx() || y >= c->ctm->Ly()) throw hctm::Error(CTM_E_ARG, "site outside the cell");
+}
+
+int ctm_rdm_1site(ctm_ctx* c, int x, int y, double* rho) {
   if (!c) return CTM_E_ARG;
   return guarded(c, [&] {
     if (!rho) throw hctm::Error(CTM_E_ARG, "rho is NULL");
-    c->ctm->rdm1(rho);
+    check_site(c, x, y);
+    c->ctm->rdm1(x, y, rho);
   });
 }
 
-int ctm_rdm_2site(ctm_ctx* c, int dir, double* rho) {
+int ctm_rdm_2site(ctm_ctx* c, int x, int y, int dir, double* rho) {
   if (!c) return CTM_E_ARG;
   return guarded(c, [&] {
     if (!rho) throw hctm::Error(CTM_E_ARG, "rho is NULL");
     if (dir != 0 && dir != 1) throw hctm::Error(CTM_E_ARG, "dir must be 0 or 1");
-    c->ctm->rdm2(dir, rho);
+    check_site(c, x, y);
+    c->ctm->rdm2(x, y, dir, rho);
   });
 }
 
@@ -176,11 +188,12 @@ void ctm_free(ctm_ctx* c) { delete c; }
 
 const char* ctm_last_error(const ctm_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
 
-int ctm_env_epsilon(ctm_ctx* c, double* eps) {
+int ctm_env_epsilon(ctm_ctx* c, int x, int y, double* eps) {
   if (!c) return CTM_E_ARG;
   return guarded(c, [&] {
     if (!eps) throw hctm::Error(CTM_E_ARG, "eps is NULL");
-    c->ctm->epsilon_plain(eps);
+    check_site(c, x, y);
+    c->ctm->epsilon_plain(x, y, eps);
   });
 }
 
@@ -200,32 +213,38 @@ int ctm_log_kappa(ctm_ctx* c, double* lk) {
   });
 }
 
-int ctm_num_moves(ctm_ctx* c, int* n) {
+int ctm_num_records(ctm_ctx* c, int* n) {
   if (!c || !n) return CTM_E_ARG;
   *n = (int)c->ctm->records().size();
   return CTM_OK;
 }
 
-int ctm_move_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, int* k_odd) {
+int ctm_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, int* k_odd, int* where) {
   if (!c) return CTM_E_ARG;
   return guarded(c, [&] {
     const auto& r = c->ctm->records();
-    if (m < 0 || m >= (int)r.size()) throw hctm::Error(CTM_E_ARG, "move index out of range");
+    if (m < 0 || m >= (int)r.size()) throw hctm::Error(CTM_E_ARG, "record index out of range");
     const auto& rec = r[m];
     const int ns = (int)rec.spectrum.size();
     if (n) *n = ns;
     if (k_even) *k_even = rec.k_even;
     if (k_odd) *k_odd = rec.k_odd;
+    if (where) {
+      where[0] = rec.frame;
+      where[1] = rec.column;
+      where[2] = rec.row;
+    }
     if (s)
       for (int i = 0; i < ns && i < cap; ++i) s[i] = rec.spectrum[i];
   });
 }
 
-int ctm_sector_dims(ctm_ctx* c, int side, int* chi_even, int* chi_odd) {
+int ctm_sector_dims(ctm_ctx* c, int x, int y, int side, int* chi_even, int* chi_odd) {
   if (!c) return CTM_E_ARG;
   return guarded(c, [&] {
     if (side < 0 || side > 3) throw hctm::Error(CTM_E_ARG, "side must be 0..3");
-    const hctm::Leg l = c->ctm->side(side);
+    check_site(c, x, y);
+    const hctm::Leg l = c->ctm->bond(x, y, side);
     if (chi_even) *chi_even = l.e;
     if (chi_odd) *chi_odd = l.o;
   });

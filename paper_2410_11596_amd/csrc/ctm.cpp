@@ -1,24 +1,36 @@
-// Directional CTMRG on a 1x1 unit cell in the eigenbasis of the bra-ket swap.
+// Directional CTMRG on an Lx x Ly unit cell in the eigenbasis of the bra-ket
+// swap.
 //
-// Frames.  The eight environment tensors are kept in slots
+// Frames.  Every site (x, y) of the cell (x to the right, y downwards,
+// periodic) has eight environment tensors in slots
 //   0 C1[d,r]  1 T1[l,d,r]  2 C2[l,d]  3 T2[u,l,d]  4 C3[u,l]  5 T3[r,u,l]
 //   6 C4[r,u]  7 T4[d,r,u]
-// (legs counter-clockwise).  Turning the lattice by a quarter turn (old right
-// leg becomes the up leg) maps slot i to slot i-2, so a move in any direction
-// is the left move of a rotated frame r: its C1 is slot 2r, its T1 slot 2r+1,
-// and the double layer is a_r with legs (j - r) mod 4 of a.  Moves are run in
-// the order left (r=0), right (2), top (1), bottom (3).
+// (legs counter-clockwise; C1 is the corner up-left of the site, T1 the edge
+// above it, ...).  Turning the lattice by a quarter turn (old right leg
+// becomes the up leg) maps slot i to slot i-2, so a move in any direction is
+// the left move of a rotated frame r: its C1 is slot 2r, its T1 slot 2r+1,
+// and the double layer is a_r with legs (j - r) mod 4 of a.  In frame r the
+// frame's right is the cell direction (3 - r) mod 4 and its down (2 - r) mod 4
+// (0 up, 1 left, 2 down, 3 right).  Moves are run in the order left (r=0),
+// right (2), top (1), bottom (3).
 //
-// One left move (frame r), all products being block-diagonal GEMMs per parity
-// sector:
-//   quadrants  Q_j[W|N] = C1 T1 T4 a of frame j, for j = r..r+3 (a quadrant
-//              is recomputed only after one of its tensors changed);
+// One left move of frame r sweeps the frame columns X = 0 .. LX-1.  At column
+// X, for every frame row Y, the cut between rows Y and Y+1 takes its
+// projectors from the 2x2 block of sites with top-left (X, Y); all products
+// are block-diagonal GEMMs per parity sector:
+//   quadrants  Q1 = C1 T1 T4 a of frame r at (X, Y), Q2 the same of frame r+1
+//              at (X+1, Y), Q3 of frame r+2 at (X+1, Y+1), Q4 of frame r+3 at
+//              (X, Y+1) (a quadrant is recomputed only after one of its
+//              tensors changed);
 //   halves     H_u = Q1 Q2, H_d = Q3 Q4, M = H_d H_u;
 //   SVD        per sector, truncated to chi over the merged spectrum;
-//   projectors P_a = H_u V S^-1/2, P_b = S^-1/2 W^T H_d;
-//   renormalise C1' = P_b (C1 T1), T4' = P_b (T4 a P_a), C4' = (T3 C4) P_a,
-//              each divided by its Frobenius norm.
-// Tensors are stored as fused-sector block-diagonal matrices (blocks.hpp).
+//   projectors P_a(Y) = H_u V S^-1/2, P_b(Y) = S^-1/2 W^T H_d.
+// Then the left environment of column X+1 is replaced:
+//   C1(X+1,Y) = P_b(Y-1) C1 T1,  T4(X+1,Y) = P_b(Y) T4 a P_a(Y-1),
+//   C4(X+1,Y) = T3 C4 P_a(Y)     (C1, T1, T4, a, T3, C4 of site (X, Y)),
+// each divided by its Frobenius norm.  With Lx = Ly = 1 this is the one-site
+// move.  Tensors are stored as fused-sector block-diagonal matrices
+// (blocks.hpp).
 #include "ctm.hpp"
 
 #include <algorithm>
@@ -33,16 +45,38 @@ constexpr int kJacobiSweeps = 40;
 }
 
 // ------------------------------------------------------------- memory ----
-Ctm::Ctm(CountTag, int d, int D, int chi) : d_(d), D_(D), chi_(chi) {
+Ctm::Ctm(CountTag, int d, int D, int chi, int Lx, int Ly) : d_(d), D_(D), chi_(chi), Lx_(Lx), Ly_(Ly) {
   q_ = D * D;
   cc_ = std::max(chi, q_);
+  ns_ = Lx * Ly;
 }
 
 size_t Ctm::workspace_bytes(int d, int D, int chi, const Options& o) {
-  (void)o;
-  Ctm c(CountTag{}, d, D, chi);
+  Ctm c(CountTag{}, d, D, chi, o.Lx, o.Ly);
   c.plan_memory(true);
   return c.ar_.used + 256;
+}
+
+int Ctm::site(int x, int y) const {
+  x = ((x % Lx_) + Lx_) % Lx_;
+  y = ((y % Ly_) + Ly_) % Ly_;
+  return y * Lx_ + x;
+}
+
+// cell offset (x, y) of the frame-r offset (X, Y)
+static void to_cell(int r, int X, int Y, int& x, int& y) {
+  switch (((r % 4) + 4) % 4) {
+    case 0: x = X; y = Y; break;
+    case 1: x = -Y; y = X; break;
+    case 2: x = -X; y = -Y; break;
+    default: x = Y; y = -X; break;
+  }
+}
+
+int Ctm::site_of(int r, int X, int Y) const {
+  int x, y;
+  to_cell(r, X, Y, x, y);
+  return site(x, y);
 }
 
 void Ctm::plan_memory(bool counting) {
@@ -57,23 +91,29 @@ void Ctm::plan_memory(bool counting) {
   tab_c_ = ar_.take(2 * q);
   tabT_idx_ = ti(2 * q);
   tabT_c_ = ar_.take(2 * q);
-  A_ = ar_.take((size_t)d_ * D_ * D_ * D_ * D_);
+  const int ns = ns_;
+  A_ = ar_.take((size_t)ns * d_ * D_ * D_ * D_ * D_);
   b_ = ar_.take((size_t)q);
-  a_plain_ = ar_.take((size_t)q4);
+  a_plain_.assign(ns, nullptr);
+  for (int s = 0; s < ns; ++s) a_plain_[s] = ar_.take((size_t)q4);
   plain_tmp_ = ar_.take((size_t)q4);
   plain_tmp2_ = ar_.take((size_t)q4);
-  for (int r = 0; r < 4; ++r) {
-    a_rot_[r].p = ar_.take((size_t)q4);
-    a_rot_[r].capacity = q4;
+  a_rot_.assign(4 * ns, BT());
+  for (BT& t : a_rot_) {
+    t.p = ar_.take((size_t)q4);
+    t.capacity = q4;
   }
-  for (int i = 0; i < 8; ++i) {
+  env_.assign(8 * ns, BT());
+  for (int i = 0; i < 8 * ns; ++i) {
     const long long n = (i % 2 == 0) ? cc * cc : cc * cc * q;
     env_[i].p = ar_.take((size_t)n);
     env_[i].capacity = n;
   }
-  for (int j = 0; j < 4; ++j) {
-    quad_[j].p = ar_.take((size_t)(ncap * ncap));
-    quad_[j].capacity = ncap * ncap;
+  quad_.assign(4 * ns, BT());
+  quad_ok_.assign(4 * ns, 0);
+  for (BT& t : quad_) {
+    t.p = ar_.take((size_t)(ncap * ncap));
+    t.capacity = ncap * ncap;
   }
   big_cap_ = ncap * ncap;
   big1_ = ar_.take((size_t)big_cap_);
@@ -87,10 +127,16 @@ void Ctm::plan_memory(bool counting) {
     t->capacity = ncap * ncap;
   }
   proj_cap_ = ncap * cc;
-  Pa_.p = ar_.take((size_t)proj_cap_);
-  Pa_.capacity = proj_cap_;
-  Pb_.p = ar_.take((size_t)proj_cap_);
-  Pb_.capacity = proj_cap_;
+  const int ncut = std::max(Lx_, Ly_);
+  Pa_.assign(ncut, BT());
+  Pb_.assign(ncut, BT());
+  for (int Y = 0; Y < ncut; ++Y) {
+    Pa_[Y].p = ar_.take((size_t)proj_cap_);
+    Pa_[Y].capacity = proj_cap_;
+    Pb_[Y].p = ar_.take((size_t)proj_cap_);
+    Pb_[Y].capacity = proj_cap_;
+  }
+  kg_.assign(4 * kMaxCell * kMaxCell, std::array<int, 2>{0, 0});
   for (int P = 0; P < 2; ++P) {
     SvdSector& S = sec_[P];
     S.Qr = ar_.take((size_t)(ncap * lcap));
@@ -115,11 +161,11 @@ void Ctm::plan_memory(bool counting) {
   misc_ = ar_.take(64);
   kdev_ = ti(16);
   part_ = ar_.take(2048);
-  cspec_ = ar_.take((size_t)(4 * cc));
-  cspec_old_ = ar_.take((size_t)(4 * cc));
-  csv_ = ar_.take((size_t)(8 * cc));
-  cperm_ = ti(8 * cc);
-  cmat_ = ar_.take((size_t)(8 * cc * cc));
+  cspec_ = ar_.take((size_t)(ns * 4 * cc));
+  cspec_old_ = ar_.take((size_t)(ns * 4 * cc));
+  csv_ = ar_.take((size_t)(ns * 8 * cc));
+  cperm_ = ti(ns * 8 * cc);
+  cmat_ = ar_.take((size_t)(ns * 8 * cc * cc));
   eps_.p = ar_.take((size_t)q4);
   eps_.capacity = q4;
   halves_cap_ = cc * cc * q;
@@ -128,7 +174,7 @@ void Ctm::plan_memory(bool counting) {
   const long long d4 = (long long)d_ * d_ * d_ * d_;
   dots_ = ar_.take((size_t)(2 * d4 + 16));
   dpart_ = ar_.take((size_t)(64 * kMaxDots));
-  rho_ = ar_.take((size_t)(2 * d4 + 16));
+  rho_ = ar_.take((size_t)(2 * ns * d4 + 16));
   hdev_ = ar_.take((size_t)(d4 + 16));
   gemm_scratch_cap_ = std::max<long long>(1 << 20, 24LL * lcap * lcap);
   gemm_scratch_ = ar_.take((size_t)gemm_scratch_cap_);
@@ -140,6 +186,9 @@ Ctm::Ctm(const double* A_host, int d, int D, int chi, const Options& o, hipStrea
     : d_(d), D_(D), chi_(chi), opt_(o) {
   q_ = D * D;
   cc_ = std::max(chi, q_);
+  Lx_ = o.Lx;
+  Ly_ = o.Ly;
+  ns_ = Lx_ * Ly_;
   const int qo = (D * D - D) / 2;
   lq_ = opt_.form == 0 ? Leg{q_ - qo, qo} : Leg{q_, 0};
   if (stream) {
@@ -290,7 +339,8 @@ void Ctm::setup(const double* A_host) {
   HCTM_HIP(hipMemcpy(tab_c_, tc.data(), sizeof(double) * 2 * q, hipMemcpyHostToDevice));
   HCTM_HIP(hipMemcpy(tabT_idx_, tti.data(), sizeof(int) * 2 * q, hipMemcpyHostToDevice));
   HCTM_HIP(hipMemcpy(tabT_c_, ttc.data(), sizeof(double) * 2 * q, hipMemcpyHostToDevice));
-  HCTM_HIP(hipMemcpy(A_, A_host, sizeof(double) * d_ * D * D * D * D, hipMemcpyHostToDevice));
+  const long long nA = (long long)d_ * D * D * D * D;
+  HCTM_HIP(hipMemcpy(A_, A_host, sizeof(double) * nA * ns_, hipMemcpyHostToDevice));
   std::vector<double> b(q, 0.0);
   if (opt_.boundary.empty()) {
     for (int k = 0; k < D; ++k) b[k * D + k] = 1.0;
@@ -299,55 +349,67 @@ void Ctm::setup(const double* A_host) {
   }
   HCTM_HIP(hipMemcpy(b_, b.data(), sizeof(double) * q, hipMemcpyHostToDevice));
 
-  // double layer in the rotated basis, a[U,L,Dn,R] = sum_s A[s] (x) A[s]
-  DLArgs g;
-  g.A = A_;
-  g.out = a_plain_;
-  g.tab_idx = tab_idx_;
-  g.tab_c = tab_c_;
-  g.d = d_;
-  g.D = D;
-  g.npairs = d_;
-  for (int s = 0; s < d_; ++s) {
-    g.ket[s] = s;
-    g.bra[s] = s;
-    g.w[s] = 1.0;
-  }
-  double_layer_basis(g, st_);
+  // double layer of every site in the rotated basis, a[U,L,Dn,R] = sum_s A[s] (x) A[s],
+  // packed once per frame
   const long long s0[4] = {(long long)q * q * q, (long long)q * q, (long long)q, 1};
   std::vector<CopyJob> jobs;
-  for (int r = 0; r < 4; ++r) {
-    a_rot_[r].L = Layout({lq_, lq_, lq_, lq_}, 2);
-    long long st[4];
-    for (int j = 0; j < 4; ++j) st[j] = s0[(j - r + 4) % 4];
-    plan_pack(a_plain_, st, a_rot_[r], true, jobs);
-  }
-  launch_copies(jobs);
-
-  // traced boundary: C1, T1 of every frame
-  for (int r = 0; r < 4; ++r) {
-    init_env(a_plain_, q, r, b_, tab_idx_, tab_c_, plain_tmp_, plain_tmp2_, st_);
-    BT& C = env_[2 * r];
-    BT& T = env_[2 * r + 1];
-    C.L = Layout({lq_, lq_}, 1);
-    T.L = Layout({lq_, lq_, lq_}, 1);
-    const long long sc[2] = {q, 1};
-    const long long stt[3] = {(long long)q * q, q, 1};
-    plan_pack(plain_tmp_, sc, C, true, jobs);    // init_env wrote C to plain_tmp_
-    plan_pack(plain_tmp2_, stt, T, true, jobs);   // and T to plain_tmp2_
+  for (int st = 0; st < ns_; ++st) {
+    DLArgs g;
+    g.A = A_ + st * nA;
+    g.out = a_plain_[st];
+    g.tab_idx = tab_idx_;
+    g.tab_c = tab_c_;
+    g.d = d_;
+    g.D = D;
+    g.npairs = d_;
+    for (int s = 0; s < d_; ++s) {
+      g.ket[s] = s;
+      g.bra[s] = s;
+      g.w[s] = 1.0;
+    }
+    double_layer_basis(g, st_);
+    for (int r = 0; r < 4; ++r) {
+      BT& t = a_rot(st, r);
+      t.L = Layout({lq_, lq_, lq_, lq_}, 2);
+      long long str[4];
+      for (int j = 0; j < 4; ++j) str[j] = s0[(j - r + 4) % 4];
+      plan_pack(a_plain_[st], str, t, true, jobs);
+    }
     launch_copies(jobs);
   }
-  for (int i = 0; i < 8; ++i) normalise(env_[i]);
-  for (int s = 0; s < 4; ++s) side_[s] = lq_;
+
+  // traced boundary: in frame r, C1 of a site is the double layer at frame
+  // offset (-1, -1) with its frame-up and frame-left legs traced, T1 the one
+  // at (0, -1) with its frame-up leg traced
+  for (int src = 0; src < ns_; ++src) {
+    const int sx = src % Lx_, sy = src / Lx_;
+    for (int r = 0; r < 4; ++r) {
+      init_env(a_plain_[src], q, r, b_, tab_idx_, tab_c_, plain_tmp_, plain_tmp2_, st_);
+      // the sites that see src at these offsets
+      int cx, cy, ex, ey;
+      to_cell(r, -1, -1, cx, cy);
+      to_cell(r, 0, -1, ex, ey);
+      BT& C = env(site(sx - cx, sy - cy), 2 * r);
+      BT& T = env(site(sx - ex, sy - ey), 2 * r + 1);
+      C.L = Layout({lq_, lq_}, 1);
+      T.L = Layout({lq_, lq_, lq_}, 1);
+      const long long sc[2] = {q, 1};
+      const long long stt[3] = {(long long)q * q, q, 1};
+      plan_pack(plain_tmp_, sc, C, true, jobs);    // init_env wrote C to plain_tmp_
+      plan_pack(plain_tmp2_, stt, T, true, jobs);   // and T to plain_tmp2_
+      launch_copies(jobs);
+    }
+  }
+  for (BT& t : env_) normalise(t);
   sync();
 }
 
 // ------------------------------------------------------------ quadrant ----
-// quad_[j] = C1 T1 T4 a of frame j as a matrix [w d | t r].
-void Ctm::quadrant(int j) {
-  BT& C = env_[(2 * j) % 8];
-  BT& T1 = env_[(2 * j + 1) % 8];
-  BT& T4 = env_[(2 * j + 7) % 8];
+// quad(s, o) = C1 T1 T4 a of frame o at site s as a matrix [w d | t r].
+void Ctm::quadrant(int s, int j) {
+  BT& C = env(s, 2 * j);
+  BT& T1 = env(s, 2 * j + 1);
+  BT& T4 = env(s, 2 * j + 7);
   BT X{Layout(), mid1_, mid_cap_};
   contract(C, T1, X);                                    // [c | u t]
   BT T4s{Layout(), mid2_, mid_cap_};
@@ -357,8 +419,8 @@ void Ctm::quadrant(int j) {
   BT Yp{Layout(), big2_, big_cap_};
   permute(Y, Yp, {0, 3, 2, 1}, 2);                       // [w t | u l]
   BT Qp{Layout(), big1_, big_cap_};
-  contract(Yp, a_rot_[j], Qp);                           // [w t | d r]
-  permute(Qp, quad_[j], {0, 2, 1, 3}, 2);                // [w d | t r]
+  contract(Yp, a_rot(s, j), Qp);                         // [w t | d r]
+  permute(Qp, quad(s, j), {0, 2, 1, 3}, 2);              // [w d | t r]
 }
 
 // ---------------------------------------------------------------- SVD ----
@@ -430,7 +492,9 @@ void Ctm::orth(std::vector<SvdSector*>& ss, bool ql, int passes) {
   }
 }
 
-void Ctm::truncated_svd(BT& M, int chi) {
+// kg[2]: guess of the kept states per sector (in/out, 0 = none); salt makes
+// the random start blocks differ between cuts.
+void Ctm::truncated_svd(BT& M, int chi, int* kg_io, uint64_t salt) {
   for (int attempt = 0; attempt < 4; ++attempt) {
     std::vector<SvdSector*> sub, all;
     for (int P = 0; P < 2; ++P) {
@@ -442,7 +506,7 @@ void Ctm::truncated_svd(BT& M, int chi) {
         S.trusted = 0;
         continue;
       }
-      int kg = S.kg > 0 ? S.kg : chi;
+      int kg = kg_io[P] > 0 ? kg_io[P] : chi;
       kg = std::min(kg, S.n);
       const int p = std::max(32, kg / 2);
       S.l = std::min<int>(std::min(S.n, kg + p), l_cap_);
@@ -456,7 +520,7 @@ void Ctm::truncated_svd(BT& M, int chi) {
     // subspace iteration (both sectors batched)
     if (!sub.empty()) {
       for (SvdSector* S : sub) {
-        const uint64_t seed = opt_.seed * 0x9E3779B97F4A7C15ull + (move_count_ << 4) + (S == &sec_[1] ? 1 : 0) +
+        const uint64_t seed = opt_.seed * 0x9E3779B97F4A7C15ull + (salt << 4) + (S == &sec_[1] ? 1 : 0) +
                               ((uint64_t)attempt << 2);
         random_fill(S->Y, (size_t)S->n * S->l, seed, st_);
       }
@@ -567,7 +631,7 @@ void Ctm::truncated_svd(BT& M, int chi) {
       if (S.n == 0) continue;
       if (host_k_[3 + 2 * P] < 0) throw Error(4, "Jacobi SVD did not converge");
       if (!S.direct && S.k >= S.trusted) {
-        S.kg = std::min(S.n, S.k + 64);
+        kg_io[P] = std::min(S.n, S.k + 64);
         redo = true;
       }
     }
@@ -612,7 +676,7 @@ void Ctm::truncated_svd(BT& M, int chi) {
   launch_gemms(g);
   for (int P = 0; P < 2; ++P) {
     SvdSector& S = sec_[P];
-    S.kg = S.k;
+    kg_io[P] = S.k;
     if (S.direct) {
       S.W = S.Ub;
       S.V = S.Vb;
@@ -624,180 +688,211 @@ void Ctm::truncated_svd(BT& M, int chi) {
 }
 
 // ---------------------------------------------------------------- move ----
+void Ctm::mark(int phase) {
+  const size_t i = ev_phase_.size();
+  if (ev_.size() <= i) {
+    hipEvent_t e;
+    HCTM_HIP(hipEventCreate(&e));
+    ev_.push_back(e);
+  }
+  HCTM_HIP(hipEventRecord(ev_[i], st_));
+  ev_phase_.push_back(phase);
+}
+
 void Ctm::move(int r) {
-  auto mark = [&](int i) {
-    if ((int)ev_.size() <= i) {
-      hipEvent_t e;
-      HCTM_HIP(hipEventCreate(&e));
-      ev_.push_back(e);
+  const int LX = (r % 2 == 0) ? Lx_ : Ly_;
+  const int LY = (r % 2 == 0) ? Ly_ : Lx_;
+  for (int X = 0; X < LX; ++X) {
+    mark(0);
+    for (int Y = 0; Y < LY; ++Y) {
+      const int ss[4] = {site_of(r, X, Y), site_of(r, X + 1, Y), site_of(r, X + 1, Y + 1), site_of(r, X, Y + 1)};
+      for (int i = 0; i < 4; ++i) {
+        const int o = (r + i) % 4;
+        if (!quad_ok_[ss[i] * 4 + o]) {
+          quadrant(ss[i], o);
+          quad_ok_[ss[i] * 4 + o] = 1;
+        }
+      }
     }
-    HCTM_HIP(hipEventRecord(ev_[i], st_));
-  };
-  const int e0 = ev_index_;
-  mark(e0);
-  for (int i = 0; i < 4; ++i) {
-    const int j = (r + i) % 4;
-    if (!quad_ok_[j]) {
-      quadrant(j);
-      quad_ok_[j] = true;
+    for (int Y = 0; Y < LY; ++Y) {
+      mark(1);
+      BT& Q1 = quad(site_of(r, X, Y), r);
+      BT& Q2 = quad(site_of(r, X + 1, Y), r + 1);
+      BT& Q3 = quad(site_of(r, X + 1, Y + 1), r + 2);
+      BT& Q4 = quad(site_of(r, X, Y + 1), r + 3);
+      {
+        std::vector<GemmDesc> g;
+        plan_contract(Q1, Q2, Hu_, 1.0, 0.0, g);
+        plan_contract(Q3, Q4, Hd_, 1.0, 0.0, g);
+        launch_gemms(g);
+        plan_contract(Hd_, Hu_, M_, 1.0, 0.0, g);
+        launch_gemms(g);
+      }
+      mark(2);
+      int* kg = kg_[(r * kMaxCell + X) * kMaxCell + Y].data();
+      truncated_svd(M_, chi_, kg, (uint64_t)records_.size());
+      mark(3);
+
+      // projectors of this cut
+      const Leg kn{sec_[0].k, sec_[1].k};
+      const Leg lW = Q1.L.leg[0];
+      BT& Pa = Pa_[Y];
+      BT& Pb = Pb_[Y];
+      Pa.L = Layout({lW, lq_, kn}, 2);
+      Pb.L = Layout({kn, lW, lq_}, 1);
+      if (Pa.L.size > proj_cap_ || Pb.L.size > proj_cap_) throw Error(2, "projector capacity");
+      std::vector<GemmDesc> g;
+      for (int P = 0; P < 2; ++P) {
+        SvdSector& S = sec_[P];
+        if (S.k == 0) continue;
+        const int nW = (int)Hu_.L.rows[P], nE = (int)Hu_.L.cols[P];
+        GemmDesc d{};
+        d.A = Hu_.p + Hu_.L.off[P];
+        d.B = S.V;
+        d.C = Pa.p + Pa.L.off[P];
+        d.M = nW;
+        d.N = S.k;
+        d.K = nE;
+        d.lda = nE;
+        d.ldb = S.k;
+        d.ldc = S.k;
+        d.alpha = 1.0;
+        d.cscale = S.isq;
+        g.push_back(d);
+        GemmDesc e{};
+        e.A = S.W;
+        e.B = Hd_.p + Hd_.L.off[P];
+        e.C = Pb.p + Pb.L.off[P];
+        e.M = S.k;
+        e.N = nW;
+        e.K = nE;
+        e.lda = S.k;
+        e.ldb = nW;
+        e.ldc = nW;
+        e.ta = 1;
+        e.alpha = 1.0;
+        e.rscale = S.isq;
+        g.push_back(e);
+      }
+      launch_gemms(g);
+
+      // record: the kept spectra were copied to the host at the truncation sync
+      MoveRecord rec;
+      rec.k_even = opt_.form == 0 ? kn.e : kn.e + kn.o;
+      rec.k_odd = opt_.form == 0 ? kn.o : 0;
+      rec.frame = r;
+      rec.column = X;
+      rec.row = Y;
+      for (int P = 0; P < 2; ++P)
+        for (int i = 0; i < sec_[P].k; ++i) rec.spectrum.push_back(host_d_[2048 * P + i]);
+      std::sort(rec.spectrum.begin(), rec.spectrum.end(), [](double a, double b) { return a > b; });
+      const double s0 = rec.spectrum.empty() ? 1.0 : rec.spectrum[0];
+      for (double& v : rec.spectrum) v /= s0;
+      records_.push_back(std::move(rec));
     }
-  }
-  mark(e0 + 1);
-  BT& Q1 = quad_[r];
-  BT& Q2 = quad_[(r + 1) % 4];
-  BT& Q3 = quad_[(r + 2) % 4];
-  BT& Q4 = quad_[(r + 3) % 4];
-  {
-    std::vector<GemmDesc> g;
-    plan_contract(Q1, Q2, Hu_, 1.0, 0.0, g);
-    plan_contract(Q3, Q4, Hd_, 1.0, 0.0, g);
-    launch_gemms(g);
-    plan_contract(Hd_, Hu_, M_, 1.0, 0.0, g);
-    launch_gemms(g);
-  }
-  mark(e0 + 2);
-  truncated_svd(M_, chi_);
-  mark(e0 + 3);
 
-  // projectors
-  const Leg kn{sec_[0].k, sec_[1].k};
-  const Leg lW = Q1.L.leg[0];
-  Pa_.L = Layout({lW, lq_, kn}, 2);
-  Pb_.L = Layout({kn, lW, lq_}, 1);
-  if (Pa_.L.size > proj_cap_ || Pb_.L.size > proj_cap_) throw Error(2, "projector capacity");
-  {
-    std::vector<GemmDesc> g;
-    for (int P = 0; P < 2; ++P) {
-      SvdSector& S = sec_[P];
-      if (S.k == 0) continue;
-      const int nW = (int)Hu_.L.rows[P], nE = (int)Hu_.L.cols[P];
-      GemmDesc d{};
-      d.A = Hu_.p + Hu_.L.off[P];
-      d.B = S.V;
-      d.C = Pa_.p + Pa_.L.off[P];
-      d.M = nW;
-      d.N = S.k;
-      d.K = nE;
-      d.lda = nE;
-      d.ldb = S.k;
-      d.ldc = S.k;
-      d.alpha = 1.0;
-      d.cscale = S.isq;
-      g.push_back(d);
-      GemmDesc e{};
-      e.A = S.W;
-      e.B = Hd_.p + Hd_.L.off[P];
-      e.C = Pb_.p + Pb_.L.off[P];
-      e.M = S.k;
-      e.N = nW;
-      e.K = nE;
-      e.lda = S.k;
-      e.ldb = nW;
-      e.ldc = nW;
-      e.ta = 1;
-      e.alpha = 1.0;
-      e.rscale = S.isq;
-      g.push_back(e);
+    // renormalisation: the left environment of column X+1 from column X.  All
+    // sources are read before their own site's tensors are overwritten; for
+    // LX > 1 sources and targets are different sites.
+    for (int Y = 0; Y < LY; ++Y) {
+      const int s = site_of(r, X, Y), t = site_of(r, X + 1, Y);
+      BT& Pa_up = Pa_[(Y - 1 + LY) % LY];
+      BT& Pb_up = Pb_[(Y - 1 + LY) % LY];
+      BT& Pa_dn = Pa_[Y];
+      BT& Pb_dn = Pb_[Y];
+      BT& C1 = env(s, 2 * r);
+      BT& T1 = env(s, 2 * r + 1);
+      BT& T3 = env(s, 2 * r + 5);
+      BT& C4 = env(s, 2 * r + 6);
+      BT& T4 = env(s, 2 * r + 7);
+      BT X1{Layout(), mid1_, mid_cap_};
+      contract(C1, T1, X1);                      // [c | u t]
+      BT X2{Layout(), mid2_, mid_cap_};
+      permute(X1, X2, {0, 1, 2}, 2);             // [c u | t]
+      BT T3s{Layout(), mid1_, mid_cap_};
+      permute(T3, T3s, {0, 1, 2}, 2);            // [r u | x]
+      BT Z{Layout(), mid3_, mid_cap_};
+      contract(T3s, C4, Z);                      // [r u | c]
+      BT Zp{Layout(), mid1_, mid_cap_};
+      permute(Z, Zp, {0, 2, 1}, 1);              // [r | c u]
+      BT T4s{Layout(), mid3_, mid_cap_};
+      permute(T4, T4s, {0, 1, 2}, 2);            // [w l | c]
+      BT Pas{Layout(), big2_, big_cap_};
+      permute(Pa_up, Pas, {0, 1, 2}, 1);         // [c | u k]
+      BT G{Layout(), big1_, big_cap_};
+      contract(T4s, Pas, G);                     // [w l | u k]
+      BT Gp{Layout(), big2_, big_cap_};
+      permute(G, Gp, {0, 3, 2, 1}, 2);           // [w k | u l]
+      BT H{Layout(), big1_, big_cap_};
+      contract(Gp, a_rot(s, r), H);              // [w k | e r]
+      BT Hp{Layout(), big2_, big_cap_};
+      permute(H, Hp, {0, 2, 3, 1}, 2);           // [w e | r k]
+      // the old C1, C4, T4 of site s are no longer read
+      BT& C1n = env(t, 2 * r);
+      BT& C4n = env(t, 2 * r + 6);
+      BT& T4n = env(t, 2 * r + 7);
+      contract(Pb_up, X2, C1n);                  // [k | t]
+      contract(Zp, Pa_dn, C4n);                  // [r | k]
+      contract(Pb_dn, Hp, T4n);                  // [k | r k]
+      normalise(C1n);
+      normalise(C4n);
+      normalise(T4n);
+      quad_ok_[t * 4 + r] = 0;
+      quad_ok_[t * 4 + (r + 3) % 4] = 0;
     }
-    launch_gemms(g);
+    mark(-1);
   }
-
-  // renormalisation
-  BT& C1 = env_[(2 * r) % 8];
-  BT& T1 = env_[(2 * r + 1) % 8];
-  BT& T3 = env_[(2 * r + 5) % 8];
-  BT& C4 = env_[(2 * r + 6) % 8];
-  BT& T4 = env_[(2 * r + 7) % 8];
-  BT X{Layout(), mid1_, mid_cap_};
-  contract(C1, T1, X);                       // [c | u t]
-  BT X2{Layout(), mid2_, mid_cap_};
-  permute(X, X2, {0, 1, 2}, 2);              // [c u | t]
-  BT T3s{Layout(), mid1_, mid_cap_};
-  permute(T3, T3s, {0, 1, 2}, 2);            // [r u | x]
-  BT Z{Layout(), mid3_, mid_cap_};
-  contract(T3s, C4, Z);                      // [r u | c]
-  BT Zp{Layout(), mid1_, mid_cap_};
-  permute(Z, Zp, {0, 2, 1}, 1);              // [r | c u]
-  BT T4s{Layout(), mid3_, mid_cap_};
-  permute(T4, T4s, {0, 1, 2}, 2);            // [w l | c]
-  BT Pas{Layout(), big2_, big_cap_};
-  permute(Pa_, Pas, {0, 1, 2}, 1);           // [c | u k]
-  BT G{Layout(), big1_, big_cap_};
-  contract(T4s, Pas, G);                     // [w l | u k]
-  BT Gp{Layout(), big2_, big_cap_};
-  permute(G, Gp, {0, 3, 2, 1}, 2);           // [w k | u l]
-  BT H{Layout(), big1_, big_cap_};
-  contract(Gp, a_rot_[r], H);                // [w k | e r]
-  BT Hp{Layout(), big2_, big_cap_};
-  permute(H, Hp, {0, 2, 3, 1}, 2);           // [w e | r k]
-  // the old C1, C4, T4 are no longer read: write the new ones in place
-  contract(Pb_, X2, C1);                     // [k | t]
-  contract(Zp, Pa_, C4);                     // [r | k]
-  contract(Pb_, Hp, T4);                     // [k | r k]
-  normalise(C1);
-  normalise(C4);
-  normalise(T4);
-  side_[(3 + r) % 4] = kn;
-  quad_ok_[r] = false;
-  quad_ok_[(r + 3) % 4] = false;
-  mark(e0 + 4);
-  ev_index_ += 5;
-
-  // record: the kept spectra were copied to the host at the truncation sync
-  MoveRecord rec;
-  rec.k_even = opt_.form == 0 ? kn.e : kn.e + kn.o;
-  rec.k_odd = opt_.form == 0 ? kn.o : 0;
-  for (int P = 0; P < 2; ++P)
-    for (int i = 0; i < sec_[P].k; ++i) rec.spectrum.push_back(host_d_[2048 * P + i]);
-  std::sort(rec.spectrum.begin(), rec.spectrum.end(), [](double a, double b) { return a > b; });
-  const double s0 = rec.spectrum.empty() ? 1.0 : rec.spectrum[0];
-  for (double& v : rec.spectrum) v /= s0;
-  records_.push_back(std::move(rec));
-  ++move_count_;
-  eps_ok_ = false;
+  eps_site_ = -1;
 }
 
 // --------------------------------------------------- corner spectra ----
 void Ctm::corner_spectra() {
   std::vector<SmallProb> jp;
-  SpecArgs a{};
-  const int slots[4] = {0, 2, 4, 6};
+  std::vector<SpecArgs> sa(ns_);
   double* mat = cmat_;
-  for (int c = 0; c < 4; ++c) {
-    BT& C = env_[slots[c]];
-    for (int P = 0; P < 2; ++P) {
-      const int m = (int)C.L.rows[P], n = (int)C.L.cols[P];
-      a.sv[2 * c + P] = csv_ + (2 * c + P) * cc_;
-      a.nsv[2 * c + P] = (m > 0 && n > 0) ? n : 0;
-      if (m == 0 || n == 0) continue;
-      HCTM_HIP(hipMemcpyAsync(mat, C.p + C.L.off[P], sizeof(double) * m * n, hipMemcpyDeviceToDevice, st_));
-      SmallProb p{};
-      p.a = mat;
-      p.m = m;
-      p.n = n;
-      p.lda = n;
-      p.rel = 1.1e-16 * std::max(m, 8);
-      p.max_sweeps = 40;
-      p.info = kdev_ + 8;
-      p.sv = csv_ + (2 * c + P) * cc_;
-      p.perm = cperm_ + (2 * c + P) * cc_;
-      jp.push_back(p);
-      mat += (long long)cc_ * cc_;
+  for (int st = 0; st < ns_; ++st) {
+    SpecArgs& a = sa[st];
+    for (int c = 0; c < 4; ++c) {
+      BT& C = env(st, 2 * c);
+      for (int P = 0; P < 2; ++P) {
+        const int m = (int)C.L.rows[P], n = (int)C.L.cols[P];
+        const long long slot = (long long)(st * 8 + 2 * c + P) * cc_;
+        a.sv[2 * c + P] = csv_ + slot;
+        a.nsv[2 * c + P] = (m > 0 && n > 0) ? n : 0;
+        if (m == 0 || n == 0) continue;
+        HCTM_HIP(hipMemcpyAsync(mat, C.p + C.L.off[P], sizeof(double) * m * n, hipMemcpyDeviceToDevice, st_));
+        SmallProb p{};
+        p.a = mat;
+        p.m = m;
+        p.n = n;
+        p.lda = n;
+        p.rel = 1.1e-16 * std::max(m, 8);
+        p.max_sweeps = 40;
+        p.info = kdev_ + 8;
+        p.sv = csv_ + slot;
+        p.perm = cperm_ + slot;
+        jp.push_back(p);
+        mat += (long long)cc_ * cc_;
+      }
     }
   }
   jacobi(jp, st_);
   std::swap(cspec_, cspec_old_);
-  a.spec_new = cspec_;
-  a.spec_old = cspec_old_;
-  a.len = cc_;
-  a.have_old = have_old_spec_ ? 1 : 0;
-  a.delta = misc_ + 16;
-  corner_spectra_delta(a, st_);
+  for (int st = 0; st < ns_; ++st) {
+    SpecArgs& a = sa[st];
+    a.spec_new = cspec_ + (long long)st * 4 * cc_;
+    a.spec_old = cspec_old_ + (long long)st * 4 * cc_;
+    a.len = cc_;
+    a.have_old = have_old_spec_ ? 1 : 0;
+    a.accumulate = st > 0 ? 1 : 0;
+    a.delta = misc_ + 16;
+    corner_spectra_delta(a, st_);
+  }
   have_old_spec_ = true;
 }
 
 void Ctm::step(int n_iter) {
-  ev_index_ = 0;
+  ev_phase_.clear();
   static const int order[4] = {0, 2, 1, 3};
   for (int it = 0; it < n_iter; ++it) {
     for (int m = 0; m < 4; ++m) move(order[m]);
@@ -807,27 +902,34 @@ void Ctm::step(int n_iter) {
   sync();
   delta_ = host_d_[0];
   flush_gemm_stats();
-  // phase times: quadrants, halves, svd, projectors + renormalisation
+  // phase times: quadrants, halves, svd, projectors + renormalisation; the
+  // time between two marks counts for the phase of the first
   timing.assign(4, 0.0);
-  for (int i = 0; i + 4 < ev_index_ + 1 && i < (int)ev_.size(); i += 5) {
-    for (int ph = 0; ph < 4; ++ph) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev_[i + ph], ev_[i + ph + 1]) == hipSuccess) timing[ph] += ms * 1e-3;
-    }
+  for (size_t i = 0; i + 1 < ev_phase_.size(); ++i) {
+    const int ph = ev_phase_[i];
+    if (ph < 0) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev_[i], ev_[i + 1]) == hipSuccess) timing[ph] += ms * 1e-3;
   }
 }
 
+Leg Ctm::bond(int x, int y, int side) {
+  // the first leg of the edge tensor on that side: T1's left, T2's up, T3's
+  // right, T4's down leg
+  return env(site(x, y), 2 * (side % 4) + 1).L.leg[0];
+}
+
 // ---------------------------------------------------------- observables ----
-void Ctm::compute_epsilon_rot() {
-  if (eps_ok_) return;
-  BT& C1 = env_[0];
-  BT& T1 = env_[1];
-  BT& C2 = env_[2];
-  BT& T2 = env_[3];
-  BT& C3 = env_[4];
-  BT& T3 = env_[5];
-  BT& C4 = env_[6];
-  BT& T4 = env_[7];
+void Ctm::compute_epsilon_rot(int st) {
+  if (eps_site_ == st) return;
+  BT& C1 = env(st, 0);
+  BT& T1 = env(st, 1);
+  BT& C2 = env(st, 2);
+  BT& T2 = env(st, 3);
+  BT& C3 = env(st, 4);
+  BT& T3 = env(st, 5);
+  BT& C4 = env(st, 6);
+  BT& T4 = env(st, 7);
   BT TA{Layout(), mid1_, mid_cap_};
   contract(C1, T1, TA);                    // [a | U b]
   BT TAs{Layout(), mid2_, mid_cap_};
@@ -854,16 +956,16 @@ void Ctm::compute_epsilon_rot() {
   permute(T2, T2s, {0, 1, 2}, 2);          // [c R | e]
   BT RB0{Layout(), big1_, big_cap_};
   contract(T2s, BOTs, RB0);                // [c R | Dn c']
-  BT RB{Layout(), quad_[0].p, quad_[0].capacity};
+  BT RB{Layout(), quad_[0].p, quad_[0].capacity};  // quadrant memory as scratch
   permute(RB0, RB, {0, 3, 2, 1}, 2);       // [c c' | Dn R]
-  quad_ok_[0] = false;
+  quad_ok_[0] = 0;
   contract(LTp, RB, eps_);                 // [U L | Dn R]
-  eps_ok_ = true;
+  eps_site_ = st;
 }
 
-BT Ctm::pack_impurity(int s, int sp, int kind, int frame) {
+BT Ctm::pack_impurity(int site, int s, int sp, int kind, int frame) {
   DLArgs g{};
-  g.A = A_;
+  g.A = A_ + (long long)site * d_ * D_ * D_ * D_ * D_;
   g.out = plain_tmp_;
   g.tab_idx = tab_idx_;
   g.tab_c = tab_c_;
@@ -895,13 +997,14 @@ BT Ctm::pack_impurity(int s, int sp, int kind, int frame) {
   return t;
 }
 
-// left half of the two-site environment in a frame, closed with an impurity
-BT Ctm::left_half(int f, const BT& imp) {
-  BT& C1 = env_[(2 * f) % 8];
-  BT& T1 = env_[(2 * f + 1) % 8];
-  BT& T3 = env_[(2 * f + 5) % 8];
-  BT& C4 = env_[(2 * f + 6) % 8];
-  BT& T4 = env_[(2 * f + 7) % 8];
+// left half of the two-site environment in a frame (environment of site st),
+// closed with an impurity
+BT Ctm::left_half(int f, int st, const BT& imp) {
+  BT& C1 = env(st, 2 * f);
+  BT& T1 = env(st, 2 * f + 1);
+  BT& T3 = env(st, 2 * f + 5);
+  BT& C4 = env(st, 2 * f + 6);
+  BT& T4 = env(st, 2 * f + 7);
   BT TL{Layout(), mid1_, mid_cap_};
   contract(C1, T1, TL);                    // [a | U y]
   BT T4s{Layout(), mid2_, mid_cap_};
@@ -927,12 +1030,12 @@ BT Ctm::left_half(int f, const BT& imp) {
   return out;
 }
 
-BT Ctm::right_half(int f, const BT& imp) {
-  BT& T1 = env_[(2 * f + 1) % 8];
-  BT& C2 = env_[(2 * f + 2) % 8];
-  BT& T2 = env_[(2 * f + 3) % 8];
-  BT& C3 = env_[(2 * f + 4) % 8];
-  BT& T3 = env_[(2 * f + 5) % 8];
+BT Ctm::right_half(int f, int st, const BT& imp) {
+  BT& T1 = env(st, 2 * f + 1);
+  BT& C2 = env(st, 2 * f + 2);
+  BT& T2 = env(st, 2 * f + 3);
+  BT& C3 = env(st, 2 * f + 4);
+  BT& T3 = env(st, 2 * f + 5);
   BT T1s{Layout(), mid1_, mid_cap_};
   permute(T1, T1s, {0, 1, 2}, 2);          // [y U | x]
   BT TR{Layout(), mid2_, mid_cap_};
@@ -941,8 +1044,8 @@ BT Ctm::right_half(int f, const BT& imp) {
   contract(TR, T2, W2);                    // [y U | R c'']
   BT W2p{Layout(), big2_, big_cap_};
   permute(W2, W2p, {0, 3, 1, 2}, 2);       // [y c'' | U R]
-  BT impp{Layout(), quad_[1].p, quad_[1].capacity};
-  quad_ok_[1] = false;
+  BT impp{Layout(), quad_[1].p, quad_[1].capacity};  // quadrant memory as scratch
+  quad_ok_[1] = 0;
   permute(imp, impp, {0, 3, 1, 2}, 2);     // [u r | l d]
   BT V2{Layout(), big1_, big_cap_};
   contract(W2p, impp, V2);                 // [y c'' | L Dn]
@@ -959,13 +1062,14 @@ BT Ctm::right_half(int f, const BT& imp) {
   return out;
 }
 
-void Ctm::rdm1(double* rho) {
-  compute_epsilon_rot();
+void Ctm::rdm1(int x, int y, double* rho) {
+  const int st = site(x, y);
+  compute_epsilon_rot(st);
   const int d = d_;
   int nd = 0;
   for (int s = 0; s < d; ++s)
     for (int t = (opt_.form == 0 ? s : 0); t < d; ++t) {
-      BT imp = pack_impurity(s, t, opt_.form == 0 ? 1 : 0, 0);
+      BT imp = pack_impurity(st, s, t, opt_.form == 0 ? 1 : 0, 0);
       if (imp.L.size != eps_.L.size) throw Error(1, "rdm1: layout mismatch");
       dots({DotJob{eps_.p, imp.p, eps_.L.size, dots_ + nd}}, dpart_, st_);
       ++nd;
@@ -975,11 +1079,14 @@ void Ctm::rdm1(double* rho) {
   sync();
 }
 
-// rho2: the left and right halves of the 4 x 3 environment, each closed with
-// the impurities of one site; in the Z2 form only sym x sym and anti x anti
-// pairs couple (the environment is even).
-void Ctm::rdm2(int dir, double* rho) {
+// rho2 of the pair (x, y)-(x+1, y) (dir 0) or (x, y)-(x, y+1) (dir 1): the
+// left half of the first site's environment and the right half of the
+// second's, in the frame where the pair is horizontal, each closed with the
+// impurities of its site; in the Z2 form only sym x sym and anti x anti pairs
+// couple (the environment is even).  Result (d^4) at dst on the device.
+void Ctm::rdm2_dev(int x, int y, int dir, double* dst) {
   const int f = dir == 0 ? 0 : 1;
+  const int s1 = site(x, y), s2 = dir == 0 ? site(x + 1, y) : site(x, y + 1);
   const int d = d_;
   halves_used_ = 0;
   std::vector<DotJob> jobs;
@@ -987,23 +1094,26 @@ void Ctm::rdm2(int dir, double* rho) {
   if (opt_.form != 0) {
     std::vector<BT> L, R;
     for (int s = 0; s < d; ++s)
-      for (int t = 0; t < d; ++t) L.push_back(left_half(f, pack_impurity(s, t, 0, f)));
+      for (int t = 0; t < d; ++t) L.push_back(left_half(f, s1, pack_impurity(s1, s, t, 0, f)));
     for (int s = 0; s < d; ++s)
-      for (int t = 0; t < d; ++t) R.push_back(right_half(f, pack_impurity(s, t, 0, f)));
+      for (int t = 0; t < d; ++t) R.push_back(right_half(f, s2, pack_impurity(s2, s, t, 0, f)));
     int k = 0;
     for (int a = 0; a < d * d; ++a)
-      for (int b = 0; b < d * d; ++b) jobs.push_back(DotJob{L[a].p, R[b].p, L[a].L.size, dots_ + k++});
+      for (int b = 0; b < d * d; ++b) {
+        if (L[a].L.size != R[b].L.size) throw Error(1, "rdm2: layout mismatch");
+        jobs.push_back(DotJob{L[a].p, R[b].p, L[a].L.size, dots_ + k++});
+      }
     mode = 2;
   } else {
     std::vector<BT> Ls, La, Rs, Ra;
     for (int s = 0; s < d; ++s)
-      for (int t = s; t < d; ++t) Ls.push_back(left_half(f, pack_impurity(s, t, 1, f)));
+      for (int t = s; t < d; ++t) Ls.push_back(left_half(f, s1, pack_impurity(s1, s, t, 1, f)));
     for (int s = 0; s < d; ++s)
-      for (int t = s + 1; t < d; ++t) La.push_back(left_half(f, pack_impurity(s, t, 2, f)));
+      for (int t = s + 1; t < d; ++t) La.push_back(left_half(f, s1, pack_impurity(s1, s, t, 2, f)));
     for (int s = 0; s < d; ++s)
-      for (int t = s; t < d; ++t) Rs.push_back(right_half(f, pack_impurity(s, t, 1, f)));
+      for (int t = s; t < d; ++t) Rs.push_back(right_half(f, s2, pack_impurity(s2, s, t, 1, f)));
     for (int s = 0; s < d; ++s)
-      for (int t = s + 1; t < d; ++t) Ra.push_back(right_half(f, pack_impurity(s, t, 2, f)));
+      for (int t = s + 1; t < d; ++t) Ra.push_back(right_half(f, s2, pack_impurity(s2, s, t, 2, f)));
     int k = 0;
     for (size_t a = 0; a < Ls.size(); ++a)
       for (size_t b = 0; b < Rs.size(); ++b) {
@@ -1018,36 +1128,43 @@ void Ctm::rdm2(int dir, double* rho) {
     mode = 3;
   }
   dots(jobs, dpart_, st_);
-  assemble_rho(dots_, d, mode, rho_, st_);
-  HCTM_HIP(hipMemcpyAsync(rho, rho_, sizeof(double) * d * d * d * d, hipMemcpyDeviceToHost, st_));
+  assemble_rho(dots_, d, mode, dst, st_);
+}
+
+void Ctm::rdm2(int x, int y, int dir, double* rho) {
+  rdm2_dev(x, y, dir, rho_);
+  HCTM_HIP(hipMemcpyAsync(rho, rho_, sizeof(double) * d_ * d_ * d_ * d_, hipMemcpyDeviceToHost, st_));
   sync();
 }
 
 double Ctm::energy(const double* h_host) {
-  const int d = d_, n = d * d;
-  std::vector<double> rh(n * n), rv(n * n);
-  // device copies of both RDMs, then E = Tr(rho_h h) + Tr(rho_v h) on the GPU
-  rdm2(0, rh.data());
-  HCTM_HIP(hipMemcpyAsync(rho_ + n * n, rho_, sizeof(double) * n * n, hipMemcpyDeviceToDevice, st_));
-  rdm2(1, rv.data());
-  // rho_ now holds [rho_v, rho_h]
-  HCTM_HIP(hipMemcpyAsync(hdev_, h_host, sizeof(double) * n * n, hipMemcpyHostToDevice, st_));
-  trace_products(rho_, 2, hdev_, n, misc_ + 20, st_);
+  // E = (1/ns) sum over sites of Tr(rho_h h) + Tr(rho_v h): all 2 ns RDMs on
+  // the device, traced against h / ns
+  const int n = d_ * d_;
+  const long long d4 = (long long)n * n;
+  for (int st = 0; st < ns_; ++st)
+    for (int dir = 0; dir < 2; ++dir) rdm2_dev(st % Lx_, st / Lx_, dir, rho_ + (2 * st + dir) * d4);
+  std::vector<double> hs(h_host, h_host + d4);
+  for (double& v : hs) v /= ns_;
+  HCTM_HIP(hipMemcpyAsync(hdev_, hs.data(), sizeof(double) * d4, hipMemcpyHostToDevice, st_));
+  trace_products(rho_, 2 * ns_, hdev_, n, misc_ + 20, st_);
   HCTM_HIP(hipMemcpyAsync(host_d_, misc_ + 20, sizeof(double), hipMemcpyDeviceToHost, st_));
   sync();
   return host_d_[0];
 }
 
-// eps in the plain basis (unnormalised) into plain_tmp2_; <eps~, a~> into misc_[24]
-void Ctm::epsilon_plain(double* eps_host) {
-  compute_epsilon_rot();
+// eps of site (x, y) in the plain basis (unnormalised) into plain_tmp2_;
+// <eps~, a~> into misc_[24]
+void Ctm::epsilon_plain(int x, int y, double* eps_host) {
+  const int sid = site(x, y);
+  compute_epsilon_rot(sid);
   const long long q4 = (long long)q_ * q_ * q_ * q_;
-  dots({DotJob{eps_.p, a_rot_[0].p, eps_.L.size, misc_ + 24}}, dpart_, st_);
+  dots({DotJob{eps_.p, a_rot(sid, 0).p, eps_.L.size, misc_ + 24}}, dpart_, st_);
   fill(plain_tmp_, 0.0, (size_t)q4, st_);
   const long long q = q_;
-  const long long st[4] = {q * q * q, q * q, q, 1};
+  const long long str[4] = {q * q * q, q * q, q, 1};
   std::vector<CopyJob> jobs;
-  plan_pack(plain_tmp_, st, eps_, false, jobs);
+  plan_pack(plain_tmp_, str, eps_, false, jobs);
   launch_copies(jobs);
   basis4(plain_tmp_, plain_tmp2_, q_, tabT_idx_, tabT_c_, st_);
   if (eps_host) {
@@ -1058,11 +1175,15 @@ void Ctm::epsilon_plain(double* eps_host) {
 }
 
 double Ctm::s_err() {
-  epsilon_plain(nullptr);
-  swap_asym(plain_tmp2_, D_, part_, misc_ + 26, st_);
-  HCTM_HIP(hipMemcpyAsync(host_d_, misc_ + 26, sizeof(double), hipMemcpyDeviceToHost, st_));
+  for (int st = 0; st < ns_; ++st) {
+    epsilon_plain(st % Lx_, st / Lx_, nullptr);
+    swap_asym(plain_tmp2_, D_, part_, misc_ + 26 + st, st_);
+  }
+  HCTM_HIP(hipMemcpyAsync(host_d_, misc_ + 26, sizeof(double) * ns_, hipMemcpyDeviceToHost, st_));
   sync();
-  return host_d_[0];
+  double m = 0.0;
+  for (int st = 0; st < ns_; ++st) m = std::max(m, host_d_[st]);
+  return m;
 }
 
 void Ctm::top_bottom(BT& top, BT& bot) {
@@ -1081,9 +1202,10 @@ void Ctm::top_bottom(BT& top, BT& bot) {
 }
 
 double Ctm::log_kappa() {
-  compute_epsilon_rot();
+  if (ns_ != 1) throw Error(1, "log_kappa: defined for the 1x1 cell only");
+  compute_epsilon_rot(0);
   // Z11 = <eps~, a~>
-  dots({DotJob{eps_.p, a_rot_[0].p, eps_.L.size, misc_ + 40}}, dpart_, st_);
+  dots({DotJob{eps_.p, a_rot(0, 0).p, eps_.L.size, misc_ + 40}}, dpart_, st_);
   // Z00 = Tr(C1 C2 C3 C4)
   {
     BT c12{Layout(), big1_, big_cap_}, c123{Layout(), big2_, big_cap_}, c1234{Layout(), big1_, big_cap_};

@@ -1,5 +1,6 @@
-// Directional CTMRG engine in the Z2 (Hermitian) basis.
+// Directional CTMRG engine in the Z2 (Hermitian) basis, Lx x Ly unit cell.
 #pragma once
+#include <array>
 #include <string>
 #include <vector>
 
@@ -23,13 +24,19 @@ struct Arena {
   }
 };
 
+// one truncation: the cut between frame rows `row` and `row`+1 left of frame
+// column `column` in a move of frame `frame`
 struct MoveRecord {
   std::vector<double> spectrum;  // kept values, merged, descending, / largest
   int k_even = 0, k_odd = 0;
+  int frame = 0, column = 0, row = 0;
 };
+
+constexpr int kMaxCell = 4;  // Lx, Ly <= kMaxCell
 
 struct Options {
   int form = 0;  // 0 Z2, 1 dense
+  int Lx = 1, Ly = 1;
   std::vector<double> boundary;
   double tau = 1e-12;
   int svd_iters = 12;
@@ -60,7 +67,7 @@ struct SvdSector {
 class Ctm {
  public:
   struct CountTag {};
-  Ctm(CountTag, int d, int D, int chi);
+  Ctm(CountTag, int d, int D, int chi, int Lx, int Ly);
   Ctm(const double* A_host, int d, int D, int chi, const Options& o, hipStream_t stream, void* workspace,
       size_t ws_bytes);
   ~Ctm();
@@ -68,14 +75,16 @@ class Ctm {
 
   void step(int n_iter);
   double delta() const { return delta_; }
-  void rdm1(double* rho);
-  void rdm2(int dir, double* rho);
-  void epsilon_plain(double* eps_host);
-  double s_err();
-  double log_kappa();
-  double energy(const double* h_host);
+  void rdm1(int x, int y, double* rho);
+  void rdm2(int x, int y, int dir, double* rho);
+  void epsilon_plain(int x, int y, double* eps_host);
+  double s_err();      // largest over the sites
+  double log_kappa();  // 1x1 cell only
+  double energy(const double* h_host);  // mean over the sites of E_h + E_v
   const std::vector<MoveRecord>& records() const { return records_; }
-  Leg side(int s) const { return side_[s]; }
+  Leg bond(int x, int y, int side);  // side 0 top, 1 right, 2 bottom, 3 left
+  int Lx() const { return Lx_; }
+  int Ly() const { return Ly_; }
   hipStream_t stream() const { return st_; }
   std::vector<double> timing;  // per-phase seconds of the last step() call
   GemmStats gemm_stats;        // accumulated since the last reset (profile mode)
@@ -89,19 +98,27 @@ class Ctm {
   void permute(const BT& in, BT& out, std::initializer_list<int> perm, int nr_out);
   void contract(const BT& A, const BT& B, BT& C);
   void normalise(BT& t);
-  void quadrant(int j);
+  int site(int x, int y) const;             // wrapped site index y*Lx + x
+  int site_of(int r, int X, int Y) const;   // site at frame-r coordinates
+  BT& env(int s, int i) { return env_[s * 8 + ((i % 8) + 8) % 8]; }
+  BT& quad(int s, int o) { return quad_[s * 4 + (o % 4)]; }
+  BT& a_rot(int s, int r) { return a_rot_[s * 4 + (r % 4)]; }
+  void quadrant(int s, int o);
   void move(int r);
-  void truncated_svd(BT& M, int chi);
+  void mark(int phase);
+  void truncated_svd(BT& M, int chi, int* kg, uint64_t salt);
   void orth(std::vector<SvdSector*>& ss, bool ql, int passes);
   void corner_spectra();
-  void compute_epsilon_rot();  // eps~ into eps_ (layout [U L | Dn R])
-  BT left_half(int frame, const BT& imp);
-  BT right_half(int frame, const BT& imp);
-  BT pack_impurity(int s, int sp, int kind, int frame);  // kind 0 plain, 1 sym, 2 anti
+  void compute_epsilon_rot(int s);  // eps~ of site s into eps_ (layout [U L | Dn R])
+  BT left_half(int frame, int s, const BT& imp);
+  BT right_half(int frame, int s, const BT& imp);
+  BT pack_impurity(int site, int s, int sp, int kind, int frame);  // kind 0 plain, 1 sym, 2 anti
+  void rdm2_dev(int x, int y, int dir, double* dst);
   void sync();
   void top_bottom(BT& top, BT& bot);  // TOP[a U | c], BOT[c' Dn | e] (frame 0)
 
   int d_, D_, chi_, q_, cc_;
+  int Lx_ = 1, Ly_ = 1, ns_ = 1;
   Leg lq_;
   Options opt_;
   hipStream_t st_ = nullptr;
@@ -115,17 +132,16 @@ class Ctm {
   double* tab_c_ = nullptr;
   int* tabT_idx_ = nullptr;  // U^T
   double* tabT_c_ = nullptr;
-  double* A_ = nullptr;
+  double* A_ = nullptr;       // ns tensors, site s at s * d D^4
   double* b_ = nullptr;
-  double* a_plain_ = nullptr;  // q^4, rotated basis, frame 0
+  std::vector<double*> a_plain_;  // per site: q^4, rotated basis, frame 0
   double* plain_tmp_ = nullptr;  // q^4 scratch
   double* plain_tmp2_ = nullptr;
-  BT a_rot_[4];
+  std::vector<BT> a_rot_;        // site s, frame r at s*4 + r
 
-  BT env_[8];
-  Leg side_[4];
-  BT quad_[4];
-  bool quad_ok_[4] = {false, false, false, false};
+  std::vector<BT> env_;          // site s, slot i at s*8 + i
+  std::vector<BT> quad_;         // site s, frame o at s*4 + o
+  std::vector<char> quad_ok_;
 
   // scratch
   double *big1_ = nullptr, *big2_ = nullptr;
@@ -133,9 +149,10 @@ class Ctm {
   double *mid1_ = nullptr, *mid2_ = nullptr, *mid3_ = nullptr;
   long long mid_cap_ = 0;
   BT Hu_, Hd_, M_;
-  BT Pa_, Pb_;
+  std::vector<BT> Pa_, Pb_;      // one pair per cut of the column being swept
   long long proj_cap_ = 0;
   SvdSector sec_[2];
+  std::vector<std::array<int, 2>> kg_;  // kept-state guess per (frame, column, row)
   int l_cap_ = 0;
   double* misc_ = nullptr;  // small device scalars
   int* kdev_ = nullptr;
@@ -143,7 +160,7 @@ class Ctm {
   double* host_d_ = nullptr;
   double* part_ = nullptr;
   // corner spectra
-  double* cspec_ = nullptr;     // 4 corners x chi (current, normalised)
+  double* cspec_ = nullptr;     // sites x 4 corners x chi (current, normalised)
   double* cspec_old_ = nullptr;
   double* csv_ = nullptr;       // scratch singular values
   int* cperm_ = nullptr;
@@ -152,11 +169,10 @@ class Ctm {
   double delta_ = 1e300;
   // observables
   BT eps_;
-  bool eps_ok_ = false;
-  uint64_t move_count_ = 0;
+  int eps_site_ = -1;  // site whose eps~ eps_ holds (-1: none)
   std::vector<MoveRecord> records_;
-  std::vector<hipEvent_t> ev_;
-  int ev_index_ = 0;
+  std::vector<hipEvent_t> ev_;   // phase marks of the current step()
+  std::vector<int> ev_phase_;
   double* halves_ = nullptr;
   long long halves_cap_ = 0;
   int halves_used_ = 0;
@@ -165,7 +181,7 @@ class Ctm {
   long long gemm_scratch_cap_ = 0;
   double* dots_ = nullptr;     // dot-product results
   double* dpart_ = nullptr;    // dot-product partial sums (64 per job)
-  double* rho_ = nullptr;      // device RDM output (d^4)
+  double* rho_ = nullptr;      // device RDM outputs (2 ns d^4)
   double* hdev_ = nullptr;     // bond operator (d^4)
   MoveRecord pending_;
   // profile mode: pending GEMM event pairs and their flops

@@ -811,7 +811,11 @@ __global__ void corner_spectra_kernel(SpecArgs a) {
     dl[c] = sqrt(d2);
   }
   __syncthreads();
-  if (c == 0) *a.delta = a.have_old ? fmax(fmax(dl[0], dl[1]), fmax(dl[2], dl[3])) : 1e300;
+  if (c == 0) {
+    double v = a.have_old ? fmax(fmax(dl[0], dl[1]), fmax(dl[2], dl[3])) : 1e300;
+    if (a.accumulate) v = fmax(v, *a.delta);
+    *a.delta = v;
+  }
 }
 
 }  // namespace

@@ -38,8 +38,9 @@ struct SelectArgs {
   double* isv1;
 };
 
-// corner spectra: merge the two sector spectra of each corner, divide by the
-// sum, pad to len; delta = max_c || new_c - old_c ||_2 (if have_old)
+// corner spectra of one site: merge the two sector spectra of each corner,
+// divide by the sum, pad to len; delta = max_c || new_c - old_c ||_2 (if
+// have_old), or the maximum of that and the incoming *delta (accumulate)
 struct SpecArgs {
   const double* sv[8];  // corner c sector P at sv[2c+P]
   int nsv[8];
@@ -47,6 +48,7 @@ struct SpecArgs {
   const double* spec_old;
   int len;
   int have_old;
+  int accumulate;
   double* delta;
 };
 void corner_spectra_delta(const SpecArgs& a, hipStream_t s);

@@ -1,0 +1,130 @@
+"""The C ABI without a GPU: every symbol the headers declare is exported by
+libhctm.so, and the calls that do no device work (defaults, workspace sizing,
+argument checks) behave as documented in include/hctm.h."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2410_11596_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("hctm.h", "hctm_testing.h")]
+DECL = re.compile(r"^\s*(?:const\s+)?(?:int|void|char|long long|size_t)\s*\**\s*(\w+)\s*\(", re.M)
+
+
+def declared():
+    names = []
+    for h in HEADERS:
+        with open(h) as f:
+            text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+        names += DECL.findall(text)
+    return names
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2410_11596_amd import build
+
+        build.build()
+    return binding.lib()
+
+
+def test_headers_declare_the_documented_calls():
+    names = declared()
+    for must in ("ctm_init", "ctm_step", "ctm_converged", "ctm_rdm_1site", "ctm_rdm_2site", "ctm_free"):
+        assert must in names
+    assert len(names) == len(set(names))
+
+
+def test_library_exports_every_declared_symbol(L):
+    names = declared()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # the binding wraps exactly the declared set
+    assert sorted(binding.EXPORTS) == sorted(names)
+
+
+def test_opts_default(L):
+    o = binding.CtmOpts()
+    assert L.ctm_opts_default(ctypes.byref(o)) == binding.CTM_OK
+    assert o.form == binding.CTM_FORM_Z2
+    assert o.svd_rel_cutoff == 1e-12
+    assert o.svd_iters == 12
+    assert not o.boundary and not o.stream and not o.workspace
+    assert o.Lx == 1 and o.Ly == 1
+    assert L.ctm_opts_default(None) == binding.CTM_E_ARG
+
+
+def _ws(L, d, D, chi, **kw):
+    o = binding.CtmOpts()
+    L.ctm_opts_default(ctypes.byref(o))
+    keep = None
+    for k, v in kw.items():
+        if k == "boundary":
+            keep = np.ascontiguousarray(v, dtype=np.float64)
+            o.boundary = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        else:
+            setattr(o, k, v)
+    n = ctypes.c_size_t(0)
+    rc = L.ctm_workspace_size(d, D, chi, ctypes.byref(o), ctypes.byref(n))
+    return rc, n.value
+
+
+def test_workspace_size_grows_with_chi_and_cell(L):
+    rc, a = _ws(L, 2, 4, 32)
+    assert rc == 0 and a > 0
+    rc, b = _ws(L, 2, 4, 64)
+    assert rc == 0 and b > a
+    rc, c = _ws(L, 2, 4, 64, Lx=2, Ly=2)
+    assert rc == 0 and c > b
+    # the D = 6, chi = 144 workload fits comfortably in one GPU's HBM
+    rc, big = _ws(L, 2, 6, 144)
+    assert rc == 0 and big < 16 * 2**30
+
+
+@pytest.mark.parametrize("d,D,chi", [(0, 2, 8), (17, 2, 8), (2, 0, 8), (2, 9, 8), (2, 2, 0), (2, 2, 5000)])
+def test_size_checks(L, d, D, chi):
+    rc, _ = _ws(L, d, D, chi)
+    assert rc == binding.CTM_E_ARG
+    assert b"must be" in L.ctm_last_error(None)
+
+
+def test_option_checks(L):
+    assert _ws(L, 2, 2, 8, form=7)[0] == binding.CTM_E_ARG
+    assert _ws(L, 2, 2, 8, svd_rel_cutoff=-1.0)[0] == binding.CTM_E_ARG
+    assert _ws(L, 2, 2, 8, svd_iters=0)[0] == binding.CTM_E_ARG
+    assert _ws(L, 2, 2, 8, Lx=0)[0] == binding.CTM_E_ARG
+    assert _ws(L, 2, 2, 8, Ly=5)[0] == binding.CTM_E_ARG
+    # the Z2 form needs a swap-symmetric boundary vector; the plain form does not
+    b = np.array([1.0, 0.5, 0.0, 1.0])
+    assert _ws(L, 2, 2, 8, boundary=b)[0] == binding.CTM_E_ARG
+    assert b"swap symmetric" in L.ctm_last_error(None)
+    assert _ws(L, 2, 2, 8, boundary=b, form=binding.CTM_FORM_DENSE)[0] == 0
+    assert _ws(L, 2, 2, 8, boundary=np.array([1.0, 0.5, 0.5, 1.0]))[0] == 0
+    assert _ws(L, 2, 2, 8, boundary=np.zeros(4))[0] == binding.CTM_E_ARG
+    assert _ws(L, 2, 2, 8, boundary=np.array([1.0, np.nan, np.nan, 1.0]))[0] == binding.CTM_E_NUMERIC
+
+
+def test_init_rejects_bad_arguments_before_touching_a_device(L):
+    A = np.ones((2, 2, 2, 2, 2))
+    ctx = ctypes.c_void_p(1234)
+    dp = A.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.ctm_init(ctypes.byref(ctx), dp, 2, 9, 8, None) == binding.CTM_E_ARG
+    assert ctx.value is None  # *out is cleared on failure
+    assert L.ctm_init(ctypes.byref(ctx), None, 2, 2, 8, None) == binding.CTM_E_ARG
+    assert L.ctm_init(None, dp, 2, 2, 8, None) == binding.CTM_E_ARG
+    A[0, 0, 0, 0, 0] = np.inf
+    assert L.ctm_init(ctypes.byref(ctx), dp, 2, 2, 8, None) == binding.CTM_E_NUMERIC
+    assert b"non-finite" in L.ctm_last_error(None)
+
+
+def test_null_context(L):
+    L.ctm_free(None)
+    assert L.ctm_step(None, 1) == binding.CTM_E_ARG
+    n = ctypes.c_int(0)
+    assert L.ctm_num_records(None, ctypes.byref(n)) == binding.CTM_E_ARG
+    assert isinstance(L.ctm_last_error(None), bytes)
