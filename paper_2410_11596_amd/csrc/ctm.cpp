@@ -42,6 +42,8 @@ namespace hctm {
 namespace {
 constexpr int kDirectMax = 160;  // sectors up to this size are decomposed directly
 constexpr int kJacobiSweeps = 40;
+// relative residual of the leading columns that ends the subspace iteration
+constexpr double kSubspaceTol = 1e-12;
 }
 
 // ------------------------------------------------------------- memory ----
@@ -137,12 +139,22 @@ void Ctm::plan_memory(bool counting) {
     Pb_[Y].capacity = proj_cap_;
   }
   kg_.assign(4 * kMaxCell * kMaxCell, std::array<int, 2>{0, 0});
+  // right vectors of the last truncation of every cut (warm starts)
+  warm_cap_ = ncap * cc;
+  warm_.assign(2 * 4 * kMaxCell * kMaxCell, WarmV());
+  for (int r = 0; r < 4; ++r) {
+    const int LX = (r % 2 == 0) ? Lx_ : Ly_, LY = (r % 2 == 0) ? Ly_ : Lx_;
+    for (int X = 0; X < LX; ++X)
+      for (int Y = 0; Y < LY; ++Y)
+        for (int P = 0; P < 2; ++P) warm_[((r * kMaxCell + X) * kMaxCell + Y) * 2 + P].V = ar_.take((size_t)warm_cap_);
+  }
   for (int P = 0; P < 2; ++P) {
     SvdSector& S = sec_[P];
     S.Qr = ar_.take((size_t)(ncap * lcap));
     S.Ql = ar_.take((size_t)(ncap * lcap));
     S.Y = ar_.take((size_t)(ncap * lcap));
     S.Tm = ar_.take((size_t)(ncap * lcap));
+    S.Qold = ar_.take((size_t)(ncap * lcap));
     S.G = ar_.take((size_t)(lcap * lcap));
     S.Ri = ar_.take((size_t)(lcap * lcap));
     S.B = ar_.take((size_t)(lcap * lcap));
@@ -212,7 +224,7 @@ Ctm::Ctm(const double* A_host, int d, int D, int chi, const Options& o, hipStrea
   ar_.cap = need;
   plan_memory(false);
   HCTM_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_k_), 64 * sizeof(int), hipHostMallocDefault));
-  HCTM_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_d_), 4096 * sizeof(double), hipHostMallocDefault));
+  HCTM_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_d_), (4096 + 64) * sizeof(double), hipHostMallocDefault));
   setup(A_host);
 }
 
@@ -424,16 +436,28 @@ void Ctm::quadrant(int s, int j) {
 }
 
 // ---------------------------------------------------------------- SVD ----
-void Ctm::orth(std::vector<SvdSector*>& ss, bool ql, int passes) {
-  // src = S.Y, dst = Ql or Qr, scratch Tm; 2 or 3 CholeskyQR passes, the
-  // result always ends in dst (pass 0: src->dst, 1: dst->Tm, 2: Tm->dst;
-  // with 2 passes the last product writes dst from Tm's predecessor).
-  if (passes < 1 || passes > 3) throw Error(1, "orth: passes must be 1, 2 or 3");
-  for (int pass = 0; pass < passes; ++pass) {
+// CholeskyQR of S->Y into Ql (ql) or Qr with S->passes passes per sector
+// (1 inside the subspace iteration, 3 for its final iterate).  Buffer chain
+// per sector: pass p reads Y (p = 0) or the previous pass's output and writes
+// dst if (passes - 1 - p) is even, else the scratch Tm, so that the last
+// pass always ends in dst.
+void Ctm::orth(std::vector<SvdSector*>& ss, bool ql) {
+  int pmax = 0;
+  for (SvdSector* S : ss) {
+    if (S->passes < 1 || S->passes > 3) throw Error(1, "orth: passes must be 1, 2 or 3");
+    pmax = std::max(pmax, S->passes);
+  }
+  auto src_of = [&](SvdSector* S, int pass) -> const double* {
+    double* dstq = ql ? S->Ql : S->Qr;
+    return pass == 0 ? S->Y : (((S->passes - pass) % 2 == 0) ? dstq : S->Tm);
+  };
+  for (int pass = 0; pass < pmax; ++pass) {
+    std::vector<SvdSector*> act;
+    for (SvdSector* S : ss)
+      if (pass < S->passes) act.push_back(S);
     std::vector<GemmDesc> g;
-    for (SvdSector* S : ss) {
-      double* dstq = ql ? S->Ql : S->Qr;
-      const double* src = pass == 0 ? S->Y : (((passes - pass) % 2 == 0) ? dstq : S->Tm);
+    for (SvdSector* S : act) {
+      const double* src = src_of(S, pass);
       GemmDesc d{};
       d.A = src;
       d.B = src;
@@ -452,30 +476,28 @@ void Ctm::orth(std::vector<SvdSector*>& ss, bool ql, int passes) {
     }
     launch_gemms(g);
     std::vector<SmallProb> sp;
-    for (SvdSector* S : ss) {
+    for (SvdSector* S : act) {
       SmallProb p{};
       p.a = S->G;
       p.b = S->Ri;
       p.m = p.n = S->l;
       p.lda = p.ldb = S->l;
       // unit-diagonal (column-scaled) Gram; a small shift in the first pass
-      // keeps the factorisation defined while the columns are nearly parallel.
-      // Inner iterations need only a well-conditioned basis (one pass); the
-      // last one is orthonormalised to rounding (three passes).
-      p.rel = pass == 0 ? 1e-10 : 0.0;
+      // keeps the factorisation defined while the columns are nearly parallel
+      // (a random start); once the basis is aligned it is lowered so that the
+      // residual check below is not limited by it
+      p.rel = pass == 0 ? S->rel0 : 0.0;
       p.flags = 1;
-      p.sv = S->isv;
+      p.sv = S->isv;  // column norms of the pass's input (kept for the check)
       p.info = S->info;
       sp.push_back(p);
     }
     chol_inv(sp, st_);
-    for (SvdSector* S : ss) {
-      // pass p writes dst if (passes - 1 - p) is even, else the scratch Tm
+    for (SvdSector* S : act) {
       double* dstq = ql ? S->Ql : S->Qr;
-      const double* src = pass == 0 ? S->Y : (((passes - pass) % 2 == 0) ? dstq : S->Tm);
-      double* dst = ((passes - 1 - pass) % 2 == 0) ? dstq : S->Tm;
+      double* dst = ((S->passes - 1 - pass) % 2 == 0) ? dstq : S->Tm;
       GemmDesc d{};
-      d.A = src;
+      d.A = src_of(S, pass);
       d.B = S->Ri;
       d.C = dst;
       d.M = S->n;
@@ -492,9 +514,17 @@ void Ctm::orth(std::vector<SvdSector*>& ss, bool ql, int passes) {
   }
 }
 
-// kg[2]: guess of the kept states per sector (in/out, 0 = none); salt makes
-// the random start blocks differ between cuts.
-void Ctm::truncated_svd(BT& M, int chi, int* kg_io, uint64_t salt) {
+// Truncated SVD of both sector blocks of M (batched): randomized subspace
+// iteration, Rayleigh-Ritz and one-sided Jacobi, or Jacobi on the block itself
+// when it is small.  key selects the cut: its previous kept count guesses the
+// subspace size, and its previous right vectors start the iteration (warm
+// start) when the block size is unchanged.  A sector stops iterating once
+// M Q_r lies in the span of the left basis to kSubspaceTol (leading columns,
+// relative to the largest); its last iterate is re-orthonormalised to
+// rounding.  At most the configured number of iterations run.  salt makes the
+// random blocks differ between cuts.
+void Ctm::truncated_svd(BT& M, int chi, int key, uint64_t salt) {
+  int* kg_io = kg_[key].data();
   for (int attempt = 0; attempt < 4; ++attempt) {
     std::vector<SvdSector*> sub, all;
     for (int P = 0; P < 2; ++P) {
@@ -502,12 +532,16 @@ void Ctm::truncated_svd(BT& M, int chi, int* kg_io, uint64_t salt) {
       S.n = (int)M.L.rows[P];
       S.Mp = M.p + M.L.off[P];
       S.k = 0;
+      S.warm = false;
+      S.fin = false;
+      S.done = false;
       if (S.n == 0) {
         S.trusted = 0;
         continue;
       }
       int kg = kg_io[P] > 0 ? kg_io[P] : chi;
       kg = std::min(kg, S.n);
+      S.kg = kg;
       const int p = std::max(32, kg / 2);
       S.l = std::min<int>(std::min(S.n, kg + p), l_cap_);
       S.direct = S.n <= kDirectMax || S.l >= S.n;
@@ -519,17 +553,41 @@ void Ctm::truncated_svd(BT& M, int chi, int* kg_io, uint64_t salt) {
     }
     // subspace iteration (both sectors batched)
     if (!sub.empty()) {
+      std::vector<CopyJob> jobs;
       for (SvdSector* S : sub) {
-        const uint64_t seed = opt_.seed * 0x9E3779B97F4A7C15ull + (salt << 4) + (S == &sec_[1] ? 1 : 0) +
-                              ((uint64_t)attempt << 2);
+        const int P = S == &sec_[1] ? 1 : 0;
+        const uint64_t seed = opt_.seed * 0x9E3779B97F4A7C15ull + (salt << 4) + P + ((uint64_t)attempt << 2);
         random_fill(S->Y, (size_t)S->n * S->l, seed, st_);
+        const WarmV& w = warm_[key * 2 + P];
+        if (attempt == 0 && w.V && w.n == S->n && w.k > 0) {
+          // previous right vectors in the leading columns
+          S->warm = true;
+          CopyJob j{};
+          j.in = w.V;
+          j.out = S->Y;
+          j.r = 2;
+          j.dims[0] = S->n;
+          j.dims[1] = std::min(w.k, S->l);
+          j.istr[0] = w.k;
+          j.istr[1] = 1;
+          j.ostr[0] = S->l;
+          j.ostr[1] = 1;
+          jobs.push_back(j);
+        }
+        S->passes = 3;
       }
-      orth(sub, false, 3);  // Qr
+      launch_copies(jobs);
+      for (SvdSector* S : sub) S->rel0 = 1e-10;
+      orth(sub, false);  // Qr
+      // Iterate; from the second iteration on, before a sector's new left
+      // basis is formed, the residual of the leading columns of Y = M Q_r
+      // outside the previous left basis (relative to the largest column)
+      // decides whether this iterate is the final one.
       const int T = std::max(1, opt_.svd_iters);
-      for (int t = 0; t < T; ++t) {
-        const bool last = t == T - 1;
+      std::vector<SvdSector*> act = sub;
+      for (int t = 0; t < T && !act.empty(); ++t) {
         std::vector<GemmDesc> g;
-        for (SvdSector* S : sub) {
+        for (SvdSector* S : act) {
           GemmDesc d{};
           d.A = S->Mp;
           d.B = S->Qr;
@@ -544,8 +602,63 @@ void Ctm::truncated_svd(BT& M, int chi, int* kg_io, uint64_t salt) {
           g.push_back(d);
         }
         launch_gemms(g);
-        orth(sub, true, last ? 3 : 1);  // Ql
-        for (SvdSector* S : sub) {
+        for (SvdSector* S : act) S->fin = t == T - 1;
+        if (t >= 1) {
+          std::vector<SvdSector*> chk = act;
+          // C = Ql^T Y[:, :kc] (into G), P = Ql C (into Qold)
+          for (SvdSector* S : chk) {
+            const int kc = std::min(S->kg, S->l);
+            GemmDesc d{};
+            d.A = S->Ql;
+            d.B = S->Y;
+            d.C = S->G;
+            d.M = S->l;
+            d.N = kc;
+            d.K = S->n;
+            d.lda = S->l;
+            d.ldb = S->l;
+            d.ldc = kc;
+            d.ta = 1;
+            d.alpha = 1.0;
+            g.push_back(d);
+          }
+          launch_gemms(g);
+          for (SvdSector* S : chk) {
+            const int kc = std::min(S->kg, S->l);
+            GemmDesc d{};
+            d.A = S->Ql;
+            d.B = S->G;
+            d.C = S->Qold;
+            d.M = S->n;
+            d.N = kc;
+            d.K = S->l;
+            d.lda = S->l;
+            d.ldb = kc;
+            d.ldc = kc;
+            d.alpha = 1.0;
+            g.push_back(d);
+          }
+          launch_gemms(g);
+          for (size_t c = 0; c < chk.size(); ++c) {
+            SvdSector* S = chk[c];
+            const int kc = std::min(S->kg, S->l);
+            fill(misc_ + 48 + 2 * c, 0.0, 2, st_);
+            col_resid(S->Y, S->l, S->Qold, kc, S->n, kc, misc_ + 48 + 2 * c, st_);
+          }
+          HCTM_HIP(hipMemcpyAsync(host_d_ + 4096, misc_ + 48, sizeof(double) * 2 * chk.size(),
+                                  hipMemcpyDeviceToHost, st_));
+          sync();
+          for (size_t c = 0; c < chk.size(); ++c) {
+            const double e = host_d_[4096 + 2 * c], ymax = host_d_[4096 + 2 * c + 1];
+            if (e <= kSubspaceTol * ymax) chk[c]->fin = true;
+          }
+        }
+        for (SvdSector* S : act) {
+          S->passes = S->fin ? 3 : 1;
+          S->rel0 = (S->warm || t >= 3) ? 1e-14 : 1e-10;
+        }
+        orth(act, true);  // Ql
+        for (SvdSector* S : act) {
           GemmDesc d{};
           d.A = S->Mp;
           d.B = S->Ql;
@@ -561,7 +674,11 @@ void Ctm::truncated_svd(BT& M, int chi, int* kg_io, uint64_t salt) {
           g.push_back(d);
         }
         launch_gemms(g);
-        orth(sub, false, last ? 3 : 1);  // Qr; Y keeps Z = M^T Ql
+        orth(act, false);  // Qr; Y keeps Z = M^T Ql
+        std::vector<SvdSector*> next;
+        for (SvdSector* S : act)
+          if (!S->fin) next.push_back(S);
+        act.swap(next);
       }
       // B = Z^T Qr = Ql^T M Qr
       std::vector<GemmDesc> g;
@@ -628,6 +745,7 @@ void Ctm::truncated_svd(BT& M, int chi, int* kg_io, uint64_t salt) {
     for (int P = 0; P < 2; ++P) {
       SvdSector& S = sec_[P];
       S.k = host_k_[P];
+      S.sweeps = host_k_[3 + 2 * P];
       if (S.n == 0) continue;
       if (host_k_[3 + 2 * P] < 0) throw Error(4, "Jacobi SVD did not converge");
       if (!S.direct && S.k >= S.trusted) {
@@ -674,6 +792,7 @@ void Ctm::truncated_svd(BT& M, int chi, int* kg_io, uint64_t salt) {
     g.push_back(e);
   }
   launch_gemms(g);
+  std::vector<CopyJob> save;
   for (int P = 0; P < 2; ++P) {
     SvdSector& S = sec_[P];
     kg_io[P] = S.k;
@@ -684,7 +803,24 @@ void Ctm::truncated_svd(BT& M, int chi, int* kg_io, uint64_t salt) {
       S.W = S.Wbuf;
       S.V = S.Vbuf;
     }
+    // keep the kept right vectors of this cut for the next warm start
+    WarmV& w = warm_[key * 2 + P];
+    w.n = 0;
+    w.k = 0;
+    if (w.V && !S.direct && S.k > 0 && (long long)S.n * S.k <= warm_cap_) {
+      CopyJob j{};
+      j.in = S.V;
+      j.out = w.V;
+      j.r = 1;
+      j.dims[0] = S.n * S.k;
+      j.istr[0] = 1;
+      j.ostr[0] = 1;
+      save.push_back(j);
+      w.n = S.n;
+      w.k = S.k;
+    }
   }
+  launch_copies(save);
 }
 
 // ---------------------------------------------------------------- move ----
@@ -729,8 +865,7 @@ void Ctm::move(int r) {
         launch_gemms(g);
       }
       mark(2);
-      int* kg = kg_[(r * kMaxCell + X) * kMaxCell + Y].data();
-      truncated_svd(M_, chi_, kg, (uint64_t)records_.size());
+      truncated_svd(M_, chi_, (r * kMaxCell + X) * kMaxCell + Y, (uint64_t)records_.size());
       mark(3);
 
       // projectors of this cut

@@ -52,10 +52,16 @@ struct GemmStats {
 
 // per-sector state of the truncated SVD
 struct SvdSector {
-  int n = 0, l = 0, kg = 0, trusted = 0, k = 0;
+  int n = 0, l = 0, kg = 0, trusted = 0, k = 0, sweeps = 0;
+  int passes = 1;        // CholeskyQR passes of the next orthonormalisation
+  double rel0 = 1e-10;   // relative diagonal shift of its first pass
   bool direct = false;
+  bool warm = false;     // started from the cut's previous right vectors
+  bool fin = false;      // the next iterate is the final one
+  bool done = false;
   const double* Mp = nullptr;  // sector block of M (n x n, ld = n)
   double *Qr = nullptr, *Ql = nullptr, *Y = nullptr, *Tm = nullptr;
+  double* Qold = nullptr;  // projection of Y on the previous left basis (check)
   double *G = nullptr, *Ri = nullptr, *B = nullptr, *Bj = nullptr;
   double *Ub = nullptr, *Vb = nullptr, *Wbuf = nullptr, *Vbuf = nullptr;
   const double *W = nullptr, *V = nullptr;  // kept vectors (n x k) of M_P
@@ -106,8 +112,8 @@ class Ctm {
   void quadrant(int s, int o);
   void move(int r);
   void mark(int phase);
-  void truncated_svd(BT& M, int chi, int* kg, uint64_t salt);
-  void orth(std::vector<SvdSector*>& ss, bool ql, int passes);
+  void truncated_svd(BT& M, int chi, int key, uint64_t salt);
+  void orth(std::vector<SvdSector*>& ss, bool ql);
   void corner_spectra();
   void compute_epsilon_rot(int s);  // eps~ of site s into eps_ (layout [U L | Dn R])
   BT left_half(int frame, int s, const BT& imp);
@@ -153,6 +159,12 @@ class Ctm {
   long long proj_cap_ = 0;
   SvdSector sec_[2];
   std::vector<std::array<int, 2>> kg_;  // kept-state guess per (frame, column, row)
+  struct WarmV {
+    double* V = nullptr;  // n x k right vectors of the cut's last truncation
+    int n = 0, k = 0;
+  };
+  std::vector<WarmV> warm_;  // (frame, column, row) x sector
+  long long warm_cap_ = 0;
   int l_cap_ = 0;
   double* misc_ = nullptr;  // small device scalars
   int* kdev_ = nullptr;

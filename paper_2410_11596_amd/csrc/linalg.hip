@@ -436,6 +436,192 @@ __global__ __launch_bounds__(NT) void chol_inv_regs_kernel(SmallBatch b) {
     chol_inv_regs<5>(P, Lpk, buf);
 }
 
+// ------------------------------------- Cholesky inverse, one elimination ----
+// R^-1 of G = R^T R for n <= 16 * kGjMaxR, one workgroup of 256 threads (one
+// wave per SIMD) per matrix.  The elimination of G (G = L_u D L_u^T, L_u unit
+// lower) and the inverse X = L_u^-1 run in the same sweep over the columns and
+// in the same registers.  With multipliers m_i = G_ij / d_j (i > j), step j
+// updates
+//   entries (i, k), k > j (still G):        G_ik -= m_i G_kj
+//   entries (i, k), k < j (S, see below):   S_ik -= m_i S_jk
+// and leaves column j alone.  S_ic = -d_c X_ic is X with column c scaled by
+// -d_c: the update of X is linear in each column, and at step c the value
+// held at (i, c), G_ic = m_i d_c, is exactly -d_c X_ic = -d_c (-m_i).  So the
+// column-to-X transition costs nothing.  Each step broadcasts through LDS
+// column j of G (rows >= j, including the pivot d_j) and row j of S (columns
+// < j), written by their owners at the end of step j-1; one barrier per step.
+// At the end X_ic = -S_ic / d_c and R^-1[c][i] = X_ic / sqrt(d_i).  Thread
+// (ty, tx) of the 16 x 16 grid holds the entries (ty + 16u, tx + 16v), u >= v.
+// Pivots d_j <= 1e-27 max(diag) drop their column: zero multipliers, and
+// row and column of X zero (as in chol_inv_regs).
+constexpr int NTC = 256;
+constexpr int kGjMaxR = 14;  // n <= 224
+
+template <int R>
+__device__ void chol_gj(const SmallProb& P, double* buf, double* red, int* bad) {
+  const int n = P.n, ld = P.lda, ldr = P.ldb;
+  const double* G = P.a;
+  double* Ri = P.b;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const bool scale = (P.flags & 1) != 0;
+  double* dsc = P.sv;
+  constexpr int L = 16 * R;
+  // buf: [2 buffers][L + 1]
+  if (scale)
+    for (int i = tid; i < n; i += NTC) {
+      const double g = G[(long long)i * ld + i];
+      dsc[i] = g > 0.0 ? sqrt(g) : 1.0;
+    }
+  if (tid == 0) *bad = 0;
+  for (int i = tid; i < 2 * (L + 1); i += NTC) buf[i] = 0.0;
+  __syncthreads();
+  double dmax = 0.0;
+  for (int i = tid; i < n; i += NTC) {
+    const double g = G[(long long)i * ld + i];
+    dmax = fmax(dmax, scale ? g / (dsc[i] * dsc[i]) : g);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = dmax;
+  __syncthreads();
+  dmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  const double shift = P.rel * dmax;
+  const double thresh = 1e-27 * dmax;
+
+  double a[R][R];  // a[u][v] used for u >= v only
+#pragma unroll
+  for (int u = 0; u < R; ++u)
+#pragma unroll
+    for (int v = 0; v <= u; ++v) {
+      const int i = ty + 16 * u, k = tx + 16 * v;
+      double x = 0.0;
+      if (i < n && k <= i) {
+        x = G[(long long)i * ld + k];
+        if (scale) x /= dsc[i] * dsc[k];
+        if (i == k) x += shift;
+      }
+      a[u][v] = x;
+    }
+  // step 0: column 0 of G below the pivot, the pivot in slot L
+  if (tx == 0)
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i = ty + 16 * u;
+      if (i == 0) {
+        buf[L] = a[u][0];
+        buf[0] = 0.0;
+      } else {
+        buf[i] = a[u][0];
+      }
+    }
+  __syncthreads();
+
+  // one vector per step: w_k = G_kj (k > j), 0 (k = j), S_jk (k < j); the
+  // pivot d_j in slot L
+  for (int j = 0; j < n; ++j) {
+    const double* wv = buf + (j & 1) * (L + 1);
+    double* nw = buf + ((j + 1) & 1) * (L + 1);
+    const int jb = j >> 4;
+    double ci[R], w[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) ci[u] = wv[ty + 16 * u];
+#pragma unroll
+    for (int v = 0; v < R; ++v) w[v] = wv[tx + 16 * v];
+    const double dj = wv[L];
+    // 1/d_j: hardware reciprocal and two Newton steps (error below 1 ulp)
+    double inv = 0.0;
+    if (dj > thresh) {
+      double r0 = __builtin_amdgcn_rcp(dj);
+      r0 = fma(r0, fma(-dj, r0, 1.0), r0);
+      inv = fma(r0, fma(-dj, r0, 1.0), r0);
+    }
+    double m[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      m[u] = ci[u] * inv;
+      if (u == jb && ty + 16 * u <= j) m[u] = 0.0;  // rows <= j of the pivot block
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      if (u < jb) continue;  // rows <= j are final (uniform)
+#pragma unroll
+      for (int v = 0; v <= u; ++v) a[u][v] = fma(-m[u], w[v], a[u][v]);
+    }
+    // publish step j+1's vector (its entries are final now)
+    const int j1 = j + 1;
+    if (j1 < n) {
+      const int j1b = j1 >> 4, j1l = j1 & 15;
+#pragma unroll
+      for (int v = 0; v < R; ++v) {
+        if (v != j1b) continue;  // uniform
+        if (tx == j1l)
+#pragma unroll
+          for (int u = v; u < R; ++u) {
+            const int i = ty + 16 * u;
+            if (i > j1) nw[i] = a[u][v];
+            if (i == j1) {
+              nw[i] = 0.0;
+              nw[L] = a[u][v];
+            }
+          }
+        if (ty == j1l)
+#pragma unroll
+          for (int c = 0; c <= v; ++c) {
+            const int k = tx + 16 * c;
+            if (k < j1) nw[k] = a[v][c];
+          }
+      }
+    }
+    __syncthreads();
+  }
+  // the pivots d_i sit on the diagonal: gather them through LDS
+  double* dg = buf;  // all reads of the last step are done
+  if (tx == ty)
+#pragma unroll
+    for (int u = 0; u < R; ++u) dg[ty + 16 * u] = a[u][u];
+  __syncthreads();
+  int nbad = 0;
+  double rs[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int i = ty + 16 * u;
+    const double d = i < n ? dg[i] : 1.0;
+    rs[u] = d > thresh ? 1.0 / sqrt(d) : 0.0;
+    if (i < n && !(d > thresh) && tx == 0) ++nbad;
+  }
+  if (nbad) atomicAdd(bad, nbad);
+  // R^-1[c][i] = X_ic / sqrt(d_i) (/ scale of c), X_ic = -S_ic / d_c, X_ii = 1
+#pragma unroll
+  for (int u = 0; u < R; ++u)
+#pragma unroll
+    for (int v = 0; v < R; ++v) {
+      const int i = ty + 16 * u, c = tx + 16 * v;
+      if (i < n && c < n) {
+        double x = 0.0;
+        if (v <= u && c <= i) {
+          const double dc = dg[c];
+          if (c == i)
+            x = rs[u];
+          else
+            x = dc > thresh ? -a[u][v] / dc * rs[u] : 0.0;
+          if (scale) x /= dsc[c];
+        }
+        Ri[(long long)c * ldr + i] = x;
+      }
+    }
+  __syncthreads();
+  if (tid == 0 && P.info) *P.info = *bad;
+}
+
+// R = ceil(max n / 16) of the batch; smaller problems carry zero blocks
+template <int R>
+__global__ __launch_bounds__(NTC) void chol_gj_kernel(SmallBatch b) {
+  __shared__ double buf[2 * (16 * R + 1)];
+  __shared__ double red[4];
+  __shared__ int bad;
+  chol_gj<R>(b.p[blockIdx.x], buf, red, &bad);
+}
+
 __global__ __launch_bounds__(NT) void chol_inv_kernel(SmallBatch b) {
   __shared__ double Lp[kLdsTri];
   __shared__ double Xp[kLdsTri];
@@ -739,6 +925,39 @@ __global__ void gather_cols_kernel(const double* __restrict__ X, int ldx, const 
   U[(long long)r * ldu + c] = s > 0.0 ? X[(long long)r * ldx + perm[c]] / s : 0.0;
 }
 
+// ------------------------------------------------- subspace convergence ----
+// Column residuals of a subspace-iteration step: for the leading k columns,
+// out[0] = max_i |A_i - B_i| and out[1] = max_i |A_i| (A = M Q_r, B its
+// projection on the current left basis).  Both are written as the bit
+// patterns of non-negative doubles with atomic max (the order of the bits is
+// the order of the values); out must be cleared first.
+__global__ __launch_bounds__(256) void col_resid_kernel(const double* __restrict__ A, int lda,
+                                                        const double* __restrict__ B, int ldb, int n,
+                                                        unsigned long long* out) {
+  const int c = blockIdx.x;
+  __shared__ double red[2][4];
+  double d2 = 0.0, a2 = 0.0;
+  for (int r = threadIdx.x; r < n; r += 256) {
+    const double a = A[(long long)r * lda + c], b = B[(long long)r * ldb + c];
+    d2 += (a - b) * (a - b);
+    a2 += a * a;
+  }
+  d2 = wave_sum(d2);
+  a2 = wave_sum(a2);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][w] = d2;
+    red[1][w] = a2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    d2 = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    a2 = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    atomicMax(out, (unsigned long long)__double_as_longlong(sqrt(d2)));
+    atomicMax(out + 1, (unsigned long long)__double_as_longlong(sqrt(a2)));
+  }
+}
+
 // --------------------------------------------------------- truncation ----
 // Merge the two descending spectra (even sector first on ties) and keep
 // k = min(chi, #{s > tau * s_max}) (at least one).  Writes k_even, k_odd,
@@ -863,18 +1082,35 @@ void scale_inv(double* p, size_t n, const double* nrm, hipStream_t s) {
 }
 
 void chol_inv(const std::vector<SmallProb>& probs, hipStream_t s) {
-  // register-resident kernel for n <= 160, the LDS/global one above that
+  // one-elimination register kernel for n <= 224, the LDS/global one above
   std::vector<SmallProb> small, large;
-  for (const SmallProb& p : probs) (p.n <= 160 ? small : large).push_back(p);
+  for (const SmallProb& p : probs) (p.n <= 16 * kGjMaxR ? small : large).push_back(p);
   for (int pass = 0; pass < 2; ++pass) {
     const std::vector<SmallProb>& v = pass == 0 ? small : large;
     for (size_t i = 0; i < v.size(); i += kMaxSmall) {
       SmallBatch b;
       b.n = 0;
       for (size_t j = i; j < v.size() && b.n < kMaxSmall; ++j) b.p[b.n++] = v[j];
-      if (pass == 0)
-        hipLaunchKernelGGL(chol_inv_regs_kernel, dim3(b.n), dim3(NT), 0, s, b);
-      else
+      if (pass == 0) {
+        int nmax = 1;
+        for (int q = 0; q < b.n; ++q) nmax = std::max(nmax, b.p[q].n);
+        switch ((nmax + 15) / 16) {
+          case 1: hipLaunchKernelGGL(chol_gj_kernel<1>, dim3(b.n), dim3(NTC), 0, s, b); break;
+          case 2: hipLaunchKernelGGL(chol_gj_kernel<2>, dim3(b.n), dim3(NTC), 0, s, b); break;
+          case 3: hipLaunchKernelGGL(chol_gj_kernel<3>, dim3(b.n), dim3(NTC), 0, s, b); break;
+          case 4: hipLaunchKernelGGL(chol_gj_kernel<4>, dim3(b.n), dim3(NTC), 0, s, b); break;
+          case 5: hipLaunchKernelGGL(chol_gj_kernel<5>, dim3(b.n), dim3(NTC), 0, s, b); break;
+          case 6: hipLaunchKernelGGL(chol_gj_kernel<6>, dim3(b.n), dim3(NTC), 0, s, b); break;
+          case 7: hipLaunchKernelGGL(chol_gj_kernel<7>, dim3(b.n), dim3(NTC), 0, s, b); break;
+          case 8: hipLaunchKernelGGL(chol_gj_kernel<8>, dim3(b.n), dim3(NTC), 0, s, b); break;
+          case 9: hipLaunchKernelGGL(chol_gj_kernel<9>, dim3(b.n), dim3(NTC), 0, s, b); break;
+          case 10: hipLaunchKernelGGL(chol_gj_kernel<10>, dim3(b.n), dim3(NTC), 0, s, b); break;
+          case 11: hipLaunchKernelGGL(chol_gj_kernel<11>, dim3(b.n), dim3(NTC), 0, s, b); break;
+          case 12: hipLaunchKernelGGL(chol_gj_kernel<12>, dim3(b.n), dim3(NTC), 0, s, b); break;
+          case 13: hipLaunchKernelGGL(chol_gj_kernel<13>, dim3(b.n), dim3(NTC), 0, s, b); break;
+          default: hipLaunchKernelGGL(chol_gj_kernel<14>, dim3(b.n), dim3(NTC), 0, s, b); break;
+        }
+      } else
         hipLaunchKernelGGL(chol_inv_kernel, dim3(b.n), dim3(NT), 0, s, b);
       HCTM_HIP(hipGetLastError());
     }
@@ -925,6 +1161,13 @@ void jacobi(const std::vector<SmallProb>& probs, hipStream_t s) {
     hipLaunchKernelGGL(jacobi_kernel, dim3(b.n), dim3(NT), 0, s, b);
     HCTM_HIP(hipGetLastError());
   }
+}
+
+void col_resid(const double* A, int lda, const double* B, int ldb, int n, int k, double* out, hipStream_t s) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(col_resid_kernel, dim3(k), dim3(256), 0, s, A, lda, B, ldb, n,
+                     reinterpret_cast<unsigned long long*>(out));
+  HCTM_HIP(hipGetLastError());
 }
 
 void gather_cols(const double* X, int ldx, const int* perm, const double* sv, int m, int k, double* U, int ldu,

@@ -61,6 +61,9 @@ void scale_inv(double* p, size_t n, const double* nrm, hipStream_t s);
 void chol_inv(const std::vector<SmallProb>& probs, hipStream_t s);
 void jacobi(const std::vector<SmallProb>& probs, hipStream_t s);
 size_t jacobi_log_doubles(int n, int max_sweeps);
+// out[0] = max_i |A_i - B_i|, out[1] = max_i |A_i| over the first k columns
+// (n rows); out (two doubles) must be zero before
+void col_resid(const double* A, int lda, const double* B, int ldb, int n, int k, double* out, hipStream_t s);
 void gather_cols(const double* X, int ldx, const int* perm, const double* sv, int m, int k, double* U, int ldu,
                  hipStream_t s);
 void select_states(const SelectArgs& a, hipStream_t s);

@@ -88,7 +88,7 @@ def test_copy_is_exact_permutation(hc, shape, perm):
     assert np.array_equal(dY.cpu().numpy().reshape(Y.shape), Y)
 
 
-@pytest.mark.parametrize("n", [1, 12, 33, 64, 65, 100, 142, 160, 200])
+@pytest.mark.parametrize("n", [1, 12, 16, 17, 33, 64, 65, 100, 126, 142, 160, 192, 200, 224, 250])
 def test_cholesky_inverse(hc, n):
     rng = np.random.default_rng(n)
     X = rng.standard_normal((n + 30, n))
