@@ -14,6 +14,7 @@ throughput and their ratio, the live MFMA roofline of the FP64 GEMM kernel
 launches in the timed Z2 region) and the CPU oracle timed on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +27,60 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CTMRG steps/s Z2 vs dense (FP64 vs mixed) at D=6 χ=144; p50/p99 solve latency"
 FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (datasheet)
+GEMM_SOURCE = os.path.join(ROOT, "paper_2410_11596_amd", "csrc", "gemm.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f64_kernel_traffic_D6_chi144.json")
+
+
+def gemm_source_hash():
+    with open(GEMM_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def gemm_traffic():
+    """HBM bytes per GEMM launch measured with the FETCH_SIZE / WRITE_SIZE
+    counters for the current kernel source, or None when there is no
+    measurement of this source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("gemm_source_sha256") != gemm_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def copy_check(nbytes):
+    """A plain device copy of nbytes (read nbytes, write nbytes), three times:
+    the reference the HBM counters are scaled by."""
+    import torch
+
+    from paper_2410_11596_amd import binding
+
+    n = nbytes // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        binding.dev_copy(src, dst, [n], [1], [1])
+    torch.cuda.synchronize()
+    assert bool((dst == 1.0).all())
+
+
+def event_pair_overhead(n=200):
+    """Mean duration of an empty HIP event pair on the current stream, right
+    after a small kernel (the fixed cost inside every timed launch)."""
+    import torch
+
+    x = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t = 0.0
+    for _ in range(n):
+        x.add_(1.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        e1.record()
+        e1.synchronize()
+        t += e0.elapsed_time(e1) * 1e-3
+    return t / n
 
 
 def time_form(A, chi, form, steps, warmup, profile):
@@ -92,6 +147,8 @@ def main():
     ap.add_argument("--chi", type=int, default=144)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--copy-check", type=int, default=0, metavar="BYTES",
+                    help="before timing, copy BYTES three times (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
@@ -103,6 +160,8 @@ def main():
     from paper_2410_11596_amd import inputs
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.copy_check > 0:
+        copy_check(args.copy_check)
     A = inputs.iid_tensor(2, args.D, 0)
     tz, stats, phases, split = time_form(A, args.chi, "z2", args.steps, args.warmup, profile=True)
     z2_rate = args.steps / tz
@@ -132,7 +191,12 @@ def main():
                                zip(["corners", "halves", "svd", "renormalise"], phases.tolist())},
     }
     if stats["launches"] > 0 and stats["seconds"] > 0:
-        achieved = stats["flops"] / stats["seconds"] / 1e12
+        # mean algorithmic flops per launch over the mean launch duration; an
+        # event pair costs a fixed few microseconds even around no work, which
+        # is measured on the same stream and taken off every launch
+        ev = event_pair_overhead()
+        kernel_s = stats["seconds"] - stats["launches"] * ev
+        achieved = stats["flops"] / kernel_s / 1e12
         out["roofline"] = {
             "bound": "mfma",
             "kernel": "gemm_f64_kernel",
@@ -140,8 +204,12 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": gemm_traffic(),
             "launches": stats["launches"],
+            "flops_per_launch": stats["flops"] / stats["launches"],
+            "avg_launch_us": 1e6 * kernel_s / stats["launches"],
+            "event_pair_overhead_us": 1e6 * ev,
+            "achieved_uncorrected": stats["flops"] / stats["seconds"] / 1e12,
             "gemm_share_of_step": stats["seconds"] / tz,
         }
     if not args.no_dense:
