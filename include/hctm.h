@@ -159,11 +159,13 @@ int ctm_num_records(ctm_ctx* c, int* n);
  * Record of truncation m (0-based, in the order run): the kept singular
  * values of the decomposed matrix, merged over both sectors in descending
  * order and divided by the largest, and the kept sector sizes.  s: host array
- * of at least cap doubles.  where (may be NULL): 3 ints, the frame of the
- * move (0 left, 1 top, 2 right, 3 bottom), the column swept and the row of
- * the cut, in the coordinates of that frame.
+ * of at least cap doubles.  info (may be NULL): 7 ints, the frame of the move
+ * (0 left, 1 top, 2 right, 3 bottom), the column swept and the row of the cut
+ * in the coordinates of that frame, then for the even and the odd sector the
+ * subspace iterations run (0: the block was decomposed directly) and the
+ * Jacobi sweeps of the final small SVD.
  */
-int ctm_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, int* k_odd, int* where);
+int ctm_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, int* k_odd, int* info);
 
 /* Current boundary bond on side 0..3 (top, right, bottom, left) of site
  * (x, y): the bond of the edge tensor's first leg (T1's left, T2's up, T3's

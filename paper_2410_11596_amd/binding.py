@@ -264,11 +264,11 @@ class CTMRG:
         cap = 8192
         s = np.zeros(cap)
         n, ke, ko = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        where = (ctypes.c_int * 3)()
+        info = (ctypes.c_int * 7)()
         _check(lib().ctm_record(self._ctx, m, _dptr(s), cap, ctypes.byref(n), ctypes.byref(ke), ctypes.byref(ko),
-                                where), self._ctx)
-        return {"spectrum": s[: n.value].copy(), "kept": (ke.value, ko.value), "frame": where[0],
-                "column": where[1], "row": where[2]}
+                                info), self._ctx)
+        return {"spectrum": s[: n.value].copy(), "kept": (ke.value, ko.value), "frame": info[0],
+                "column": info[1], "row": info[2], "iters": (info[3], info[4]), "sweeps": (info[5], info[6])}
 
     def records(self):
         return [self.record(m) for m in range(self.num_records())]

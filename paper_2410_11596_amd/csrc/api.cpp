@@ -219,7 +219,7 @@ int ctm_num_records(ctm_ctx* c, int* n) {
   return CTM_OK;
 }
 
-int ctm_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, int* k_odd, int* where) {
+int ctm_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, int* k_odd, int* info) {
   if (!c) return CTM_E_ARG;
   return guarded(c, [&] {
     const auto& r = c->ctm->records();
@@ -229,10 +229,14 @@ int ctm_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, int* 
     if (n) *n = ns;
     if (k_even) *k_even = rec.k_even;
     if (k_odd) *k_odd = rec.k_odd;
-    if (where) {
-      where[0] = rec.frame;
-      where[1] = rec.column;
-      where[2] = rec.row;
+    if (info) {
+      info[0] = rec.frame;
+      info[1] = rec.column;
+      info[2] = rec.row;
+      info[3] = rec.iters[0];
+      info[4] = rec.iters[1];
+      info[5] = rec.sweeps[0];
+      info[6] = rec.sweeps[1];
     }
     if (s)
       for (int i = 0; i < ns && i < cap; ++i) s[i] = rec.spectrum[i];

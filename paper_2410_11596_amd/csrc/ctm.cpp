@@ -532,6 +532,8 @@ void Ctm::truncated_svd(BT& M, int chi, int key, uint64_t salt) {
       S.n = (int)M.L.rows[P];
       S.Mp = M.p + M.L.off[P];
       S.k = 0;
+      S.iters = 0;
+      S.sweeps = 0;
       S.warm = false;
       S.fin = false;
       S.done = false;
@@ -676,8 +678,10 @@ void Ctm::truncated_svd(BT& M, int chi, int key, uint64_t salt) {
         launch_gemms(g);
         orth(act, false);  // Qr; Y keeps Z = M^T Ql
         std::vector<SvdSector*> next;
-        for (SvdSector* S : act)
+        for (SvdSector* S : act) {
+          S->iters = t + 1;
           if (!S->fin) next.push_back(S);
+        }
         act.swap(next);
       }
       // B = Z^T Qr = Ql^T M Qr
@@ -918,6 +922,10 @@ void Ctm::move(int r) {
       rec.frame = r;
       rec.column = X;
       rec.row = Y;
+      for (int P = 0; P < 2; ++P) {
+        rec.iters[P] = sec_[P].iters;
+        rec.sweeps[P] = sec_[P].sweeps;
+      }
       for (int P = 0; P < 2; ++P)
         for (int i = 0; i < sec_[P].k; ++i) rec.spectrum.push_back(host_d_[2048 * P + i]);
       std::sort(rec.spectrum.begin(), rec.spectrum.end(), [](double a, double b) { return a > b; });

@@ -30,6 +30,8 @@ struct MoveRecord {
   std::vector<double> spectrum;  // kept values, merged, descending, / largest
   int k_even = 0, k_odd = 0;
   int frame = 0, column = 0, row = 0;
+  int iters[2] = {0, 0};   // subspace iterations per sector (0: decomposed directly)
+  int sweeps[2] = {0, 0};  // Jacobi sweeps per sector
 };
 
 constexpr int kMaxCell = 4;  // Lx, Ly <= kMaxCell
@@ -52,7 +54,7 @@ struct GemmStats {
 
 // per-sector state of the truncated SVD
 struct SvdSector {
-  int n = 0, l = 0, kg = 0, trusted = 0, k = 0, sweeps = 0;
+  int n = 0, l = 0, kg = 0, trusted = 0, k = 0, sweeps = 0, iters = 0;
   int passes = 1;        // CholeskyQR passes of the next orthonormalisation
   double rel0 = 1e-10;   // relative diagonal shift of its first pass
   bool direct = false;

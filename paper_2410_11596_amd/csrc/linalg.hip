@@ -745,20 +745,36 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(SmallBatch b) {
 // the right vectors can be rebuilt in parallel afterwards (jacobi_v_kernel).
 constexpr int kJacLds = 19968;  // doubles of LDS for X (n = m <= 141)
 
+// Sum over the 16 lanes of a DPP row, result in every lane: swap neighbours,
+// swap pairs (quad permutations), then the mirrored half row and row.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ double sum16(double v) {
-#pragma unroll
-  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
   return v;
 }
 
+// Round-robin pairing of n2 (even) columns: round r pairs column n2-1 with r
+// and (r + p) with (r - p) modulo n2 - 1 for p = 1 .. n2/2 - 1.
 __device__ __forceinline__ void rr_pair(int r, int pp, int n2, int& i, int& j) {
   const int mr = n2 - 1;
   if (pp == 0) {
     i = r;
     j = n2 - 1;
   } else {
-    i = (r + pp) % mr;
-    j = (r - pp + mr) % mr;
+    i = r + pp;
+    if (i >= mr) i -= mr;
+    j = r - pp;
+    if (j < 0) j += mr;
   }
   if (i > j) {
     const int t = i;
@@ -767,6 +783,11 @@ __device__ __forceinline__ void rr_pair(int r, int pp, int n2, int& i, int& j) {
   }
 }
 
+// One pair of 16 lanes per column pair; each lane keeps its rows of the two
+// columns in registers between the dot product and the rotation.  Squared
+// column norms are kept in LDS and recomputed only for the columns a
+// rotation changed, so a round needs one dot product per pair.
+constexpr int kJacRows = 10;  // rows per lane, m <= 160
 __global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
   __shared__ double Xs[kJacLds];
   __shared__ int any_rot;
@@ -794,6 +815,12 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
   int sweep = 0;
   for (sweep = 0; sweep < P.max_sweeps; ++sweep) {
     if (tid == 0) any_rot = 0;
+    if (sweep == 0)
+      for (int j = tid; j < n; j += NT) {
+        double s2 = 0.0;
+        for (int k = 0; k < m; ++k) s2 += Xs[j * m + k] * Xs[j * m + k];
+        nrm[j] = s2;
+      }
     __syncthreads();
     for (int r = 0; r < rounds; ++r) {
       double2* lg = rlog ? reinterpret_cast<double2*>(rlog) + ((long long)sweep * rounds + r) * npairs : nullptr;
@@ -804,27 +831,45 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
         if (j < n) {
           double* xi = Xs + i * m;
           double* xj = Xs + j * m;
-          double a = 0.0, bb = 0.0, g = 0.0;
-          for (int k = sub; k < m; k += 16) {
-            const double u = xi[k], v = xj[k];
-            a += u * u;
-            bb += v * v;
-            g += u * v;
+          double u[kJacRows], v[kJacRows];
+          double g = 0.0;
+#pragma unroll
+          for (int q = 0; q < kJacRows; ++q) {
+            const int k = sub + 16 * q;
+            u[q] = k < m ? xi[k] : 0.0;
+            v[q] = k < m ? xj[k] : 0.0;
+            g = fma(u[q], v[q], g);
           }
-          a = sum16(a);
-          bb = sum16(bb);
           g = sum16(g);
+          const double a = nrm[i], bb = nrm[j];
+          // sqrt(a) sqrt(b), not sqrt(a b): near-zero blocks (a sector that
+          // the state leaves empty up to rounding) would underflow the product
           if (fmin(a, bb) > small2 && fabs(g) > tol * sqrt(a) * sqrt(bb)) {
             const double zeta = (bb - a) / (2.0 * g);
             const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             c = 1.0 / sqrt(1.0 + t * t);
             sn = c * t;
-            for (int k = sub; k < m; k += 16) {
-              const double u = xi[k], v = xj[k];
-              xi[k] = c * u - sn * v;
-              xj[k] = sn * u + c * v;
+            double a2 = 0.0, b2 = 0.0;
+#pragma unroll
+            for (int q = 0; q < kJacRows; ++q) {
+              const int k = sub + 16 * q;
+              const double x = c * u[q] - sn * v[q], y = sn * u[q] + c * v[q];
+              if (k < m) {
+                xi[k] = x;
+                xj[k] = y;
+              }
+              a2 = fma(x, x, a2);
+              b2 = fma(y, y, b2);
             }
-            if (sub == 0) any_rot = 1;
+            // exact norms of the rotated columns (the update a - t g loses
+            // relative accuracy when a column is nearly emptied)
+            a2 = sum16(a2);
+            b2 = sum16(b2);
+            if (sub == 0) {
+              nrm[i] = a2;
+              nrm[j] = b2;
+              any_rot = 1;
+            }
           }
         }
         if (sub == 0 && rlog) lg[pp] = make_double2(c, sn);
@@ -840,9 +885,9 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
   }
   if (tid == 0 && P.info) *P.info = (sweep <= P.max_sweeps && !any_rot) ? sweep : -sweep;
   for (int j = tid; j < n; j += NT) {
-    double s = 0.0;
-    for (int k = 0; k < m; ++k) s += Xs[j * m + k] * Xs[j * m + k];
-    nrm[j] = sqrt(s);
+    double s2 = 0.0;
+    for (int k = 0; k < m; ++k) s2 += Xs[j * m + k] * Xs[j * m + k];
+    nrm[j] = sqrt(s2);
   }
   for (int e = tid; e < m * n; e += NT) {
     const int r = e / n, c = e % n;
@@ -862,51 +907,54 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
 }
 
 // Rebuild V (n x n, row-major, written to P.a) from the rotation log in
-// P.b: rows are independent, 32 rows per workgroup held column-major in LDS;
-// the log is staged 16 rounds at a time so that each round reads LDS only.
+// P.b: rows are independent, kVRows rows per workgroup held column-major in
+// LDS; the log is staged kVChunk rounds at a time so that each round reads
+// LDS only.
 constexpr int kVChunk = 16;
+constexpr int kVRows = 8;
 __global__ __launch_bounds__(256) void jacobi_v_kernel(SmallBatch b) {
-  __shared__ double Vs[160 * 32];
+  __shared__ double Vs[160 * kVRows];
   __shared__ double2 Ls[kVChunk * 80];
   const SmallProb& P = b.p[blockIdx.y];
   const int n = P.n;
   const int sweeps = P.info ? abs(*P.info) : 0;
   const double2* lg = reinterpret_cast<const double2*>(P.b);
   double* V = P.a;
-  const int r0 = blockIdx.x * 32;
+  const int r0 = blockIdx.x * kVRows;
   if (r0 >= n) return;
-  const int rows = min(32, n - r0);
-  for (int e = threadIdx.x; e < 32 * n; e += 256) {
-    const int c = e / 32, rr = e % 32;
-    Vs[c * 32 + rr] = (r0 + rr == c) ? 1.0 : 0.0;
+  const int rows = min(kVRows, n - r0);
+  for (int e = threadIdx.x; e < kVRows * n; e += 256) {
+    const int c = e / kVRows, rr = e % kVRows;
+    Vs[c * kVRows + rr] = (r0 + rr == c) ? 1.0 : 0.0;
   }
   const int n2 = n + (n & 1), npairs = n2 / 2, rounds = n2 - 1;
   const long long total = (long long)sweeps * rounds;
+  int r = 0;
   for (long long t0 = 0; t0 < total; t0 += kVChunk) {
     const int nr = (int)min<long long>(kVChunk, total - t0);
     __syncthreads();
     for (int e = threadIdx.x; e < nr * npairs; e += 256) Ls[e] = lg[t0 * npairs + e];
     __syncthreads();
     for (int q = 0; q < nr; ++q) {
-      const int r = (int)((t0 + q) % rounds);
-      for (int e = threadIdx.x; e < npairs * 32; e += 256) {
-        const int pp = e / 32, rr = e % 32;
+      for (int e = threadIdx.x; e < npairs * kVRows; e += 256) {
+        const int pp = e / kVRows, rr = e % kVRows;
         const double2 cs = Ls[q * npairs + pp];
         if (cs.y == 0.0 || rr >= rows) continue;
         int i, j;
         rr_pair(r, pp, n2, i, j);
         if (j >= n) continue;
-        const double u = Vs[i * 32 + rr], v = Vs[j * 32 + rr];
-        Vs[i * 32 + rr] = cs.x * u - cs.y * v;
-        Vs[j * 32 + rr] = cs.y * u + cs.x * v;
+        const double u = Vs[i * kVRows + rr], v = Vs[j * kVRows + rr];
+        Vs[i * kVRows + rr] = cs.x * u - cs.y * v;
+        Vs[j * kVRows + rr] = cs.y * u + cs.x * v;
       }
+      if (++r == rounds) r = 0;
       __syncthreads();
     }
   }
   __syncthreads();
   for (int e = threadIdx.x; e < rows * n; e += 256) {
     const int rr = e / n, c = e % n;
-    V[(long long)(r0 + rr) * n + c] = Vs[c * 32 + rr];
+    V[(long long)(r0 + rr) * n + c] = Vs[c * kVRows + rr];
   }
 }
 
@@ -1150,7 +1198,7 @@ void jacobi(const std::vector<SmallProb>& probs, hipStream_t s) {
     hipLaunchKernelGGL(jacobi_lds_kernel, dim3(b.n), dim3(NT), 0, s, b);
     HCTM_HIP(hipGetLastError());
     if (bv.n > 0) {
-      hipLaunchKernelGGL(jacobi_v_kernel, dim3((nmax + 31) / 32, bv.n), dim3(256), 0, s, bv);
+      hipLaunchKernelGGL(jacobi_v_kernel, dim3((nmax + kVRows - 1) / kVRows, bv.n), dim3(256), 0, s, bv);
       HCTM_HIP(hipGetLastError());
     }
   }
