@@ -70,7 +70,11 @@ typedef struct {
                                   b = sum_k |k k> (the open boundary).  In the Z2
                                   form b must be swap symmetric, b[k*D+l] = b[l*D+k]. */
   double svd_rel_cutoff;       /* keep singular values > cutoff * largest (default 1e-12) */
-  int svd_iters;               /* subspace iterations per truncated SVD (default 12) */
+  int svd_iters;               /* at most this many subspace iterations per truncated
+                                  SVD (default 12); fewer once the basis has converged */
+  int form_m;                  /* 0 (default): apply the decomposed matrix through the
+                                  enlarged corners when few iterations are expected;
+                                  1: always form it (H_d H_u) first */
   unsigned long long seed;     /* seed of the subspace-iteration start blocks */
   int profile;                 /* 1: time every GEMM launch with HIP events (ctm_gemm_stats) */
   void* stream;                /* hipStream_t or NULL */
@@ -159,11 +163,12 @@ int ctm_num_records(ctm_ctx* c, int* n);
  * Record of truncation m (0-based, in the order run): the kept singular
  * values of the decomposed matrix, merged over both sectors in descending
  * order and divided by the largest, and the kept sector sizes.  s: host array
- * of at least cap doubles.  info (may be NULL): 7 ints, the frame of the move
+ * of at least cap doubles.  info (may be NULL): 8 ints, the frame of the move
  * (0 left, 1 top, 2 right, 3 bottom), the column swept and the row of the cut
  * in the coordinates of that frame, then for the even and the odd sector the
  * subspace iterations run (0: the block was decomposed directly) and the
- * Jacobi sweeps of the final small SVD.
+ * Jacobi sweeps of the final small SVD, and 1 if the matrix was applied
+ * through the enlarged corners instead of being formed (see form_m).
  */
 int ctm_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, int* k_odd, int* info);
 

@@ -35,6 +35,7 @@ class CtmOpts(ctypes.Structure):
         ("boundary", ctypes.POINTER(ctypes.c_double)),
         ("svd_rel_cutoff", ctypes.c_double),
         ("svd_iters", ctypes.c_int),
+        ("form_m", ctypes.c_int),
         ("seed", ctypes.c_ulonglong),
         ("profile", ctypes.c_int),
         ("stream", ctypes.c_void_p),
@@ -154,7 +155,7 @@ class CTMRG:
     """
 
     def __init__(self, A, chi, form="z2", boundary=None, svd_rel_cutoff=1e-12, svd_iters=12, seed=0x5EED,
-                 stream=None, torch_workspace=True, profile=False):
+                 stream=None, torch_workspace=True, profile=False, form_m=False):
         torch = _torch()
         A = _cell_array(A)
         self.Ly, self.Lx = A.shape[0], A.shape[1]
@@ -166,6 +167,7 @@ class CTMRG:
         o.Lx, o.Ly = self.Lx, self.Ly
         o.svd_rel_cutoff = svd_rel_cutoff
         o.svd_iters = svd_iters
+        o.form_m = 1 if form_m else 0
         o.seed = seed
         o.profile = 1 if profile else 0
         self._b = None
@@ -264,11 +266,12 @@ class CTMRG:
         cap = 8192
         s = np.zeros(cap)
         n, ke, ko = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        info = (ctypes.c_int * 7)()
+        info = (ctypes.c_int * 8)()
         _check(lib().ctm_record(self._ctx, m, _dptr(s), cap, ctypes.byref(n), ctypes.byref(ke), ctypes.byref(ko),
                                 info), self._ctx)
         return {"spectrum": s[: n.value].copy(), "kept": (ke.value, ko.value), "frame": info[0],
-                "column": info[1], "row": info[2], "iters": (info[3], info[4]), "sweeps": (info[5], info[6])}
+                "column": info[1], "row": info[2], "iters": (info[3], info[4]), "sweeps": (info[5], info[6]),
+                "implicit": bool(info[7])}
 
     def records(self):
         return [self.record(m) for m in range(self.num_records())]

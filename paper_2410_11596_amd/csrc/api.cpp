@@ -59,6 +59,8 @@ hctm::Options to_options(const ctm_opts* o, int D) {
   opt.tau = o->svd_rel_cutoff;
   if (o->svd_iters < 1 || o->svd_iters > 1000) throw hctm::Error(CTM_E_ARG, "svd_iters out of range");
   opt.svd_iters = o->svd_iters;
+  if (o->form_m != 0 && o->form_m != 1) throw hctm::Error(CTM_E_ARG, "form_m must be 0 or 1");
+  opt.form_m = o->form_m;
   opt.seed = o->seed;
   opt.profile = o->profile ? 1 : 0;
   if (o->boundary) {
@@ -99,6 +101,7 @@ int ctm_opts_default(ctm_opts* o) {
   o->boundary = nullptr;
   o->svd_rel_cutoff = 1e-12;
   o->svd_iters = 12;
+  o->form_m = 0;
   o->seed = 0x5eedull;
   return CTM_OK;
 }
@@ -237,6 +240,7 @@ int ctm_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, int* 
       info[4] = rec.iters[1];
       info[5] = rec.sweeps[0];
       info[6] = rec.sweeps[1];
+      info[7] = rec.implicit;
     }
     if (s)
       for (int i = 0; i < ns && i < cap; ++i) s[i] = rec.spectrum[i];

@@ -44,6 +44,9 @@ constexpr int kDirectMax = 160;  // sectors up to this size are decomposed direc
 constexpr int kJacobiSweeps = 40;
 // relative residual of the leading columns that ends the subspace iteration
 constexpr double kSubspaceTol = 1e-12;
+// apply M through the corners when the cut's last truncation took at most
+// this many subspace iterations (forming M costs about as much as 8 of them)
+constexpr int kImplicitIters = 7;
 }
 
 // ------------------------------------------------------------- memory ----
@@ -139,6 +142,7 @@ void Ctm::plan_memory(bool counting) {
     Pb_[Y].capacity = proj_cap_;
   }
   kg_.assign(4 * kMaxCell * kMaxCell, std::array<int, 2>{0, 0});
+  iters_prev_.assign(4 * kMaxCell * kMaxCell, 0);
   // right vectors of the last truncation of every cut (warm starts)
   warm_cap_ = ncap * cc;
   warm_.assign(2 * 4 * kMaxCell * kMaxCell, WarmV());
@@ -155,6 +159,8 @@ void Ctm::plan_memory(bool counting) {
     S.Y = ar_.take((size_t)(ncap * lcap));
     S.Tm = ar_.take((size_t)(ncap * lcap));
     S.Qold = ar_.take((size_t)(ncap * lcap));
+    S.C1 = ar_.take((size_t)(ncap * lcap));
+    S.C2 = ar_.take((size_t)(ncap * lcap));
     S.G = ar_.take((size_t)(lcap * lcap));
     S.Ri = ar_.take((size_t)(lcap * lcap));
     S.B = ar_.take((size_t)(lcap * lcap));
@@ -514,6 +520,61 @@ void Ctm::orth(std::vector<SvdSector*>& ss, bool ql) {
   }
 }
 
+// Y = M Qr (trans = false) or Y = M^T Ql (trans = true) for every sector of
+// ss.  With the matrix formed this is one block product; otherwise M is
+// applied as the chain Q3 Q4 Q1 Q2 of the four enlarged corners (transposed
+// and reversed for M^T), which costs 8 n^2 l per application instead of the
+// 6 n^3 of forming H_u, H_d and M.
+void Ctm::apply_M(std::vector<SvdSector*>& ss, bool trans) {
+  std::vector<GemmDesc> g;
+  if (!implicit_) {
+    for (SvdSector* S : ss) {
+      GemmDesc d{};
+      d.A = S->Mp;
+      d.B = trans ? S->Ql : S->Qr;
+      d.C = S->Y;
+      d.M = S->n;
+      d.N = S->l;
+      d.K = S->n;
+      d.lda = S->n;
+      d.ldb = S->l;
+      d.ldc = S->l;
+      d.ta = trans ? 1 : 0;
+      d.alpha = 1.0;
+      g.push_back(d);
+    }
+    launch_gemms(g);
+    return;
+  }
+  static const int order_n[4] = {1, 0, 3, 2};  // Q2, then Q1, Q4, Q3
+  static const int order_t[4] = {2, 3, 0, 1};  // Q3^T, then Q4^T, Q1^T, Q2^T
+  for (int step = 0; step < 4; ++step) {
+    const int qi = trans ? order_t[step] : order_n[step];
+    const BT& Q = *impl_q_[qi];
+    for (size_t c = 0; c < ss.size(); ++c) {
+      SvdSector* S = ss[c];
+      const int P = S == &sec_[1] ? 1 : 0;
+      const double* src = step == 0 ? (trans ? S->Ql : S->Qr) : ((step % 2 == 1) ? S->C1 : S->C2);
+      double* dst = step == 3 ? S->Y : ((step % 2 == 0) ? S->C1 : S->C2);
+      const int rows = (int)Q.L.rows[P], cols = (int)Q.L.cols[P];
+      GemmDesc d{};
+      d.A = Q.p + Q.L.off[P];
+      d.B = src;
+      d.C = dst;
+      d.M = trans ? cols : rows;
+      d.N = S->l;
+      d.K = trans ? rows : cols;
+      d.lda = (int)Q.L.ld(P);
+      d.ldb = S->l;
+      d.ldc = S->l;
+      d.ta = trans ? 1 : 0;
+      d.alpha = 1.0;
+      g.push_back(d);
+    }
+    launch_gemms(g);
+  }
+}
+
 // Truncated SVD of both sector blocks of M (batched): randomized subspace
 // iteration, Rayleigh-Ritz and one-sided Jacobi, or Jacobi on the block itself
 // when it is small.  key selects the cut: its previous kept count guesses the
@@ -523,14 +584,16 @@ void Ctm::orth(std::vector<SvdSector*>& ss, bool ql) {
 // relative to the largest); its last iterate is re-orthonormalised to
 // rounding.  At most the configured number of iterations run.  salt makes the
 // random blocks differ between cuts.
-void Ctm::truncated_svd(BT& M, int chi, int key, uint64_t salt) {
+void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
   int* kg_io = kg_[key].data();
+  implicit_ = M == nullptr;
   for (int attempt = 0; attempt < 4; ++attempt) {
     std::vector<SvdSector*> sub, all;
     for (int P = 0; P < 2; ++P) {
       SvdSector& S = sec_[P];
-      S.n = (int)M.L.rows[P];
-      S.Mp = M.p + M.L.off[P];
+      // M acts on the east cut: H_d H_u = Q3 Q4 Q1 Q2
+      S.n = implicit_ ? (int)impl_q_[1]->L.cols[P] : (int)M->L.rows[P];
+      S.Mp = implicit_ ? nullptr : M->p + M->L.off[P];
       S.k = 0;
       S.iters = 0;
       S.sweeps = 0;
@@ -548,6 +611,7 @@ void Ctm::truncated_svd(BT& M, int chi, int key, uint64_t salt) {
       S.l = std::min<int>(std::min(S.n, kg + p), l_cap_);
       S.direct = S.n <= kDirectMax || S.l >= S.n;
       if (S.direct && S.n > l_cap_) throw Error(1, "truncated_svd: sector too large for a direct decomposition");
+      if (S.direct && implicit_) throw Error(1, "truncated_svd: a direct decomposition needs the matrix");
       if (S.direct) S.l = S.n;
       S.trusted = S.direct ? S.n : S.l - p / 2;
       all.push_back(&S);
@@ -588,22 +652,8 @@ void Ctm::truncated_svd(BT& M, int chi, int key, uint64_t salt) {
       const int T = std::max(1, opt_.svd_iters);
       std::vector<SvdSector*> act = sub;
       for (int t = 0; t < T && !act.empty(); ++t) {
+        apply_M(act, false);  // Y = M Qr
         std::vector<GemmDesc> g;
-        for (SvdSector* S : act) {
-          GemmDesc d{};
-          d.A = S->Mp;
-          d.B = S->Qr;
-          d.C = S->Y;
-          d.M = S->n;
-          d.N = S->l;
-          d.K = S->n;
-          d.lda = S->n;
-          d.ldb = S->l;
-          d.ldc = S->l;
-          d.alpha = 1.0;
-          g.push_back(d);
-        }
-        launch_gemms(g);
         for (SvdSector* S : act) S->fin = t == T - 1;
         if (t >= 1) {
           std::vector<SvdSector*> chk = act;
@@ -660,22 +710,7 @@ void Ctm::truncated_svd(BT& M, int chi, int key, uint64_t salt) {
           S->rel0 = (S->warm || t >= 3) ? 1e-14 : 1e-10;
         }
         orth(act, true);  // Ql
-        for (SvdSector* S : act) {
-          GemmDesc d{};
-          d.A = S->Mp;
-          d.B = S->Ql;
-          d.C = S->Y;
-          d.M = S->n;
-          d.N = S->l;
-          d.K = S->n;
-          d.lda = S->n;
-          d.ldb = S->l;
-          d.ldc = S->l;
-          d.ta = 1;
-          d.alpha = 1.0;
-          g.push_back(d);
-        }
-        launch_gemms(g);
+        apply_M(act, true);  // Y = M^T Ql
         orth(act, false);  // Qr; Y keeps Z = M^T Ql
         std::vector<SvdSector*> next;
         for (SvdSector* S : act) {
@@ -860,16 +895,37 @@ void Ctm::move(int r) {
       BT& Q2 = quad(site_of(r, X + 1, Y), r + 1);
       BT& Q3 = quad(site_of(r, X + 1, Y + 1), r + 2);
       BT& Q4 = quad(site_of(r, X, Y + 1), r + 3);
-      {
+      const int key = (r * kMaxCell + X) * kMaxCell + Y;
+      // Form H_u, H_d and M only when the subspace iteration is expected to
+      // be long (the last truncation at this cut needed many iterations) or
+      // a sector is small enough to be decomposed directly; otherwise apply
+      // M through the corners.
+      bool implicit = !opt_.form_m && iters_prev_[key] > 0 && iters_prev_[key] <= kImplicitIters;
+      for (int P = 0; P < 2; ++P) {
+        const int n = (int)Q2.L.cols[P];
+        if (n == 0) continue;
+        const int kg = kg_[key][P] > 0 ? std::min(kg_[key][P], n) : std::min(chi_, n);
+        const int l = std::min(std::min(n, kg + std::max(32, kg / 2)), l_cap_);
+        if (n <= kDirectMax || l >= n) implicit = false;
+      }
+      if (implicit) {
+        impl_q_[0] = &Q1;
+        impl_q_[1] = &Q2;
+        impl_q_[2] = &Q3;
+        impl_q_[3] = &Q4;
+        mark(2);
+        truncated_svd(nullptr, chi_, key, (uint64_t)records_.size());
+      } else {
         std::vector<GemmDesc> g;
         plan_contract(Q1, Q2, Hu_, 1.0, 0.0, g);
         plan_contract(Q3, Q4, Hd_, 1.0, 0.0, g);
         launch_gemms(g);
         plan_contract(Hd_, Hu_, M_, 1.0, 0.0, g);
         launch_gemms(g);
+        mark(2);
+        truncated_svd(&M_, chi_, key, (uint64_t)records_.size());
       }
-      mark(2);
-      truncated_svd(M_, chi_, (r * kMaxCell + X) * kMaxCell + Y, (uint64_t)records_.size());
+      iters_prev_[key] = std::max(sec_[0].iters, sec_[1].iters);
       mark(3);
 
       // projectors of this cut
@@ -881,7 +937,70 @@ void Ctm::move(int r) {
       Pb.L = Layout({kn, lW, lq_}, 1);
       if (Pa.L.size > proj_cap_ || Pb.L.size > proj_cap_) throw Error(2, "projector capacity");
       std::vector<GemmDesc> g;
-      for (int P = 0; P < 2; ++P) {
+      if (implicit) {
+        // P_a = Q1 (Q2 V) S^-1/2, P_b = S^-1/2 (W^T Q3) Q4
+        for (int P = 0; P < 2; ++P) {
+          SvdSector& S = sec_[P];
+          if (S.k == 0) continue;
+          GemmDesc d{};
+          d.A = Q2.p + Q2.L.off[P];
+          d.B = S.V;
+          d.C = S.C1;
+          d.M = (int)Q2.L.rows[P];
+          d.N = S.k;
+          d.K = (int)Q2.L.cols[P];
+          d.lda = (int)Q2.L.ld(P);
+          d.ldb = S.k;
+          d.ldc = S.k;
+          d.alpha = 1.0;
+          g.push_back(d);
+          GemmDesc e{};
+          e.A = S.W;
+          e.B = Q3.p + Q3.L.off[P];
+          e.C = S.C2;
+          e.M = S.k;
+          e.N = (int)Q3.L.cols[P];
+          e.K = (int)Q3.L.rows[P];
+          e.lda = S.k;
+          e.ldb = (int)Q3.L.ld(P);
+          e.ldc = (int)Q3.L.cols[P];
+          e.ta = 1;
+          e.alpha = 1.0;
+          g.push_back(e);
+        }
+        launch_gemms(g);
+        for (int P = 0; P < 2; ++P) {
+          SvdSector& S = sec_[P];
+          if (S.k == 0) continue;
+          GemmDesc d{};
+          d.A = Q1.p + Q1.L.off[P];
+          d.B = S.C1;
+          d.C = Pa.p + Pa.L.off[P];
+          d.M = (int)Q1.L.rows[P];
+          d.N = S.k;
+          d.K = (int)Q1.L.cols[P];
+          d.lda = (int)Q1.L.ld(P);
+          d.ldb = S.k;
+          d.ldc = S.k;
+          d.alpha = 1.0;
+          d.cscale = S.isq;
+          g.push_back(d);
+          GemmDesc e{};
+          e.A = S.C2;
+          e.B = Q4.p + Q4.L.off[P];
+          e.C = Pb.p + Pb.L.off[P];
+          e.M = S.k;
+          e.N = (int)Q4.L.cols[P];
+          e.K = (int)Q4.L.rows[P];
+          e.lda = (int)Q3.L.cols[P];
+          e.ldb = (int)Q4.L.ld(P);
+          e.ldc = (int)Q4.L.cols[P];
+          e.alpha = 1.0;
+          e.rscale = S.isq;
+          g.push_back(e);
+        }
+      }
+      for (int P = 0; P < 2 && !implicit; ++P) {
         SvdSector& S = sec_[P];
         if (S.k == 0) continue;
         const int nW = (int)Hu_.L.rows[P], nE = (int)Hu_.L.cols[P];
@@ -922,6 +1041,7 @@ void Ctm::move(int r) {
       rec.frame = r;
       rec.column = X;
       rec.row = Y;
+      rec.implicit = implicit ? 1 : 0;
       for (int P = 0; P < 2; ++P) {
         rec.iters[P] = sec_[P].iters;
         rec.sweeps[P] = sec_[P].sweeps;

@@ -32,6 +32,7 @@ struct MoveRecord {
   int frame = 0, column = 0, row = 0;
   int iters[2] = {0, 0};   // subspace iterations per sector (0: decomposed directly)
   int sweeps[2] = {0, 0};  // Jacobi sweeps per sector
+  int implicit = 0;        // 1: the matrix was applied through the corners
 };
 
 constexpr int kMaxCell = 4;  // Lx, Ly <= kMaxCell
@@ -42,6 +43,7 @@ struct Options {
   std::vector<double> boundary;
   double tau = 1e-12;
   int svd_iters = 12;
+  int form_m = 0;  // 1: always form the decomposed matrix
   unsigned long long seed = 0x5eed;
   int profile = 0;  // 1: time every GEMM launch with HIP events
 };
@@ -64,6 +66,7 @@ struct SvdSector {
   const double* Mp = nullptr;  // sector block of M (n x n, ld = n)
   double *Qr = nullptr, *Ql = nullptr, *Y = nullptr, *Tm = nullptr;
   double* Qold = nullptr;  // projection of Y on the previous left basis (check)
+  double *C1 = nullptr, *C2 = nullptr;  // intermediates of M applied through the corners
   double *G = nullptr, *Ri = nullptr, *B = nullptr, *Bj = nullptr;
   double *Ub = nullptr, *Vb = nullptr, *Wbuf = nullptr, *Vbuf = nullptr;
   const double *W = nullptr, *V = nullptr;  // kept vectors (n x k) of M_P
@@ -114,7 +117,8 @@ class Ctm {
   void quadrant(int s, int o);
   void move(int r);
   void mark(int phase);
-  void truncated_svd(BT& M, int chi, int key, uint64_t salt);
+  void truncated_svd(const BT* M, int chi, int key, uint64_t salt);  // M null: apply via impl_q_
+  void apply_M(std::vector<SvdSector*>& ss, bool trans);
   void orth(std::vector<SvdSector*>& ss, bool ql);
   void corner_spectra();
   void compute_epsilon_rot(int s);  // eps~ of site s into eps_ (layout [U L | Dn R])
@@ -161,6 +165,9 @@ class Ctm {
   long long proj_cap_ = 0;
   SvdSector sec_[2];
   std::vector<std::array<int, 2>> kg_;  // kept-state guess per (frame, column, row)
+  std::vector<int> iters_prev_;           // subspace iterations of the last truncation per cut
+  bool implicit_ = false;                 // M applied through the corners impl_q_
+  const BT* impl_q_[4] = {nullptr, nullptr, nullptr, nullptr};
   struct WarmV {
     double* V = nullptr;  // n x k right vectors of the cut's last truncation
     int n = 0, k = 0;
