@@ -613,6 +613,10 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
       if (S.direct && S.n > l_cap_) throw Error(1, "truncated_svd: sector too large for a direct decomposition");
       if (S.direct && implicit_) throw Error(1, "truncated_svd: a direct decomposition needs the matrix");
       if (S.direct) S.l = S.n;
+      // all Ritz columns are decomposed (restricting the Rayleigh-Ritz step
+      // to the leading ones gives up the oversampling's accuracy); the
+      // trailing p/2 values are not trusted for the truncation
+      S.kt = S.direct ? S.n : S.l;
       S.trusted = S.direct ? S.n : S.l - p / 2;
       all.push_back(&S);
       if (!S.direct) sub.push_back(&S);
@@ -746,8 +750,9 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
     for (SvdSector* S : all) {
       SmallProb p{};
       p.a = S->Bj;
-      p.b = S->Vb;  // right vectors accumulated with the rotations
-      p.m = p.n = S->l;
+      p.b = S->Vb;  // right vectors accumulated with the rotations (kt x kt)
+      p.m = S->l;
+      p.n = S->kt;
       p.lda = S->l;
       p.rel = 1.1e-16 * S->l;
       p.max_sweeps = kJacobiSweeps;
@@ -802,9 +807,9 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
     SvdSector& S = sec_[P];
     if (S.k == 0) continue;
     gather_cols(S.Bj, S.l, S.perm, S.sv, S.l, S.k, S.Ub, S.k, st_);
-    gather_cols(S.Vb, S.l, S.perm, nullptr, S.l, S.k, S.B, S.k, st_);
+    gather_cols(S.Vb, S.kt, S.perm, nullptr, S.kt, S.k, S.B, S.k, st_);
   }
-  for (int P = 0; P < 2; ++P) std::swap(sec_[P].B, sec_[P].Vb);  // Vb <- gathered (l x k)
+  for (int P = 0; P < 2; ++P) std::swap(sec_[P].B, sec_[P].Vb);  // Vb <- gathered (kt x k)
   for (int P = 0; P < 2; ++P) {
     SvdSector& S = sec_[P];
     if (S.k == 0) continue;
@@ -825,9 +830,10 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
     d.alpha = 1.0;
     g.push_back(d);
     GemmDesc e = d;
-    e.A = S.Qr;
+    e.A = S.Qr;  // its first kt columns
     e.B = S.Vb;
     e.C = S.Vbuf;
+    e.K = S.kt;
     g.push_back(e);
   }
   launch_gemms(g);
