@@ -442,6 +442,14 @@ void Ctm::quadrant(int s, int j) {
 }
 
 // ---------------------------------------------------------------- SVD ----
+// Oversampling of the subspace for a kept-state guess kg at a cut: half the
+// guess (at least 32) while the cut's subspace iteration still needs many
+// iterations, 16 once it converges within three.
+int Ctm::oversample(int kg, int key) const {
+  const int it = iters_prev_[key];
+  return (it > 0 && it <= 3) ? 16 : std::max(32, kg / 2);
+}
+
 // CholeskyQR of S->Y into Ql (ql) or Qr with S->passes passes per sector
 // (1 inside the subspace iteration, 3 for its final iterate).  Buffer chain
 // per sector: pass p reads Y (p = 0) or the previous pass's output and writes
@@ -607,7 +615,7 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
       int kg = kg_io[P] > 0 ? kg_io[P] : chi;
       kg = std::min(kg, S.n);
       S.kg = kg;
-      const int p = std::max(32, kg / 2);
+      const int p = oversample(kg, key);
       S.l = std::min<int>(std::min(S.n, kg + p), l_cap_);
       S.direct = S.n <= kDirectMax || S.l >= S.n;
       if (S.direct && S.n > l_cap_) throw Error(1, "truncated_svd: sector too large for a direct decomposition");
@@ -644,7 +652,9 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
           j.ostr[1] = 1;
           jobs.push_back(j);
         }
-        S->passes = 3;
+        // a warm block is its own well-conditioned basis plus random columns:
+        // two passes orthonormalise it to rounding
+        S->passes = S->warm ? 2 : 3;
       }
       launch_copies(jobs);
       for (SvdSector* S : sub) S->rel0 = 1e-10;
@@ -710,7 +720,7 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
           }
         }
         for (SvdSector* S : act) {
-          S->passes = S->fin ? 3 : 1;
+          S->passes = S->fin ? (S->warm ? 2 : 3) : 1;
           S->rel0 = (S->warm || t >= 3) ? 1e-14 : 1e-10;
         }
         orth(act, true);  // Ql
@@ -911,7 +921,7 @@ void Ctm::move(int r) {
         const int n = (int)Q2.L.cols[P];
         if (n == 0) continue;
         const int kg = kg_[key][P] > 0 ? std::min(kg_[key][P], n) : std::min(chi_, n);
-        const int l = std::min(std::min(n, kg + std::max(32, kg / 2)), l_cap_);
+        const int l = std::min(std::min(n, kg + oversample(kg, key)), l_cap_);
         if (n <= kDirectMax || l >= n) implicit = false;
       }
       if (implicit) {

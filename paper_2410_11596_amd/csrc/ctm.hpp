@@ -120,6 +120,7 @@ class Ctm {
   void mark(int phase);
   void truncated_svd(const BT* M, int chi, int key, uint64_t salt);  // M null: apply via impl_q_
   void apply_M(std::vector<SvdSector*>& ss, bool trans);
+  int oversample(int kg, int key) const;
   void orth(std::vector<SvdSector*>& ss, bool ql);
   void corner_spectra();
   void compute_epsilon_rot(int s);  // eps~ of site s into eps_ (layout [U L | Dn R])

@@ -755,12 +755,29 @@ __device__ __forceinline__ double dpp_move(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ __forceinline__ double sum16(double v) {
+// Sum over the 8 lanes of a half DPP row (swap neighbours, swap pairs, then
+// the mirrored half row), result in all 8 lanes.
+__device__ __forceinline__ double sum8(double v) {
   v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
   v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
   v += dpp_move<0x141>(v);  // row_half_mirror
-  v += dpp_move<0x140>(v);  // row_mirror
   return v;
+}
+
+// 1/x and 1/sqrt(x) from the hardware estimates and two Newton steps each
+// (the estimates are good to far more than 2^-14, so two steps reach the
+// rounding level).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+__device__ __forceinline__ double rsq_nr(double x) {
+  const double h = 0.5 * x;
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
 }
 
 // Round-robin pairing of n2 (even) columns: round r pairs column n2-1 with r
@@ -783,11 +800,12 @@ __device__ __forceinline__ void rr_pair(int r, int pp, int n2, int& i, int& j) {
   }
 }
 
-// One pair of 16 lanes per column pair; each lane keeps its rows of the two
+// One group of 8 lanes per column pair; each lane keeps its rows of the two
 // columns in registers between the dot product and the rotation.  Squared
 // column norms are kept in LDS and recomputed only for the columns a
 // rotation changed, so a round needs one dot product per pair.
-constexpr int kJacRows = 10;  // rows per lane, m <= 160
+constexpr int kJacLanes = 8;
+constexpr int kJacRows = 20;  // rows per lane, m <= 160
 __global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
   __shared__ double Xs[kJacLds];
   __shared__ int any_rot;
@@ -811,7 +829,7 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
   const double small2 = f2 * (2.3e-16 * m) * (2.3e-16 * m);
   const double tol = P.rel;
   const int n2 = n + (n & 1), npairs = n2 / 2, rounds = n2 - 1;
-  const int sub = tid & 15, grp = tid >> 4, ngrp = NT / 16;
+  const int sub = tid & (kJacLanes - 1), grp = tid / kJacLanes, ngrp = NT / kJacLanes;
   int sweep = 0;
   for (sweep = 0; sweep < P.max_sweeps; ++sweep) {
     if (tid == 0) any_rot = 0;
@@ -835,24 +853,24 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
           double g = 0.0;
 #pragma unroll
           for (int q = 0; q < kJacRows; ++q) {
-            const int k = sub + 16 * q;
+            const int k = sub + kJacLanes * q;
             u[q] = k < m ? xi[k] : 0.0;
             v[q] = k < m ? xj[k] : 0.0;
             g = fma(u[q], v[q], g);
           }
-          g = sum16(g);
+          g = sum8(g);
           const double a = nrm[i], bb = nrm[j];
           // sqrt(a) sqrt(b), not sqrt(a b): near-zero blocks (a sector that
           // the state leaves empty up to rounding) would underflow the product
           if (fmin(a, bb) > small2 && fabs(g) > tol * sqrt(a) * sqrt(bb)) {
-            const double zeta = (bb - a) / (2.0 * g);
-            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            c = 1.0 / sqrt(1.0 + t * t);
+            const double zeta = (bb - a) * rcp_nr(2.0 * g);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+            c = rsq_nr(fma(t, t, 1.0));
             sn = c * t;
             double a2 = 0.0, b2 = 0.0;
 #pragma unroll
             for (int q = 0; q < kJacRows; ++q) {
-              const int k = sub + 16 * q;
+              const int k = sub + kJacLanes * q;
               const double x = c * u[q] - sn * v[q], y = sn * u[q] + c * v[q];
               if (k < m) {
                 xi[k] = x;
@@ -863,8 +881,8 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
             }
             // exact norms of the rotated columns (the update a - t g loses
             // relative accuracy when a column is nearly emptied)
-            a2 = sum16(a2);
-            b2 = sum16(b2);
+            a2 = sum8(a2);
+            b2 = sum8(b2);
             if (sub == 0) {
               nrm[i] = a2;
               nrm[j] = b2;
