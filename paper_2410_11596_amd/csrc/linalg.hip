@@ -437,8 +437,25 @@ __global__ __launch_bounds__(NT) void chol_inv_regs_kernel(SmallBatch b) {
 }
 
 // ------------------------------------- Cholesky inverse, one elimination ----
-// R^-1 of G = R^T R for n <= 16 * kGjMaxR, one workgroup of 256 threads (one
-// wave per SIMD) per matrix.  The elimination of G (G = L_u D L_u^T, L_u unit
+// 1/x and 1/sqrt(x) from the hardware estimates and two Newton steps each
+// (the estimates are good to far more than 2^-14, so two steps reach the
+// rounding level).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+__device__ __forceinline__ double rsq_nr(double x) {
+  const double h = 0.5 * x;
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+
+// R^-1 of G = R^T R for n <= kGjSide * kGjMaxR, one workgroup of 1024 threads
+// (four waves per SIMD, so that the latency of one wave's dependent FMAs and
+// LDS reads is hidden behind the others) per matrix.  The elimination of G (G = L_u D L_u^T, L_u unit
 // lower) and the inverse X = L_u^-1 run in the same sweep over the columns and
 // in the same registers.  With multipliers m_i = G_ij / d_j (i > j), step j
 // updates
@@ -451,29 +468,31 @@ __global__ __launch_bounds__(NT) void chol_inv_regs_kernel(SmallBatch b) {
 // column j of G (rows >= j, including the pivot d_j) and row j of S (columns
 // < j), written by their owners at the end of step j-1; one barrier per step.
 // At the end X_ic = -S_ic / d_c and R^-1[c][i] = X_ic / sqrt(d_i).  Thread
-// (ty, tx) of the 16 x 16 grid holds the entries (ty + 16u, tx + 16v), u >= v.
+// (ty, tx) of the 32 x 32 grid holds the entries (ty + 32u, tx + 32v), u >= v.
 // Pivots d_j <= 1e-27 max(diag) drop their column: zero multipliers, and
 // row and column of X zero (as in chol_inv_regs).
-constexpr int NTC = 256;
-constexpr int kGjMaxR = 14;  // n <= 224
+constexpr int kGjSide = 32;
+constexpr int NTC = kGjSide * kGjSide;
+constexpr int kGjWaves = NTC / 64;
+constexpr int kGjMaxR = 8;  // n <= 256
 
 template <int R>
 __device__ void chol_gj(const SmallProb& P, double* buf, double* red, int* bad) {
   const int n = P.n, ld = P.lda, ldr = P.ldb;
   const double* G = P.a;
   double* Ri = P.b;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x, tx = tid & (kGjSide - 1), ty = tid / kGjSide;
   const bool scale = (P.flags & 1) != 0;
   double* dsc = P.sv;
-  constexpr int L = 16 * R;
-  // buf: [2 buffers][L + 1]
+  constexpr int L = kGjSide * R;
+  // buf: [2 buffers][V1, V2][L]
   if (scale)
     for (int i = tid; i < n; i += NTC) {
       const double g = G[(long long)i * ld + i];
       dsc[i] = g > 0.0 ? sqrt(g) : 1.0;
     }
   if (tid == 0) *bad = 0;
-  for (int i = tid; i < 2 * (L + 1); i += NTC) buf[i] = 0.0;
+  for (int i = tid; i < 4 * L; i += NTC) buf[i] = 0.0;
   __syncthreads();
   double dmax = 0.0;
   for (int i = tid; i < n; i += NTC) {
@@ -484,7 +503,9 @@ __device__ void chol_gj(const SmallProb& P, double* buf, double* red, int* bad) 
   for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
   if ((tid & 63) == 0) red[tid >> 6] = dmax;
   __syncthreads();
-  dmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  dmax = red[0];
+#pragma unroll
+  for (int w = 1; w < kGjWaves; ++w) dmax = fmax(dmax, red[w]);
   const double shift = P.rel * dmax;
   const double thresh = 1e-27 * dmax;
 
@@ -493,7 +514,7 @@ __device__ void chol_gj(const SmallProb& P, double* buf, double* red, int* bad) 
   for (int u = 0; u < R; ++u)
 #pragma unroll
     for (int v = 0; v <= u; ++v) {
-      const int i = ty + 16 * u, k = tx + 16 * v;
+      const int i = ty + kGjSide * u, k = tx + kGjSide * v;
       double x = 0.0;
       if (i < n && k <= i) {
         x = G[(long long)i * ld + k];
@@ -502,73 +523,104 @@ __device__ void chol_gj(const SmallProb& P, double* buf, double* red, int* bad) 
       }
       a[u][v] = x;
     }
-  // step 0: column 0 of G below the pivot, the pivot in slot L
+  // Two columns per step (J, J+1), one barrier per step.  Published before
+  // the step: V1[k] = G_kJ (k >= J), S_Jk (k < J) and V2[k] = G_k,J+1
+  // (k >= J+1), S_J+1,k (k < J); an odd n is padded with a dead pivot.
+  // Step J is applied with multipliers m_i = G_iJ / d_J and vector w1
+  // (V1 with 0 at J); step J+1 sees column J+1 and row J+1 as updated by
+  // step J: d' = G_J+1,J+1 - m_J+1 G_J+1,J, multipliers
+  // m'_i = (G_i,J+1 - m_i G_J+1,J) / d' and vector w2_k = G_k,J+1 - m_k G_J+1,J
+  // (k > J+1), 0 (k = J+1), G_J+1,J (k = J: column J is S from step J+1 on),
+  // S_J+1,k - m_J+1 S_Jk (k < J).  Both updates go into one pass over the
+  // registers.
   if (tx == 0)
 #pragma unroll
+    for (int u = 0; u < R; ++u) buf[ty + kGjSide * u] = a[u][0];  // V1 of J = 0
+  if (tx == 1)
+#pragma unroll
     for (int u = 0; u < R; ++u) {
-      const int i = ty + 16 * u;
-      if (i == 0) {
-        buf[L] = a[u][0];
-        buf[0] = 0.0;
-      } else {
-        buf[i] = a[u][0];
-      }
+      const int i = ty + kGjSide * u;
+      if (i >= 1) buf[L + i] = a[u][0];  // V2 of J = 0 (column 1)
     }
   __syncthreads();
 
-  // one vector per step: w_k = G_kj (k > j), 0 (k = j), S_jk (k < j); the
-  // pivot d_j in slot L
-  for (int j = 0; j < n; ++j) {
-    const double* wv = buf + (j & 1) * (L + 1);
-    double* nw = buf + ((j + 1) & 1) * (L + 1);
-    const int jb = j >> 4;
-    double ci[R], w[R];
-#pragma unroll
-    for (int u = 0; u < R; ++u) ci[u] = wv[ty + 16 * u];
-#pragma unroll
-    for (int v = 0; v < R; ++v) w[v] = wv[tx + 16 * v];
-    const double dj = wv[L];
-    // 1/d_j: hardware reciprocal and two Newton steps (error below 1 ulp)
-    double inv = 0.0;
-    if (dj > thresh) {
-      double r0 = __builtin_amdgcn_rcp(dj);
-      r0 = fma(r0, fma(-dj, r0, 1.0), r0);
-      inv = fma(r0, fma(-dj, r0, 1.0), r0);
-    }
-    double m[R];
+  for (int J = 0; J < n; J += 2) {
+    const double* V1 = buf + ((J >> 1) & 1) * 2 * L;
+    const double* V2 = V1 + L;
+    double* N1 = buf + (((J >> 1) + 1) & 1) * 2 * L;
+    double* N2 = N1 + L;
+    const int jb = J / kGjSide;
+    const double dJ = V1[J], g1 = V1[J + 1], e2 = V2[J + 1];
+    const double inv = dJ > thresh ? rcp_nr(dJ) : 0.0;
+    const double mJ1 = g1 * inv;
+    const double d2 = e2 - mJ1 * g1;
+    const double inv2 = d2 > thresh ? rcp_nr(d2) : 0.0;
+    double m1[R], m2[R];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      m[u] = ci[u] * inv;
-      if (u == jb && ty + 16 * u <= j) m[u] = 0.0;  // rows <= j of the pivot block
+      const int i = ty + kGjSide * u;
+      double x1 = V1[i] * inv;
+      double x2 = fma(-x1, g1, V2[i]) * inv2;
+      if (u == jb) {  // uniform: only the pivot block holds rows <= J+1
+        if (i <= J) x1 = 0.0;
+        if (i <= J + 1) x2 = 0.0;
+      }
+      m1[u] = x1;
+      m2[u] = x2;
     }
+    // column blocks one at a time, so that only the multipliers stay live
 #pragma unroll
-    for (int u = 0; u < R; ++u) {
-      if (u < jb) continue;  // rows <= j are final (uniform)
+    for (int v = 0; v < R; ++v) {
+      const int k = tx + kGjSide * v;
+      const double k1 = V1[k], k2 = V2[k];
+      double w1, w2;
+      if (v > jb) {
+        w1 = k1;
+        w2 = fma(-k1 * inv, g1, k2);
+      } else if (v < jb) {
+        w1 = k1;
+        w2 = fma(-mJ1, k1, k2);
+      } else {
+        w1 = k == J ? 0.0 : k1;
+        w2 = k > J + 1 ? fma(-k1 * inv, g1, k2)
+                       : (k == J + 1 ? 0.0 : (k == J ? g1 : fma(-mJ1, k1, k2)));
+      }
 #pragma unroll
-      for (int v = 0; v <= u; ++v) a[u][v] = fma(-m[u], w[v], a[u][v]);
+      for (int u = v; u < R; ++u) {
+        if (u < jb) continue;  // rows <= J are final (uniform)
+        a[u][v] = fma(-m2[u], w2, fma(-m1[u], w1, a[u][v]));
+      }
     }
-    // publish step j+1's vector (its entries are final now)
-    const int j1 = j + 1;
-    if (j1 < n) {
-      const int j1b = j1 >> 4, j1l = j1 & 15;
+    // publish the next step's vectors (their entries are final now)
+    const int J2 = J + 2;
+    if (J2 < n) {
+      const int b2 = J2 / kGjSide, l2 = J2 % kGjSide;  // J2 + 1 is in the same block
 #pragma unroll
       for (int v = 0; v < R; ++v) {
-        if (v != j1b) continue;  // uniform
-        if (tx == j1l)
+        if (v != b2) continue;  // uniform
+        if (tx == l2)
 #pragma unroll
           for (int u = v; u < R; ++u) {
-            const int i = ty + 16 * u;
-            if (i > j1) nw[i] = a[u][v];
-            if (i == j1) {
-              nw[i] = 0.0;
-              nw[L] = a[u][v];
-            }
+            const int i = ty + kGjSide * u;
+            if (i >= J2) N1[i] = a[u][v];
           }
-        if (ty == j1l)
+        if (tx == l2 + 1)
+#pragma unroll
+          for (int u = v; u < R; ++u) {
+            const int i = ty + kGjSide * u;
+            if (i >= J2 + 1) N2[i] = a[u][v];
+          }
+        if (ty == l2)
 #pragma unroll
           for (int c = 0; c <= v; ++c) {
-            const int k = tx + 16 * c;
-            if (k < j1) nw[k] = a[v][c];
+            const int k = tx + kGjSide * c;
+            if (k < J2) N1[k] = a[v][c];
+          }
+        if (ty == l2 + 1)
+#pragma unroll
+          for (int c = 0; c <= v; ++c) {
+            const int k = tx + kGjSide * c;
+            if (k < J2) N2[k] = a[v][c];
           }
       }
     }
@@ -578,13 +630,13 @@ __device__ void chol_gj(const SmallProb& P, double* buf, double* red, int* bad) 
   double* dg = buf;  // all reads of the last step are done
   if (tx == ty)
 #pragma unroll
-    for (int u = 0; u < R; ++u) dg[ty + 16 * u] = a[u][u];
+    for (int u = 0; u < R; ++u) dg[ty + kGjSide * u] = a[u][u];
   __syncthreads();
   int nbad = 0;
   double rs[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
-    const int i = ty + 16 * u;
+    const int i = ty + kGjSide * u;
     const double d = i < n ? dg[i] : 1.0;
     rs[u] = d > thresh ? 1.0 / sqrt(d) : 0.0;
     if (i < n && !(d > thresh) && tx == 0) ++nbad;
@@ -595,7 +647,7 @@ __device__ void chol_gj(const SmallProb& P, double* buf, double* red, int* bad) 
   for (int u = 0; u < R; ++u)
 #pragma unroll
     for (int v = 0; v < R; ++v) {
-      const int i = ty + 16 * u, c = tx + 16 * v;
+      const int i = ty + kGjSide * u, c = tx + kGjSide * v;
       if (i < n && c < n) {
         double x = 0.0;
         if (v <= u && c <= i) {
@@ -613,11 +665,11 @@ __device__ void chol_gj(const SmallProb& P, double* buf, double* red, int* bad) 
   if (tid == 0 && P.info) *P.info = *bad;
 }
 
-// R = ceil(max n / 16) of the batch; smaller problems carry zero blocks
+// R = ceil(max n / kGjSide) of the batch; smaller problems carry zero blocks
 template <int R>
 __global__ __launch_bounds__(NTC) void chol_gj_kernel(SmallBatch b) {
-  __shared__ double buf[2 * (16 * R + 1)];
-  __shared__ double red[4];
+  __shared__ double buf[4 * kGjSide * R];
+  __shared__ double red[kGjWaves];
   __shared__ int bad;
   chol_gj<R>(b.p[blockIdx.x], buf, red, &bad);
 }
@@ -762,22 +814,6 @@ __device__ __forceinline__ double sum8(double v) {
   v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
   v += dpp_move<0x141>(v);  // row_half_mirror
   return v;
-}
-
-// 1/x and 1/sqrt(x) from the hardware estimates and two Newton steps each
-// (the estimates are good to far more than 2^-14, so two steps reach the
-// rounding level).
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return fma(r, fma(-x, r, 1.0), r);
-}
-
-__device__ __forceinline__ double rsq_nr(double x) {
-  const double h = 0.5 * x;
-  double y = __builtin_amdgcn_rsq(x);
-  y = y * fma(-h * y, y, 1.5);
-  return y * fma(-h * y, y, 1.5);
 }
 
 // Round-robin pairing of n2 (even) columns: round r pairs column n2-1 with r
@@ -1148,9 +1184,9 @@ void scale_inv(double* p, size_t n, const double* nrm, hipStream_t s) {
 }
 
 void chol_inv(const std::vector<SmallProb>& probs, hipStream_t s) {
-  // one-elimination register kernel for n <= 224, the LDS/global one above
+  // one-elimination register kernel for n <= 256, the LDS/global one above
   std::vector<SmallProb> small, large;
-  for (const SmallProb& p : probs) (p.n <= 16 * kGjMaxR ? small : large).push_back(p);
+  for (const SmallProb& p : probs) (p.n <= kGjSide * kGjMaxR ? small : large).push_back(p);
   for (int pass = 0; pass < 2; ++pass) {
     const std::vector<SmallProb>& v = pass == 0 ? small : large;
     for (size_t i = 0; i < v.size(); i += kMaxSmall) {
@@ -1160,7 +1196,7 @@ void chol_inv(const std::vector<SmallProb>& probs, hipStream_t s) {
       if (pass == 0) {
         int nmax = 1;
         for (int q = 0; q < b.n; ++q) nmax = std::max(nmax, b.p[q].n);
-        switch ((nmax + 15) / 16) {
+        switch ((nmax + kGjSide - 1) / kGjSide) {
           case 1: hipLaunchKernelGGL(chol_gj_kernel<1>, dim3(b.n), dim3(NTC), 0, s, b); break;
           case 2: hipLaunchKernelGGL(chol_gj_kernel<2>, dim3(b.n), dim3(NTC), 0, s, b); break;
           case 3: hipLaunchKernelGGL(chol_gj_kernel<3>, dim3(b.n), dim3(NTC), 0, s, b); break;
@@ -1168,13 +1204,7 @@ void chol_inv(const std::vector<SmallProb>& probs, hipStream_t s) {
           case 5: hipLaunchKernelGGL(chol_gj_kernel<5>, dim3(b.n), dim3(NTC), 0, s, b); break;
           case 6: hipLaunchKernelGGL(chol_gj_kernel<6>, dim3(b.n), dim3(NTC), 0, s, b); break;
           case 7: hipLaunchKernelGGL(chol_gj_kernel<7>, dim3(b.n), dim3(NTC), 0, s, b); break;
-          case 8: hipLaunchKernelGGL(chol_gj_kernel<8>, dim3(b.n), dim3(NTC), 0, s, b); break;
-          case 9: hipLaunchKernelGGL(chol_gj_kernel<9>, dim3(b.n), dim3(NTC), 0, s, b); break;
-          case 10: hipLaunchKernelGGL(chol_gj_kernel<10>, dim3(b.n), dim3(NTC), 0, s, b); break;
-          case 11: hipLaunchKernelGGL(chol_gj_kernel<11>, dim3(b.n), dim3(NTC), 0, s, b); break;
-          case 12: hipLaunchKernelGGL(chol_gj_kernel<12>, dim3(b.n), dim3(NTC), 0, s, b); break;
-          case 13: hipLaunchKernelGGL(chol_gj_kernel<13>, dim3(b.n), dim3(NTC), 0, s, b); break;
-          default: hipLaunchKernelGGL(chol_gj_kernel<14>, dim3(b.n), dim3(NTC), 0, s, b); break;
+          default: hipLaunchKernelGGL(chol_gj_kernel<8>, dim3(b.n), dim3(NTC), 0, s, b); break;
         }
       } else
         hipLaunchKernelGGL(chol_inv_kernel, dim3(b.n), dim3(NT), 0, s, b);
