@@ -194,7 +194,9 @@ void Ctm::plan_memory(bool counting) {
   dpart_ = ar_.take((size_t)(64 * kMaxDots));
   rho_ = ar_.take((size_t)(2 * ns * d4 + 16));
   hdev_ = ar_.take((size_t)(d4 + 16));
-  gemm_scratch_cap_ = std::max<long long>(1 << 20, 24LL * lcap * lcap);
+  // split-K partial tiles: a few K slices of the tall n x l products of both
+  // sectors, or of the l x l Gram matrices
+  gemm_scratch_cap_ = std::max<long long>({1LL << 20, 24LL * lcap * lcap, 16LL * ncap * lcap});
   gemm_scratch_ = ar_.take((size_t)gemm_scratch_cap_);
 }
 

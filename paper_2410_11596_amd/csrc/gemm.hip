@@ -7,10 +7,12 @@
 //
 // Tile: BM x BN per workgroup of 256 threads (4 wave64 in a 2 x 2 layout),
 // K step 16.  128 x 128 for the large block products; 64 x 64 when the
-// problems are too small to fill the 256 CUs; and for small outputs with a
-// long reduction (the l x l Gram matrices of the subspace iteration) the K
-// range is split over several workgroups whose partial tiles are summed in a
-// fixed order by a second kernel (deterministic, no atomics).  Operands are
+// problems are too small to fill the 256 CUs; and when the 64 x 64 tiles are
+// too few (the tall n x l products and the l x l Gram matrices of the
+// subspace iteration) the K range is split over several workgroups, about
+// four per CU in all, whose partial tiles are summed in a fixed order by a
+// second kernel with one thread per output element (deterministic, no
+// atomics).  Operands are
 // staged through LDS in k-major order so that one MFMA fragment read is a
 // contiguous row per 16 lanes; loads for step k+1 are issued into registers
 // before the MFMAs of step k.
@@ -277,6 +279,7 @@ void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch, lo
   g.n = 0;
   g.total = 0;
   bool any_split = false;
+  long long split_mn = 0;
   auto flush = [&]() {
     if (g.n == 0) return;
     if (cfg == 0)
@@ -285,13 +288,16 @@ void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch, lo
       hipLaunchKernelGGL((gemm_f64_kernel<64, 64>), dim3(g.total), dim3(NT), 0, s, g);
     HCTM_HIP(hipGetLastError());
     if (any_split) {
-      hipLaunchKernelGGL(splitk_reduce_kernel, dim3(64, g.n), dim3(256), 0, s, g);
+      // one thread per output element of the largest split problem
+      const unsigned gx = (unsigned)std::min<long long>(2048, (split_mn + 255) / 256);
+      hipLaunchKernelGGL(splitk_reduce_kernel, dim3(gx, g.n), dim3(256), 0, s, g);
       HCTM_HIP(hipGetLastError());
     }
     g.n = 0;
     g.total = 0;
     part_used = 0;
     any_split = false;
+    split_mn = 0;
   };
   for (const GemmDesc& d : probs) {
     if (d.M <= 0 || d.N <= 0) continue;
@@ -324,8 +330,8 @@ void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch, lo
     // split K when the call has too few output tiles and this K is long
     int ks = 1;
     if (cfg == 1 && t64 < kFill && scratch) {
-      const long long want = (2 * kFill + t64 - 1) / t64;
-      const long long maxk = d.K / 256;  // at least 256 of K per slice
+      const long long want = (4 * kFill + t64 - 1) / t64;  // about 4 workgroups per CU
+      const long long maxk = d.K / 64;  // at least 64 of K per slice
       ks = (int)std::max<long long>(1, std::min(want, maxk));
       while (ks > 1 && part_used + (long long)ks * d.M * d.N > scratch_cap) --ks;
     }
@@ -336,6 +342,7 @@ void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch, lo
       p.part = scratch + part_used;
       part_used += (long long)p.ksplit * d.M * d.N;
       any_split = true;
+      split_mn = std::max(split_mn, (long long)d.M * d.N);
     } else {
       p.part = nullptr;
     }
