@@ -35,9 +35,13 @@ int hctm_dev_chol_inv(double* G, double* Rinv, int n, double rel, int* info, voi
  * sweeps[0] = sweeps used (negative: no convergence within max_sweeps).
  * If V is not NULL (X square), V (n x n, row-major) receives the product of
  * the rotations, so that X_in V = X_out; vlog then needs
- * hctm_dev_jacobi_log_doubles(n, max_sweeps) doubles of scratch. */
-int hctm_dev_jacobi(double* X, int m, int n, double tol, int max_sweeps, double* sv, int* perm, int* sweeps,
-                    double* V, double* vlog, void* stream);
+ * hctm_dev_jacobi_log_doubles(n, max_sweeps) doubles of scratch.
+ * pre (2 <= pre < n, n <= 160 and m * n <= 19968; else ignored): the last
+ * pre columns are first orthogonalised among themselves, sweeps[1] = the
+ * sweeps of that phase (sweeps then holds 2 ints).  The result is the same
+ * decomposition; only the number of rotations changes. */
+int hctm_dev_jacobi(double* X, int m, int n, double tol, int max_sweeps, int pre, double* sv, int* perm,
+                    int* sweeps, double* V, double* vlog, void* stream);
 
 /* Scratch doubles needed by hctm_dev_jacobi's rotation log. */
 long long hctm_dev_jacobi_log_doubles(int n, int max_sweeps);

@@ -88,7 +88,8 @@ def lib():
         "hctm_dev_copy": ([vp, vp, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_longlong), P(ctypes.c_longlong), vp],
                           ctypes.c_int),
         "hctm_dev_chol_inv": ([vp, vp, ctypes.c_int, ctypes.c_double, vp, vp], ctypes.c_int),
-        "hctm_dev_jacobi": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp, vp, vp],
+        "hctm_dev_jacobi": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp,
+                             vp, vp],
                             ctypes.c_int),
         "hctm_dev_jacobi_log_doubles": ([ctypes.c_int, ctypes.c_int], ctypes.c_longlong),
     }
@@ -328,11 +329,11 @@ def dev_chol_inv(G, Rinv, n, rel, info):
     _check(lib().hctm_dev_chol_inv(_ptr(G), _ptr(Rinv), n, rel, _ptr(info), _stream_ptr(torch)))
 
 
-def dev_jacobi(X, m, n, tol, max_sweeps, sv, perm, sweeps, V=None, vlog=None):
+def dev_jacobi(X, m, n, tol, max_sweeps, sv, perm, sweeps, V=None, vlog=None, pre=0):
     torch = _torch()
     vp = _ptr(V) if V is not None else None
     lp = _ptr(vlog) if vlog is not None else None
-    _check(lib().hctm_dev_jacobi(_ptr(X), m, n, tol, max_sweeps, _ptr(sv), _ptr(perm), _ptr(sweeps), vp, lp,
+    _check(lib().hctm_dev_jacobi(_ptr(X), m, n, tol, max_sweeps, pre, _ptr(sv), _ptr(perm), _ptr(sweeps), vp, lp,
                                  _stream_ptr(torch)))
 
 

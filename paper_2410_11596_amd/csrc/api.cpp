@@ -336,8 +336,8 @@ int hctm_dev_chol_inv(double* G, double* Rinv, int n, double rel, int* info, voi
   });
 }
 
-int hctm_dev_jacobi(double* X, int m, int n, double tol, int max_sweeps, double* sv, int* perm, int* sweeps,
-                    double* V, double* vlog, void* stream) {
+int hctm_dev_jacobi(double* X, int m, int n, double tol, int max_sweeps, int pre, double* sv, int* perm,
+                    int* sweeps, double* V, double* vlog, void* stream) {
   return guarded(nullptr, [&] {
     if (m < 1 || n < 1 || n > 1024) throw hctm::Error(CTM_E_ARG, "size out of range");
     hctm::SmallProb p{};
@@ -347,6 +347,7 @@ int hctm_dev_jacobi(double* X, int m, int n, double tol, int max_sweeps, double*
     p.lda = n;
     p.rel = tol;
     p.max_sweeps = max_sweeps;
+    p.pre = pre;
     p.info = sweeps;
     p.sv = sv;
     p.perm = perm;

@@ -768,6 +768,8 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
       p.lda = S->l;
       p.rel = 1.1e-16 * S->l;
       p.max_sweeps = kJacobiSweeps;
+      // the oversampled trailing columns are the least converged ones
+      p.pre = S->direct ? 0 : S->l - S->kg;
       p.vlog = S->vlog;
       p.info = S->info + 1;
       p.sv = S->sv;

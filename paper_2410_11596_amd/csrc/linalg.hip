@@ -842,47 +842,28 @@ __device__ __forceinline__ void rr_pair(int r, int pp, int n2, int& i, int& j) {
 // rotation changed, so a round needs one dot product per pair.
 constexpr int kJacLanes = 8;
 constexpr int kJacRows = 20;  // rows per lane, m <= 160
-__global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
-  __shared__ double Xs[kJacLds];
-  __shared__ int any_rot;
-  __shared__ double red[16];
-  __shared__ double nrm[160];
-  const SmallProb& P = b.p[blockIdx.x];
-  const int m = P.m, n = P.n, ld = P.lda;
-  double* X = P.a;
-  double* rlog = P.b;  // (max_sweeps x (n2-1) x n2/2) pairs of (c, s)
+
+// Sweeps of round-robin rotations over the columns c0 .. c0 + nn - 1 of Xs
+// (column-major, m rows) until a sweep rotates nothing; rotations logged as
+// (sweep, round, pair) from lg.  Returns the sweeps done (the converged one
+// included), negated when max_sweeps ran out first.
+__device__ int jacobi_sweeps(double* Xs, double* nrm, int* any_rot, int m, int c0, int nn, double tol,
+                             double small2, int max_sweeps, double2* lg) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < m * n; e += NT) {
-    const int r = e / n, c = e % n;
-    Xs[c * m + r] = X[(long long)r * ld + c];
-  }
-  double f2 = 0.0;
-  for (int e = tid; e < m * n; e += NT) {
-    const double x = X[(long long)(e / n) * ld + (e % n)];
-    f2 += x * x;
-  }
-  f2 = block_sum(f2, red);  // includes barriers
-  const double small2 = f2 * (2.3e-16 * m) * (2.3e-16 * m);
-  const double tol = P.rel;
-  const int n2 = n + (n & 1), npairs = n2 / 2, rounds = n2 - 1;
+  const int n2 = nn + (nn & 1), npairs = n2 / 2, rounds = n2 - 1;
   const int sub = tid & (kJacLanes - 1), grp = tid / kJacLanes, ngrp = NT / kJacLanes;
-  int sweep = 0;
-  for (sweep = 0; sweep < P.max_sweeps; ++sweep) {
-    if (tid == 0) any_rot = 0;
-    if (sweep == 0)
-      for (int j = tid; j < n; j += NT) {
-        double s2 = 0.0;
-        for (int k = 0; k < m; ++k) s2 += Xs[j * m + k] * Xs[j * m + k];
-        nrm[j] = s2;
-      }
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) *any_rot = 0;
     __syncthreads();
     for (int r = 0; r < rounds; ++r) {
-      double2* lg = rlog ? reinterpret_cast<double2*>(rlog) + ((long long)sweep * rounds + r) * npairs : nullptr;
+      double2* lr = lg ? lg + ((long long)sweep * rounds + r) * npairs : nullptr;
       for (int pp = grp; pp < npairs; pp += ngrp) {
         int i, j;
         rr_pair(r, pp, n2, i, j);
         double c = 1.0, sn = 0.0;
-        if (j < n) {
+        if (j < nn) {
+          i += c0;
+          j += c0;
           double* xi = Xs + i * m;
           double* xj = Xs + j * m;
           double u[kJacRows], v[kJacRows];
@@ -922,22 +903,70 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
             if (sub == 0) {
               nrm[i] = a2;
               nrm[j] = b2;
-              any_rot = 1;
+              *any_rot = 1;
             }
           }
         }
-        if (sub == 0 && rlog) lg[pp] = make_double2(c, sn);
+        if (sub == 0 && lr) lr[pp] = make_double2(c, sn);
       }
       __syncthreads();
     }
-    const int rot = any_rot;
+    const int rot = *any_rot;
     __syncthreads();
-    if (!rot) {
-      ++sweep;  // the converged sweep is logged too (identity rotations)
-      break;
-    }
+    if (!rot) return sweep + 1;  // the converged sweep is logged too (identity rotations)
   }
-  if (tid == 0 && P.info) *P.info = (sweep <= P.max_sweeps && !any_rot) ? sweep : -sweep;
+  return -max_sweeps;
+}
+
+// Offset (in (c, s) pairs) of the log of the leading phase over the trailing
+// columns: after the room for max_sweeps sweeps over all n columns.
+__host__ __device__ inline long long jacobi_pre_log_offset(int n, int max_sweeps) {
+  const long long n2 = n + (n & 1);
+  return (long long)max_sweeps * (n2 - 1) * (n2 / 2);
+}
+
+// A subspace-iteration Ritz block is close to diagonal except among its
+// trailing (oversampled, least converged) columns; with P.pre set, those are
+// orthogonalised among themselves first (short sweeps), so that the sweeps
+// over all columns start from nearly orthogonal columns and converge in few
+// sweeps.  The result is the same one-sided Jacobi SVD (the full sweeps run
+// until a sweep rotates nothing).
+__global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
+  __shared__ double Xs[kJacLds];
+  __shared__ int any_rot;
+  __shared__ double red[16];
+  __shared__ double nrm[160];
+  const SmallProb& P = b.p[blockIdx.x];
+  const int m = P.m, n = P.n, ld = P.lda;
+  double* X = P.a;
+  double2* rlog = reinterpret_cast<double2*>(P.b);  // rotation log or null
+  const int tid = threadIdx.x;
+  for (int e = tid; e < m * n; e += NT) {
+    const int r = e / n, c = e % n;
+    Xs[c * m + r] = X[(long long)r * ld + c];
+  }
+  double f2 = 0.0;
+  for (int e = tid; e < m * n; e += NT) {
+    const double x = X[(long long)(e / n) * ld + (e % n)];
+    f2 += x * x;
+  }
+  f2 = block_sum(f2, red);  // includes barriers
+  const double small2 = f2 * (2.3e-16 * m) * (2.3e-16 * m);
+  const double tol = P.rel;
+  for (int j = tid; j < n; j += NT) {
+    double s2 = 0.0;
+    for (int k = 0; k < m; ++k) s2 += Xs[j * m + k] * Xs[j * m + k];
+    nrm[j] = s2;
+  }
+  __syncthreads();
+  const int pre = (P.pre >= 2 && P.pre < n) ? P.pre : 0;
+  if (pre) {
+    const int sp = jacobi_sweeps(Xs, nrm, &any_rot, m, n - pre, pre, tol, small2, P.max_sweeps,
+                                 rlog ? rlog + jacobi_pre_log_offset(n, P.max_sweeps) : nullptr);
+    if (tid == 0 && P.info) P.info[1] = sp < 0 ? -sp : sp;
+  }
+  const int sweeps = jacobi_sweeps(Xs, nrm, &any_rot, m, 0, n, tol, small2, P.max_sweeps, rlog);
+  if (tid == 0 && P.info) *P.info = sweeps;
   for (int j = tid; j < n; j += NT) {
     double s2 = 0.0;
     for (int k = 0; k < m; ++k) s2 += Xs[j * m + k] * Xs[j * m + k];
@@ -963,25 +992,16 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
 // Rebuild V (n x n, row-major, written to P.a) from the rotation log in
 // P.b: rows are independent, kVRows rows per workgroup held column-major in
 // LDS; the log is staged kVChunk rounds at a time so that each round reads
-// LDS only.
+// LDS only.  The rotations of the leading phase over the trailing columns
+// (P.pre) come first.
 constexpr int kVChunk = 16;
 constexpr int kVRows = 8;
-__global__ __launch_bounds__(256) void jacobi_v_kernel(SmallBatch b) {
-  __shared__ double Vs[160 * kVRows];
-  __shared__ double2 Ls[kVChunk * 80];
-  const SmallProb& P = b.p[blockIdx.y];
-  const int n = P.n;
-  const int sweeps = P.info ? abs(*P.info) : 0;
-  const double2* lg = reinterpret_cast<const double2*>(P.b);
-  double* V = P.a;
-  const int r0 = blockIdx.x * kVRows;
-  if (r0 >= n) return;
-  const int rows = min(kVRows, n - r0);
-  for (int e = threadIdx.x; e < kVRows * n; e += 256) {
-    const int c = e / kVRows, rr = e % kVRows;
-    Vs[c * kVRows + rr] = (r0 + rr == c) ? 1.0 : 0.0;
-  }
-  const int n2 = n + (n & 1), npairs = n2 / 2, rounds = n2 - 1;
+
+// Apply the logged rotations of `sweeps` sweeps over the columns
+// c0 .. c0 + nn - 1 to the rows held in Vs.
+__device__ void replay_rotations(double* Vs, double2* Ls, const double2* lg, int c0, int nn, int sweeps,
+                                 int rows) {
+  const int n2 = nn + (nn & 1), npairs = n2 / 2, rounds = n2 - 1;
   const long long total = (long long)sweeps * rounds;
   int r = 0;
   for (long long t0 = 0; t0 < total; t0 += kVChunk) {
@@ -996,7 +1016,9 @@ __global__ __launch_bounds__(256) void jacobi_v_kernel(SmallBatch b) {
         if (cs.y == 0.0 || rr >= rows) continue;
         int i, j;
         rr_pair(r, pp, n2, i, j);
-        if (j >= n) continue;
+        if (j >= nn) continue;
+        i += c0;
+        j += c0;
         const double u = Vs[i * kVRows + rr], v = Vs[j * kVRows + rr];
         Vs[i * kVRows + rr] = cs.x * u - cs.y * v;
         Vs[j * kVRows + rr] = cs.y * u + cs.x * v;
@@ -1005,6 +1027,27 @@ __global__ __launch_bounds__(256) void jacobi_v_kernel(SmallBatch b) {
       __syncthreads();
     }
   }
+}
+
+__global__ __launch_bounds__(256) void jacobi_v_kernel(SmallBatch b) {
+  __shared__ double Vs[160 * kVRows];
+  __shared__ double2 Ls[kVChunk * 80];
+  const SmallProb& P = b.p[blockIdx.y];
+  const int n = P.n;
+  const int sweeps = P.info ? abs(P.info[0]) : 0;
+  const int pre = (P.info && P.pre >= 2 && P.pre < n) ? P.pre : 0;
+  const double2* lg = reinterpret_cast<const double2*>(P.b);
+  double* V = P.a;
+  const int r0 = blockIdx.x * kVRows;
+  if (r0 >= n) return;
+  const int rows = min(kVRows, n - r0);
+  for (int e = threadIdx.x; e < kVRows * n; e += 256) {
+    const int c = e / kVRows, rr = e % kVRows;
+    Vs[c * kVRows + rr] = (r0 + rr == c) ? 1.0 : 0.0;
+  }
+  if (pre)
+    replay_rotations(Vs, Ls, lg + jacobi_pre_log_offset(n, P.max_sweeps), n - pre, pre, P.info[1], rows);
+  replay_rotations(Vs, Ls, lg, 0, n, sweeps, rows);
   __syncthreads();
   for (int e = threadIdx.x; e < rows * n; e += 256) {
     const int rr = e / n, c = e % n;
@@ -1214,8 +1257,9 @@ void chol_inv(const std::vector<SmallProb>& probs, hipStream_t s) {
 }
 
 size_t jacobi_log_doubles(int n, int max_sweeps) {
-  const size_t n2 = n + (n & 1);
-  return (size_t)max_sweeps * (n2 - 1) * n2;  // (c, s) per pair per round
+  // (c, s) per pair per round: the sweeps over all columns, then those of the
+  // leading phase over the trailing columns (at most as many)
+  return 4 * (size_t)jacobi_pre_log_offset(n, max_sweeps);
 }
 
 void jacobi(const std::vector<SmallProb>& probs, hipStream_t s) {

@@ -16,6 +16,8 @@ struct SmallProb {
   double* vlog;    // Jacobi: rotation log (jacobi_log_doubles), enables the LDS kernel with V
   int flags;       // Cholesky: 1 = factor the unit-diagonal Gram D^-1 G D^-1 (D = sqrt diag G);
                    // Rinv is then D^-1 R^-1 (sv must point to n doubles of scratch)
+  int pre;         // Jacobi (LDS kernel): the last pre columns are first orthogonalised among
+                   // themselves (0: not); their sweep count goes to info[1]
 };
 
 constexpr int kMaxSmall = 16;

@@ -105,8 +105,9 @@ def test_cholesky_inverse(hc, n):
     assert np.abs(Q.T @ Q - np.eye(n)).max() < 1e-11 * np.linalg.cond(X) ** 2
 
 
-@pytest.mark.parametrize("m,n", [(1, 1), (8, 5), (40, 40), (120, 97), (150, 150), (201, 180)])
-def test_jacobi_svd(hc, m, n):
+@pytest.mark.parametrize("m,n,pre", [(1, 1, 0), (8, 5, 0), (8, 5, 2), (40, 40, 0), (40, 40, 16), (120, 97, 0),
+                                     (120, 97, 33), (126, 126, 42), (150, 150, 0), (201, 180, 0)])
+def test_jacobi_svd(hc, m, n, pre):
     rng = np.random.default_rng(m + n)
     # graded singular values, as in the CTMRG spectra
     U, _ = np.linalg.qr(rng.standard_normal((m, m)))
@@ -120,8 +121,10 @@ def test_jacobi_svd(hc, m, n):
     sw = torch.zeros(4, dtype=torch.int32, device="cuda")
     V = torch.zeros((n, n), dtype=torch.float64, device="cuda") if m == n else None
     vlog = torch.zeros(max(1, hc.jacobi_log_doubles(n, 60)), dtype=torch.float64, device="cuda") if m == n else None
-    hc.dev_jacobi(dX, m, n, 1.1e-16 * m, 60, sv, perm, sw, V, vlog)
+    hc.dev_jacobi(dX, m, n, 1.1e-16 * m, 60, sv, perm, sw, V, vlog, pre=pre)
     torch.cuda.synchronize()
+    if pre:
+        assert int(sw[1].item()) >= 1
     if V is not None:
         Vh = V.cpu().numpy()
         # accumulated rotations: orthogonality to a few hundred ulps
