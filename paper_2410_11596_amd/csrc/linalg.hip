@@ -453,46 +453,61 @@ __device__ __forceinline__ double rsq_nr(double x) {
   return y * fma(-h * y, y, 1.5);
 }
 
-// R^-1 of G = R^T R for n <= kGjSide * kGjMaxR, one workgroup of 1024 threads
-// (four waves per SIMD, so that the latency of one wave's dependent FMAs and
-// LDS reads is hidden behind the others) per matrix.  The elimination of G (G = L_u D L_u^T, L_u unit
-// lower) and the inverse X = L_u^-1 run in the same sweep over the columns and
-// in the same registers.  With multipliers m_i = G_ij / d_j (i > j), step j
-// updates
+// R^-1 of G = R^T R for n <= 256, one workgroup per matrix: a GS x GS grid
+// of threads (GS = 16 up to n = 64, else 32: more waves hide more latency), thread (ty, tx) holding the
+// entries (ty + GS u, tx + GS v), u >= v, in registers.  The elimination of G
+// (G = L_u D L_u^T, L_u unit lower) and the inverse X = L_u^-1 run in the same
+// sweep over the columns and in the same registers.  With multipliers
+// m_i = G_ij / d_j (i > j), step j updates
 //   entries (i, k), k > j (still G):        G_ik -= m_i G_kj
 //   entries (i, k), k < j (S, see below):   S_ik -= m_i S_jk
 // and leaves column j alone.  S_ic = -d_c X_ic is X with column c scaled by
 // -d_c: the update of X is linear in each column, and at step c the value
 // held at (i, c), G_ic = m_i d_c, is exactly -d_c X_ic = -d_c (-m_i).  So the
-// column-to-X transition costs nothing.  Each step broadcasts through LDS
-// column j of G (rows >= j, including the pivot d_j) and row j of S (columns
-// < j), written by their owners at the end of step j-1; one barrier per step.
-// At the end X_ic = -S_ic / d_c and R^-1[c][i] = X_ic / sqrt(d_i).  Thread
-// (ty, tx) of the 32 x 32 grid holds the entries (ty + 32u, tx + 32v), u >= v.
-// Pivots d_j <= 1e-27 max(diag) drop their column: zero multipliers, and
-// row and column of X zero (as in chol_inv_regs).
-constexpr int kGjSide = 32;
-constexpr int NTC = kGjSide * kGjSide;
-constexpr int kGjWaves = NTC / 64;
-constexpr int kGjMaxR = 8;  // n <= 256
+// column-to-X transition costs nothing.  At the end X_ic = -S_ic / d_c and
+// R^-1[c][i] = X_ic / sqrt(d_i).
+//
+// Two columns (J, J+1) per step.  Their owners publish V1[k] = G_kJ (k >= J),
+// S_Jk (k < J) and V2[k] = G_k,J+1 (k >= J+1), S_J+1,k (k < J); an odd n is
+// padded with a dead pivot.  Step J+1 sees column J+1 and row J+1 as updated
+// by step J: d' = G_J+1,J+1 - m_J+1 G_J+1,J, multipliers
+// m'_i = (G_i,J+1 - m_i G_J+1,J) / d' and vector w2_k = G_k,J+1 - m_k G_J+1,J
+// (k > J+1), 0 (k = J+1), G_J+1,J (k = J: column J is S from step J+1 on),
+// S_J+1,k - m_J+1 S_Jk (k < J); step J's vector w1 is V1 with 0 at J.  Phase
+// A computes m, m', w1, w2 once per index into LDS; phase B applies both
+// rank-one updates in one pass over the registers and publishes the next
+// pair.  Two barriers per pair of columns.  Pivots d_j <= 1e-27 max(diag)
+// drop their column: zero multipliers, and row and column of X zero (as in
+// chol_inv_regs).
+constexpr int kGjMaxN = 256;
+#ifndef HCTM_GJ16_MAX
+#define HCTM_GJ16_MAX 64
+#endif
+constexpr int kGj16Max = HCTM_GJ16_MAX;  // largest n on the 16 x 16 grid
 
-template <int R>
+template <int GS, int R>
 __device__ void chol_gj(const SmallProb& P, double* buf, double* red, int* bad) {
+  constexpr int NTC = GS * GS, NWV = NTC / 64, L = GS * R;
   const int n = P.n, ld = P.lda, ldr = P.ldb;
   const double* G = P.a;
   double* Ri = P.b;
-  const int tid = threadIdx.x, tx = tid & (kGjSide - 1), ty = tid / kGjSide;
+  const int tid = threadIdx.x, tx = tid % GS, ty = tid / GS;
   const bool scale = (P.flags & 1) != 0;
   double* dsc = P.sv;
-  constexpr int L = kGjSide * R;
-  // buf: [2 buffers][V1, V2][L]
+  // buf: V1, V2 (published columns), M1, M2 (multipliers), W1, W2 (vectors)
+  double* V1 = buf;
+  double* V2 = buf + L;
+  double* M1 = buf + 2 * L;
+  double* M2 = buf + 3 * L;
+  double* W1 = buf + 4 * L;
+  double* W2 = buf + 5 * L;
   if (scale)
     for (int i = tid; i < n; i += NTC) {
       const double g = G[(long long)i * ld + i];
       dsc[i] = g > 0.0 ? sqrt(g) : 1.0;
     }
   if (tid == 0) *bad = 0;
-  for (int i = tid; i < 4 * L; i += NTC) buf[i] = 0.0;
+  for (int i = tid; i < 6 * L; i += NTC) buf[i] = 0.0;
   __syncthreads();
   double dmax = 0.0;
   for (int i = tid; i < n; i += NTC) {
@@ -505,7 +520,7 @@ __device__ void chol_gj(const SmallProb& P, double* buf, double* red, int* bad) 
   __syncthreads();
   dmax = red[0];
 #pragma unroll
-  for (int w = 1; w < kGjWaves; ++w) dmax = fmax(dmax, red[w]);
+  for (int w = 1; w < NWV; ++w) dmax = fmax(dmax, red[w]);
   const double shift = P.rel * dmax;
   const double thresh = 1e-27 * dmax;
 
@@ -514,7 +529,7 @@ __device__ void chol_gj(const SmallProb& P, double* buf, double* red, int* bad) 
   for (int u = 0; u < R; ++u)
 #pragma unroll
     for (int v = 0; v <= u; ++v) {
-      const int i = ty + kGjSide * u, k = tx + kGjSide * v;
+      const int i = ty + GS * u, k = tx + GS * v;
       double x = 0.0;
       if (i < n && k <= i) {
         x = G[(long long)i * ld + k];
@@ -523,120 +538,99 @@ __device__ void chol_gj(const SmallProb& P, double* buf, double* red, int* bad) 
       }
       a[u][v] = x;
     }
-  // Two columns per step (J, J+1), one barrier per step.  Published before
-  // the step: V1[k] = G_kJ (k >= J), S_Jk (k < J) and V2[k] = G_k,J+1
-  // (k >= J+1), S_J+1,k (k < J); an odd n is padded with a dead pivot.
-  // Step J is applied with multipliers m_i = G_iJ / d_J and vector w1
-  // (V1 with 0 at J); step J+1 sees column J+1 and row J+1 as updated by
-  // step J: d' = G_J+1,J+1 - m_J+1 G_J+1,J, multipliers
-  // m'_i = (G_i,J+1 - m_i G_J+1,J) / d' and vector w2_k = G_k,J+1 - m_k G_J+1,J
-  // (k > J+1), 0 (k = J+1), G_J+1,J (k = J: column J is S from step J+1 on),
-  // S_J+1,k - m_J+1 S_Jk (k < J).  Both updates go into one pass over the
-  // registers.
   if (tx == 0)
 #pragma unroll
-    for (int u = 0; u < R; ++u) buf[ty + kGjSide * u] = a[u][0];  // V1 of J = 0
+    for (int u = 0; u < R; ++u) V1[ty + GS * u] = a[u][0];  // column 0
   if (tx == 1)
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const int i = ty + kGjSide * u;
-      if (i >= 1) buf[L + i] = a[u][0];  // V2 of J = 0 (column 1)
+      const int i = ty + GS * u;
+      if (i >= 1) V2[i] = a[u][0];  // column 1
     }
   __syncthreads();
 
   for (int J = 0; J < n; J += 2) {
-    const double* V1 = buf + ((J >> 1) & 1) * 2 * L;
-    const double* V2 = V1 + L;
-    double* N1 = buf + (((J >> 1) + 1) & 1) * 2 * L;
-    double* N2 = N1 + L;
-    const int jb = J / kGjSide;
-    const double dJ = V1[J], g1 = V1[J + 1], e2 = V2[J + 1];
-    const double inv = dJ > thresh ? rcp_nr(dJ) : 0.0;
-    const double mJ1 = g1 * inv;
-    const double d2 = e2 - mJ1 * g1;
-    const double inv2 = d2 > thresh ? rcp_nr(d2) : 0.0;
+    // phase A: multipliers and update vectors, one index per thread
+    {
+      const double dJ = V1[J], g1 = V1[J + 1], e2 = V2[J + 1];
+      const double inv = dJ > thresh ? rcp_nr(dJ) : 0.0;
+      const double mJ1 = g1 * inv;
+      const double d2 = e2 - mJ1 * g1;
+      const double inv2 = d2 > thresh ? rcp_nr(d2) : 0.0;
+      for (int t = tid; t < L; t += NTC) {
+        const double v1 = V1[t], v2 = V2[t];
+        const double x1 = v1 * inv;
+        const double y2 = fma(-x1, g1, v2);  // G_t,J+1 - m_t G_J+1,J
+        M1[t] = t > J ? x1 : 0.0;
+        M2[t] = t > J + 1 ? y2 * inv2 : 0.0;
+        W1[t] = t == J ? 0.0 : v1;
+        W2[t] = t > J + 1 ? y2 : (t == J + 1 ? 0.0 : (t == J ? g1 : fma(-mJ1, v1, v2)));
+      }
+    }
+    __syncthreads();
+    // phase B: both rank-one updates; rows <= J are final
+    const int jb = J / GS;
     double m1[R], m2[R];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const int i = ty + kGjSide * u;
-      double x1 = V1[i] * inv;
-      double x2 = fma(-x1, g1, V2[i]) * inv2;
-      if (u == jb) {  // uniform: only the pivot block holds rows <= J+1
-        if (i <= J) x1 = 0.0;
-        if (i <= J + 1) x2 = 0.0;
-      }
-      m1[u] = x1;
-      m2[u] = x2;
+      m1[u] = M1[ty + GS * u];
+      m2[u] = M2[ty + GS * u];
     }
-    // column blocks one at a time, so that only the multipliers stay live
 #pragma unroll
     for (int v = 0; v < R; ++v) {
-      const int k = tx + kGjSide * v;
-      const double k1 = V1[k], k2 = V2[k];
-      double w1, w2;
-      if (v > jb) {
-        w1 = k1;
-        w2 = fma(-k1 * inv, g1, k2);
-      } else if (v < jb) {
-        w1 = k1;
-        w2 = fma(-mJ1, k1, k2);
-      } else {
-        w1 = k == J ? 0.0 : k1;
-        w2 = k > J + 1 ? fma(-k1 * inv, g1, k2)
-                       : (k == J + 1 ? 0.0 : (k == J ? g1 : fma(-mJ1, k1, k2)));
-      }
+      const double w1 = W1[tx + GS * v], w2 = W2[tx + GS * v];
 #pragma unroll
       for (int u = v; u < R; ++u) {
-        if (u < jb) continue;  // rows <= J are final (uniform)
+        if (u < jb) continue;  // uniform
         a[u][v] = fma(-m2[u], w2, fma(-m1[u], w1, a[u][v]));
       }
     }
-    // publish the next step's vectors (their entries are final now)
+    // publish the next pair of columns (their entries are final now)
     const int J2 = J + 2;
     if (J2 < n) {
-      const int b2 = J2 / kGjSide, l2 = J2 % kGjSide;  // J2 + 1 is in the same block
+      const int b2 = J2 / GS, l2 = J2 % GS;  // J2 + 1 is in the same block
 #pragma unroll
       for (int v = 0; v < R; ++v) {
         if (v != b2) continue;  // uniform
         if (tx == l2)
 #pragma unroll
           for (int u = v; u < R; ++u) {
-            const int i = ty + kGjSide * u;
-            if (i >= J2) N1[i] = a[u][v];
+            const int i = ty + GS * u;
+            if (i >= J2) V1[i] = a[u][v];
           }
         if (tx == l2 + 1)
 #pragma unroll
           for (int u = v; u < R; ++u) {
-            const int i = ty + kGjSide * u;
-            if (i >= J2 + 1) N2[i] = a[u][v];
+            const int i = ty + GS * u;
+            if (i >= J2 + 1) V2[i] = a[u][v];
           }
         if (ty == l2)
 #pragma unroll
           for (int c = 0; c <= v; ++c) {
-            const int k = tx + kGjSide * c;
-            if (k < J2) N1[k] = a[v][c];
+            const int k = tx + GS * c;
+            if (k < J2) V1[k] = a[v][c];
           }
         if (ty == l2 + 1)
 #pragma unroll
           for (int c = 0; c <= v; ++c) {
-            const int k = tx + kGjSide * c;
-            if (k < J2) N2[k] = a[v][c];
+            const int k = tx + GS * c;
+            if (k < J2) V2[k] = a[v][c];
           }
       }
     }
     __syncthreads();
   }
   // the pivots d_i sit on the diagonal: gather them through LDS
-  double* dg = buf;  // all reads of the last step are done
+  double* dg = M1;
   if (tx == ty)
 #pragma unroll
-    for (int u = 0; u < R; ++u) dg[ty + kGjSide * u] = a[u][u];
+    for (int u = 0; u < R; ++u) dg[ty + GS * u] = a[u][u];
   __syncthreads();
   int nbad = 0;
   double rs[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
-    const int i = ty + kGjSide * u;
+    const int i = ty + GS * u;
     const double d = i < n ? dg[i] : 1.0;
     rs[u] = d > thresh ? 1.0 / sqrt(d) : 0.0;
     if (i < n && !(d > thresh) && tx == 0) ++nbad;
@@ -647,7 +641,7 @@ __device__ void chol_gj(const SmallProb& P, double* buf, double* red, int* bad) 
   for (int u = 0; u < R; ++u)
 #pragma unroll
     for (int v = 0; v < R; ++v) {
-      const int i = ty + kGjSide * u, c = tx + kGjSide * v;
+      const int i = ty + GS * u, c = tx + GS * v;
       if (i < n && c < n) {
         double x = 0.0;
         if (v <= u && c <= i) {
@@ -665,13 +659,13 @@ __device__ void chol_gj(const SmallProb& P, double* buf, double* red, int* bad) 
   if (tid == 0 && P.info) *P.info = *bad;
 }
 
-// R = ceil(max n / kGjSide) of the batch; smaller problems carry zero blocks
-template <int R>
-__global__ __launch_bounds__(NTC) void chol_gj_kernel(SmallBatch b) {
-  __shared__ double buf[4 * kGjSide * R];
-  __shared__ double red[kGjWaves];
+// R = ceil(max n / GS) of the batch; smaller problems carry zero blocks
+template <int GS, int R>
+__global__ __launch_bounds__(GS * GS) void chol_gj_kernel(SmallBatch b) {
+  __shared__ double buf[6 * GS * R];
+  __shared__ double red[GS * GS / 64];
   __shared__ int bad;
-  chol_gj<R>(b.p[blockIdx.x], buf, red, &bad);
+  chol_gj<GS, R>(b.p[blockIdx.x], buf, red, &bad);
 }
 
 __global__ __launch_bounds__(NT) void chol_inv_kernel(SmallBatch b) {
@@ -1229,7 +1223,7 @@ void scale_inv(double* p, size_t n, const double* nrm, hipStream_t s) {
 void chol_inv(const std::vector<SmallProb>& probs, hipStream_t s) {
   // one-elimination register kernel for n <= 256, the LDS/global one above
   std::vector<SmallProb> small, large;
-  for (const SmallProb& p : probs) (p.n <= kGjSide * kGjMaxR ? small : large).push_back(p);
+  for (const SmallProb& p : probs) (p.n <= kGjMaxN ? small : large).push_back(p);
   for (int pass = 0; pass < 2; ++pass) {
     const std::vector<SmallProb>& v = pass == 0 ? small : large;
     for (size_t i = 0; i < v.size(); i += kMaxSmall) {
@@ -1239,15 +1233,23 @@ void chol_inv(const std::vector<SmallProb>& probs, hipStream_t s) {
       if (pass == 0) {
         int nmax = 1;
         for (int q = 0; q < b.n; ++q) nmax = std::max(nmax, b.p[q].n);
-        switch ((nmax + kGjSide - 1) / kGjSide) {
-          case 1: hipLaunchKernelGGL(chol_gj_kernel<1>, dim3(b.n), dim3(NTC), 0, s, b); break;
-          case 2: hipLaunchKernelGGL(chol_gj_kernel<2>, dim3(b.n), dim3(NTC), 0, s, b); break;
-          case 3: hipLaunchKernelGGL(chol_gj_kernel<3>, dim3(b.n), dim3(NTC), 0, s, b); break;
-          case 4: hipLaunchKernelGGL(chol_gj_kernel<4>, dim3(b.n), dim3(NTC), 0, s, b); break;
-          case 5: hipLaunchKernelGGL(chol_gj_kernel<5>, dim3(b.n), dim3(NTC), 0, s, b); break;
-          case 6: hipLaunchKernelGGL(chol_gj_kernel<6>, dim3(b.n), dim3(NTC), 0, s, b); break;
-          case 7: hipLaunchKernelGGL(chol_gj_kernel<7>, dim3(b.n), dim3(NTC), 0, s, b); break;
-          default: hipLaunchKernelGGL(chol_gj_kernel<8>, dim3(b.n), dim3(NTC), 0, s, b); break;
+        // 16 x 16 threads up to n = kGj16Max, 32 x 32 beyond
+        switch (nmax <= kGj16Max ? (nmax + 15) / 16 : 10 + (nmax + 31) / 32) {
+          case 1: hipLaunchKernelGGL((chol_gj_kernel<16, 1>), dim3(b.n), dim3(256), 0, s, b); break;
+          case 2: hipLaunchKernelGGL((chol_gj_kernel<16, 2>), dim3(b.n), dim3(256), 0, s, b); break;
+          case 3: hipLaunchKernelGGL((chol_gj_kernel<16, 3>), dim3(b.n), dim3(256), 0, s, b); break;
+          case 4: hipLaunchKernelGGL((chol_gj_kernel<16, 4>), dim3(b.n), dim3(256), 0, s, b); break;
+          case 5: hipLaunchKernelGGL((chol_gj_kernel<16, 5>), dim3(b.n), dim3(256), 0, s, b); break;
+          case 6: hipLaunchKernelGGL((chol_gj_kernel<16, 6>), dim3(b.n), dim3(256), 0, s, b); break;
+          case 7: hipLaunchKernelGGL((chol_gj_kernel<16, 7>), dim3(b.n), dim3(256), 0, s, b); break;
+          case 8: hipLaunchKernelGGL((chol_gj_kernel<16, 8>), dim3(b.n), dim3(256), 0, s, b); break;
+          case 9: hipLaunchKernelGGL((chol_gj_kernel<16, 9>), dim3(b.n), dim3(256), 0, s, b); break;
+          case 13: hipLaunchKernelGGL((chol_gj_kernel<32, 3>), dim3(b.n), dim3(1024), 0, s, b); break;
+          case 14: hipLaunchKernelGGL((chol_gj_kernel<32, 4>), dim3(b.n), dim3(1024), 0, s, b); break;
+          case 15: hipLaunchKernelGGL((chol_gj_kernel<32, 5>), dim3(b.n), dim3(1024), 0, s, b); break;
+          case 16: hipLaunchKernelGGL((chol_gj_kernel<32, 6>), dim3(b.n), dim3(1024), 0, s, b); break;
+          case 17: hipLaunchKernelGGL((chol_gj_kernel<32, 7>), dim3(b.n), dim3(1024), 0, s, b); break;
+          default: hipLaunchKernelGGL((chol_gj_kernel<32, 8>), dim3(b.n), dim3(1024), 0, s, b); break;
         }
       } else
         hipLaunchKernelGGL(chol_inv_kernel, dim3(b.n), dim3(NT), 0, s, b);
