@@ -36,12 +36,16 @@ int hctm_dev_chol_inv(double* G, double* Rinv, int n, double rel, int* info, voi
  * If V is not NULL (X square), V (n x n, row-major) receives the product of
  * the rotations, so that X_in V = X_out; vlog then needs
  * hctm_dev_jacobi_log_doubles(n, max_sweeps) doubles of scratch.
- * pre (2 <= pre < n, n <= 160 and m * n <= 19968; else ignored): the last
- * pre columns are first orthogonalised among themselves, sweeps[1] = the
- * sweeps of that phase (sweeps then holds 2 ints).  The result is the same
- * decomposition; only the number of rotations changes. */
+ * pre (2 <= pre < n; else ignored): the last pre columns are first
+ * orthogonalised among themselves, sweeps[1] = the sweeps of that phase
+ * (sweeps then holds 2 ints).  The result is the same decomposition; only
+ * the number of rotations changes.  work (m * n doubles, or NULL): device
+ * scratch that lets blocks with 160 < n <= 256 or m * n > 19968 (m <= 256)
+ * run with one wave per column pair on an L2-resident column-major copy;
+ * without it such blocks take the slow global-memory kernel (which ignores
+ * pre and vlog). */
 int hctm_dev_jacobi(double* X, int m, int n, double tol, int max_sweeps, int pre, double* sv, int* perm,
-                    int* sweeps, double* V, double* vlog, void* stream);
+                    int* sweeps, double* V, double* vlog, double* work, void* stream);
 
 /* Scratch doubles needed by hctm_dev_jacobi's rotation log. */
 long long hctm_dev_jacobi_log_doubles(int n, int max_sweeps);

@@ -89,7 +89,7 @@ def lib():
                           ctypes.c_int),
         "hctm_dev_chol_inv": ([vp, vp, ctypes.c_int, ctypes.c_double, vp, vp], ctypes.c_int),
         "hctm_dev_jacobi": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp,
-                             vp, vp],
+                             vp, vp, vp],
                             ctypes.c_int),
         "hctm_dev_jacobi_log_doubles": ([ctypes.c_int, ctypes.c_int], ctypes.c_longlong),
     }
@@ -329,12 +329,13 @@ def dev_chol_inv(G, Rinv, n, rel, info):
     _check(lib().hctm_dev_chol_inv(_ptr(G), _ptr(Rinv), n, rel, _ptr(info), _stream_ptr(torch)))
 
 
-def dev_jacobi(X, m, n, tol, max_sweeps, sv, perm, sweeps, V=None, vlog=None, pre=0):
+def dev_jacobi(X, m, n, tol, max_sweeps, sv, perm, sweeps, V=None, vlog=None, pre=0, work=None):
     torch = _torch()
     vp = _ptr(V) if V is not None else None
     lp = _ptr(vlog) if vlog is not None else None
+    wp = _ptr(work) if work is not None else None
     _check(lib().hctm_dev_jacobi(_ptr(X), m, n, tol, max_sweeps, pre, _ptr(sv), _ptr(perm), _ptr(sweeps), vp, lp,
-                                 _stream_ptr(torch)))
+                                 wp, _stream_ptr(torch)))
 
 
 def jacobi_log_doubles(n, max_sweeps):

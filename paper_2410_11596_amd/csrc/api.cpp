@@ -337,7 +337,7 @@ int hctm_dev_chol_inv(double* G, double* Rinv, int n, double rel, int* info, voi
 }
 
 int hctm_dev_jacobi(double* X, int m, int n, double tol, int max_sweeps, int pre, double* sv, int* perm,
-                    int* sweeps, double* V, double* vlog, void* stream) {
+                    int* sweeps, double* V, double* vlog, double* work, void* stream) {
   return guarded(nullptr, [&] {
     if (m < 1 || n < 1 || n > 1024) throw hctm::Error(CTM_E_ARG, "size out of range");
     hctm::SmallProb p{};
@@ -353,6 +353,7 @@ int hctm_dev_jacobi(double* X, int m, int n, double tol, int max_sweeps, int pre
     p.perm = perm;
     p.b = V;
     p.vlog = vlog;
+    p.work = work;
     if (V && m != n) throw hctm::Error(CTM_E_ARG, "V needs a square X");
     hctm::jacobi({p}, reinterpret_cast<hipStream_t>(stream));
   });

@@ -174,7 +174,11 @@ void Ctm::plan_memory(bool counting) {
     S.isv = ar_.take((size_t)lcap);
     S.perm = ti(lcap);
     S.info = ti(8);
-    S.vlog = ar_.take(jacobi_log_doubles(160, kJacobiSweeps));
+    // rotation log and column-major scratch of the Jacobi SVD (blocks up to
+    // 256 x 256 run in LDS or L2)
+    const int nj = (int)std::max<long long>(160, std::min<long long>(lcap, 256));
+    S.vlog = ar_.take(jacobi_log_doubles(nj, kJacobiSweeps));
+    S.jwork = ar_.take((size_t)nj * nj);
   }
   misc_ = ar_.take(64);
   kdev_ = ti(16);
@@ -771,6 +775,7 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
       // the oversampled trailing columns are the least converged ones
       p.pre = S->direct ? 0 : S->l - S->kg;
       p.vlog = S->vlog;
+      p.work = S->jwork;
       p.info = S->info + 1;
       p.sv = S->sv;
       p.perm = S->perm;

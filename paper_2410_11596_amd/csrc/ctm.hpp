@@ -58,6 +58,7 @@ struct GemmStats {
 struct SvdSector {
   int n = 0, l = 0, kg = 0, trusted = 0, k = 0, sweeps = 0, iters = 0;
   int kt = 0;            // Ritz columns decomposed (the leading kt of the basis)
+  double* jwork = nullptr;  // column-major scratch of the Jacobi SVD
   int passes = 1;        // CholeskyQR passes of the next orthonormalisation
   double rel0 = 1e-10;   // relative diagonal shift of its first pass
   bool direct = false;

@@ -953,14 +953,20 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
     nrm[j] = s2;
   }
   __syncthreads();
+  // phase 0 over the trailing pre columns (if any), phase 1 over all; one
+  // call site, so that the sweep loop is inlined once
   const int pre = (P.pre >= 2 && P.pre < n) ? P.pre : 0;
-  if (pre) {
-    const int sp = jacobi_sweeps(Xs, nrm, &any_rot, m, n - pre, pre, tol, small2, P.max_sweeps,
-                                 rlog ? rlog + jacobi_pre_log_offset(n, P.max_sweeps) : nullptr);
-    if (tid == 0 && P.info) P.info[1] = sp < 0 ? -sp : sp;
+  for (int ph = pre ? 0 : 1; ph < 2; ++ph) {
+    const int c0 = ph == 0 ? n - pre : 0, nn = ph == 0 ? pre : n;
+    double2* lg = (rlog && ph == 0) ? rlog + jacobi_pre_log_offset(n, P.max_sweeps) : rlog;
+    const int sw = jacobi_sweeps(Xs, nrm, &any_rot, m, c0, nn, tol, small2, P.max_sweeps, lg);
+    if (tid == 0 && P.info) {
+      if (ph == 0)
+        P.info[1] = sw < 0 ? -sw : sw;
+      else
+        P.info[0] = sw;
+    }
   }
-  const int sweeps = jacobi_sweeps(Xs, nrm, &any_rot, m, 0, n, tol, small2, P.max_sweeps, rlog);
-  if (tid == 0 && P.info) *P.info = sweeps;
   for (int j = tid; j < n; j += NT) {
     double s2 = 0.0;
     for (int k = 0; k < m; ++k) s2 += Xs[j * m + k] * Xs[j * m + k];
@@ -972,6 +978,158 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
   }
   __syncthreads();
   for (int j = tid; j < n; j += NT) {
+    const double v = nrm[j];
+    int rank = 0;
+    for (int i = 0; i < n; ++i) {
+      const double w = nrm[i];
+      rank += (w > v) || (w == v && i < j);
+    }
+    P.sv[rank] = v;
+    P.perm[rank] = j;
+  }
+}
+
+// Jacobi for blocks too large for LDS (n, m <= 256): X is copied column-major
+// into P.work (global memory; at most 512 KB, so it stays in L2), one wave
+// works on one column pair with four rows per lane, the pairs a wave owns in
+// a round are loaded together; column norms cached in LDS; same rotation
+// order, tests, log layout and phases as the LDS kernel.
+constexpr int kJacL2Max = 256;
+constexpr int kJacL2Threads = 1024;
+constexpr int kJacL2Rows = kJacL2Max / 64;  // rows per lane
+constexpr int kJacL2Batch = 4;              // pairs loaded together by a wave
+
+__device__ int jacobi_l2_sweeps(double* Xc, double* nrm, int* any_rot, int m, int c0, int nn, double tol,
+                                double small2, int max_sweeps, double2* lg) {
+  constexpr int NW = kJacL2Threads / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n2 = nn + (nn & 1), npairs = n2 / 2, rounds = n2 - 1;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (threadIdx.x == 0) *any_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < rounds; ++r) {
+      double2* lr = lg ? lg + ((long long)sweep * rounds + r) * npairs : nullptr;
+      for (int p0 = wave; p0 < npairs; p0 += NW * kJacL2Batch) {
+        double u[kJacL2Batch][kJacL2Rows], v[kJacL2Batch][kJacL2Rows];
+        int pi[kJacL2Batch], pj[kJacL2Batch];
+#pragma unroll
+        for (int bq = 0; bq < kJacL2Batch; ++bq) {
+          const int pp = p0 + bq * NW;
+          int i = 0, j = nn;  // j >= nn: no pair
+          if (pp < npairs) rr_pair(r, pp, n2, i, j);
+          pi[bq] = i;
+          pj[bq] = j;
+          const bool live = pp < npairs && j < nn;
+          const double* xi = Xc + (long long)(c0 + i) * m;
+          const double* xj = Xc + (long long)(c0 + (live ? j : i)) * m;
+#pragma unroll
+          for (int q = 0; q < kJacL2Rows; ++q) {
+            const int k = lane + 64 * q;
+            u[bq][q] = (live && k < m) ? xi[k] : 0.0;
+            v[bq][q] = (live && k < m) ? xj[k] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int bq = 0; bq < kJacL2Batch; ++bq) {
+          const int pp = p0 + bq * NW;
+          if (pp >= npairs) break;  // uniform in the wave
+          double c = 1.0, sn = 0.0;
+          if (pj[bq] < nn) {
+            const int i = c0 + pi[bq], j = c0 + pj[bq];
+            double g = 0.0;
+#pragma unroll
+            for (int q = 0; q < kJacL2Rows; ++q) g = fma(u[bq][q], v[bq][q], g);
+            g = wave_sum(g);
+            const double a = nrm[i], bb = nrm[j];
+            if (fmin(a, bb) > small2 && fabs(g) > tol * sqrt(a) * sqrt(bb)) {
+              const double zeta = (bb - a) * rcp_nr(2.0 * g);
+              const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+              c = rsq_nr(fma(t, t, 1.0));
+              sn = c * t;
+              double a2 = 0.0, b2 = 0.0;
+              double* xi = Xc + (long long)i * m;
+              double* xj = Xc + (long long)j * m;
+#pragma unroll
+              for (int q = 0; q < kJacL2Rows; ++q) {
+                const int k = lane + 64 * q;
+                const double x = c * u[bq][q] - sn * v[bq][q], y = sn * u[bq][q] + c * v[bq][q];
+                if (k < m) {
+                  xi[k] = x;
+                  xj[k] = y;
+                }
+                a2 = fma(x, x, a2);
+                b2 = fma(y, y, b2);
+              }
+              a2 = wave_sum(a2);
+              b2 = wave_sum(b2);
+              if (lane == 0) {
+                nrm[i] = a2;
+                nrm[j] = b2;
+                *any_rot = 1;
+              }
+            }
+          }
+          if (lane == 0 && lr) lr[pp] = make_double2(c, sn);
+        }
+      }
+      __syncthreads();
+    }
+    const int rot = *any_rot;
+    __syncthreads();
+    if (!rot) return sweep + 1;
+  }
+  return -max_sweeps;
+}
+
+__global__ __launch_bounds__(kJacL2Threads) void jacobi_l2_kernel(SmallBatch b) {
+  __shared__ int any_rot;
+  __shared__ double red[16];
+  __shared__ double nrm[kJacL2Max];
+  const SmallProb& P = b.p[blockIdx.x];
+  const int m = P.m, n = P.n, ld = P.lda;
+  double* X = P.a;
+  double* Xc = P.work;
+  double2* rlog = reinterpret_cast<double2*>(P.b);
+  const int tid = threadIdx.x;
+  double f2 = 0.0;
+  for (int e = tid; e < m * n; e += kJacL2Threads) {
+    const int r = e / n, c = e % n;
+    const double x = X[(long long)r * ld + c];
+    Xc[(long long)c * m + r] = x;
+    f2 += x * x;
+  }
+  f2 = block_sum(f2, red);  // includes barriers (and makes Xc visible to the workgroup)
+  const double small2 = f2 * (2.3e-16 * m) * (2.3e-16 * m);
+  const double tol = P.rel;
+  for (int j = tid; j < n; j += kJacL2Threads) {
+    double s2 = 0.0;
+    for (int k = 0; k < m; ++k) s2 += Xc[(long long)j * m + k] * Xc[(long long)j * m + k];
+    nrm[j] = s2;
+  }
+  __syncthreads();
+  const int pre = (P.pre >= 2 && P.pre < n) ? P.pre : 0;
+  for (int ph = pre ? 0 : 1; ph < 2; ++ph) {
+    const int c0 = ph == 0 ? n - pre : 0, nn = ph == 0 ? pre : n;
+    double2* lg = (rlog && ph == 0) ? rlog + jacobi_pre_log_offset(n, P.max_sweeps) : rlog;
+    const int sw = jacobi_l2_sweeps(Xc, nrm, &any_rot, m, c0, nn, tol, small2, P.max_sweeps, lg);
+    if (tid == 0 && P.info) {
+      if (ph == 0)
+        P.info[1] = sw < 0 ? -sw : sw;
+      else
+        P.info[0] = sw;
+    }
+  }
+  for (int j = tid; j < n; j += kJacL2Threads) {
+    double s2 = 0.0;
+    for (int k = 0; k < m; ++k) s2 += Xc[(long long)j * m + k] * Xc[(long long)j * m + k];
+    nrm[j] = sqrt(s2);
+  }
+  for (int e = tid; e < m * n; e += kJacL2Threads) {
+    const int r = e / n, c = e % n;
+    X[(long long)r * ld + c] = Xc[(long long)c * m + r];
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += kJacL2Threads) {
     const double v = nrm[j];
     int rank = 0;
     for (int i = 0; i < n; ++i) {
@@ -1024,8 +1182,8 @@ __device__ void replay_rotations(double* Vs, double2* Ls, const double2* lg, int
 }
 
 __global__ __launch_bounds__(256) void jacobi_v_kernel(SmallBatch b) {
-  __shared__ double Vs[160 * kVRows];
-  __shared__ double2 Ls[kVChunk * 80];
+  __shared__ double Vs[kJacL2Max * kVRows];
+  __shared__ double2 Ls[kVChunk * (kJacL2Max / 2)];
   const SmallProb& P = b.p[blockIdx.y];
   const int n = P.n;
   const int sweeps = P.info ? abs(P.info[0]) : 0;
@@ -1265,35 +1423,47 @@ size_t jacobi_log_doubles(int n, int max_sweeps) {
 }
 
 void jacobi(const std::vector<SmallProb>& probs, hipStream_t s) {
-  // LDS kernel (rotation log + parallel V rebuild) where X fits in LDS and a
-  // log buffer is given; global-memory kernel otherwise
-  std::vector<SmallProb> lds, glob;
+  // LDS kernel where X fits in LDS, L2 kernel up to 256 x 256 with a scratch
+  // copy, global-memory kernel otherwise; with V requested, the first two
+  // log their rotations and V is rebuilt in parallel afterwards
+  std::vector<SmallProb> lds, l2, glob;
   for (const SmallProb& p : probs) {
     if (p.n > 1024) throw Error(1, "jacobi: too many columns");
-    const bool fits = (long long)p.m * p.n <= kJacLds && p.n <= 160 && (!p.b || p.vlog);
-    (fits ? lds : glob).push_back(p);
+    const bool logok = !p.b || p.vlog;
+    if ((long long)p.m * p.n <= kJacLds && p.n <= 160 && logok)
+      lds.push_back(p);
+    else if (p.work && p.m <= kJacL2Max && p.n <= kJacL2Max && logok)
+      l2.push_back(p);
+    else
+      glob.push_back(p);
   }
-  for (size_t i = 0; i < lds.size(); i += kMaxSmall) {
-    SmallBatch b, bv;
-    b.n = bv.n = 0;
-    int nmax = 0;
-    for (size_t j = i; j < lds.size() && b.n < kMaxSmall; ++j) {
-      SmallProb p = lds[j];
-      p.b = lds[j].b ? p.vlog : nullptr;  // the Jacobi kernel writes the rotation log
-      b.p[b.n++] = p;
-      if (lds[j].b) {
-        SmallProb q = lds[j];
-        q.a = lds[j].b;  // V output
-        q.b = lds[j].vlog;
-        bv.p[bv.n++] = q;
-        nmax = std::max(nmax, q.n);
+  for (int kind = 0; kind < 2; ++kind) {
+    const std::vector<SmallProb>& v = kind == 0 ? lds : l2;
+    for (size_t i = 0; i < v.size(); i += kMaxSmall) {
+      SmallBatch b, bv;
+      b.n = bv.n = 0;
+      int nmax = 0;
+      for (size_t j = i; j < v.size() && b.n < kMaxSmall; ++j) {
+        SmallProb p = v[j];
+        p.b = v[j].b ? p.vlog : nullptr;  // the Jacobi kernel writes the rotation log
+        b.p[b.n++] = p;
+        if (v[j].b) {
+          SmallProb q = v[j];
+          q.a = v[j].b;  // V output
+          q.b = v[j].vlog;
+          bv.p[bv.n++] = q;
+          nmax = std::max(nmax, q.n);
+        }
       }
-    }
-    hipLaunchKernelGGL(jacobi_lds_kernel, dim3(b.n), dim3(NT), 0, s, b);
-    HCTM_HIP(hipGetLastError());
-    if (bv.n > 0) {
-      hipLaunchKernelGGL(jacobi_v_kernel, dim3((nmax + kVRows - 1) / kVRows, bv.n), dim3(256), 0, s, bv);
+      if (kind == 0)
+        hipLaunchKernelGGL(jacobi_lds_kernel, dim3(b.n), dim3(NT), 0, s, b);
+      else
+        hipLaunchKernelGGL(jacobi_l2_kernel, dim3(b.n), dim3(kJacL2Threads), 0, s, b);
       HCTM_HIP(hipGetLastError());
+      if (bv.n > 0) {
+        hipLaunchKernelGGL(jacobi_v_kernel, dim3((nmax + kVRows - 1) / kVRows, bv.n), dim3(256), 0, s, bv);
+        HCTM_HIP(hipGetLastError());
+      }
     }
   }
   for (size_t i = 0; i < glob.size(); i += kMaxSmall) {

@@ -18,6 +18,7 @@ struct SmallProb {
                    // Rinv is then D^-1 R^-1 (sv must point to n doubles of scratch)
   int pre;         // Jacobi (LDS kernel): the last pre columns are first orthogonalised among
                    // themselves (0: not); their sweep count goes to info[1]
+  double* work;    // Jacobi: m*n doubles of device scratch (enables the L2 kernel for n <= 256)
 };
 
 constexpr int kMaxSmall = 16;

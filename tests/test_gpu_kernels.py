@@ -105,9 +105,14 @@ def test_cholesky_inverse(hc, n):
     assert np.abs(Q.T @ Q - np.eye(n)).max() < 1e-11 * np.linalg.cond(X) ** 2
 
 
-@pytest.mark.parametrize("m,n,pre", [(1, 1, 0), (8, 5, 0), (8, 5, 2), (40, 40, 0), (40, 40, 16), (120, 97, 0),
-                                     (120, 97, 33), (126, 126, 42), (150, 150, 0), (201, 180, 0)])
-def test_jacobi_svd(hc, m, n, pre):
+@pytest.mark.parametrize("m,n,pre,l2", [(1, 1, 0, 0), (8, 5, 0, 0), (8, 5, 2, 0), (40, 40, 0, 0), (40, 40, 16, 0),
+                                        (120, 97, 0, 0), (120, 97, 33, 0), (126, 126, 42, 0), (150, 150, 0, 0),
+                                        (201, 180, 0, 0), (150, 150, 0, 1), (160, 160, 16, 1), (216, 216, 72, 1),
+                                        (201, 180, 0, 1), (256, 256, 0, 1), (33, 7, 3, 1)])
+def test_jacobi_svd(hc, m, n, pre, l2):
+    """Jacobi SVD in LDS (n <= 160), in L2 with a scratch copy (l2 = 1, n <=
+    256) or in global memory (no scratch); with and without the first phase
+    over the trailing columns."""
     rng = np.random.default_rng(m + n)
     # graded singular values, as in the CTMRG spectra
     U, _ = np.linalg.qr(rng.standard_normal((m, m)))
@@ -121,7 +126,8 @@ def test_jacobi_svd(hc, m, n, pre):
     sw = torch.zeros(4, dtype=torch.int32, device="cuda")
     V = torch.zeros((n, n), dtype=torch.float64, device="cuda") if m == n else None
     vlog = torch.zeros(max(1, hc.jacobi_log_doubles(n, 60)), dtype=torch.float64, device="cuda") if m == n else None
-    hc.dev_jacobi(dX, m, n, 1.1e-16 * m, 60, sv, perm, sw, V, vlog, pre=pre)
+    work = torch.zeros(m * n, dtype=torch.float64, device="cuda") if l2 else None
+    hc.dev_jacobi(dX, m, n, 1.1e-16 * m, 60, sv, perm, sw, V, vlog, pre=pre, work=work)
     torch.cuda.synchronize()
     if pre:
         assert int(sw[1].item()) >= 1
