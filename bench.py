@@ -103,6 +103,58 @@ def time_form(A, chi, form, steps, warmup, profile):
     return (t1 - t0), stats, phases, split
 
 
+def mixed_precision(A, chi, steps, warmup, refine_max=40, tol=1e-10):
+    """Block products of the moves in FP32 (CTM_PREC_FP32), timed like the
+    FP64 form; then the error of its RDMs and energy against the FP64 form
+    after the same iterations, and after FP64 refinement iterations against
+    the converged FP64 environment."""
+    import torch
+
+    from paper_2410_11596_amd import CTMRG, inputs
+
+    h = inputs.heisenberg_bond_matrix()
+
+    def obs(g):
+        return np.concatenate([g.rdm1().ravel(), g.rdm2("h").ravel(), g.rdm2("v").ravel()]), g.energy(h)
+
+    g32 = CTMRG(A, chi, precision="fp32")
+    g32.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g32.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g64 = CTMRG(A, chi).step(warmup + steps)
+    o32, e32 = obs(g32)
+    o64, e64 = obs(g64)
+    res = {"value": steps / (t1 - t0), "unit": "CTMRG iterations/s", "ms_per_step": 1e3 * (t1 - t0) / steps,
+           "precision": "fp32 block products of the moves (FP32 MFMA, FP32 accumulation); FP64 SVD, "
+                        "normalisation and observables",
+           "max_abs_err_rdm_vs_fp64_same_iterations": float(np.abs(o32 - o64).max()),
+           "abs_err_energy_vs_fp64_same_iterations": float(abs(e32 - e64))}
+    n64 = warmup + steps
+    while not g64.converged(tol)[0] and n64 < warmup + steps + refine_max:
+        g64.step(1)
+        n64 += 1
+    o64, e64 = obs(g64)
+    g32.set_precision("fp64")
+    errs = []
+    for r in range(1, refine_max + 1):
+        g32.step(1)
+        o, e = obs(g32)
+        errs.append((float(np.abs(o - o64).max()), float(abs(e - e64))))
+        if g32.converged(tol)[0] and r >= 3:
+            break
+    res["fp64_reference_iterations"] = n64
+    res["refinement"] = {"max_abs_err_rdm_after_3": errs[min(2, len(errs) - 1)][0],
+                         "abs_err_energy_after_3": errs[min(2, len(errs) - 1)][1],
+                         "iterations_to_delta_1e-10": len(errs),
+                         "max_abs_err_rdm_at_end": errs[-1][0], "abs_err_energy_at_end": errs[-1][1]}
+    g32.close()
+    g64.close()
+    return res
+
+
 def cpu_baseline(D, chi, split, seed=0):
     """The oracle's Z2 left move on a random saturated environment (timed once)."""
     from oracle import basis, ctmrg
@@ -147,6 +199,7 @@ def main():
     ap.add_argument("--chi", type=int, default=144)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-block-product run")
     ap.add_argument("--copy-check", type=int, default=0, metavar="BYTES",
                     help="before timing, copy BYTES three times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -220,6 +273,8 @@ def main():
         out["z2_over_dense"] = z2_rate / dense_rate
         out["dense_phases_ms_per_step"] = {k: 1e3 * v / args.dense_steps for k, v in
                                            zip(["corners", "halves", "svd", "renormalise"], dphases.tolist())}
+    if not args.no_mixed:
+        out["mixed"] = mixed_precision(A, args.chi, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.D, args.chi, (84, 60))
     print(json.dumps(out), flush=True)

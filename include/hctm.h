@@ -62,6 +62,14 @@ enum {
 
 enum { CTM_FORM_Z2 = 0, CTM_FORM_DENSE = 1 };
 
+/* Arithmetic of the block products of the moves (enlarged corners, halves,
+ * projectors, renormalisation).  CTM_PREC_FP32: operands rounded to FP32,
+ * FP32 matrix-core products and accumulation, FP64 results; the truncated
+ * SVD, the normalisations and the observables stay FP64.  A run in FP32 is
+ * brought back to the FP64 fixed point by further iterations in FP64
+ * (ctm_set_precision). */
+enum { CTM_PREC_FP64 = 0, CTM_PREC_FP32 = 1 };
+
 typedef struct {
   int form;                    /* CTM_FORM_Z2 (default) or CTM_FORM_DENSE */
   int Lx, Ly;                  /* unit cell, each in [1, 4] (default 1 x 1) */
@@ -75,6 +83,7 @@ typedef struct {
   int form_m;                  /* 0 (default): apply the decomposed matrix through the
                                   enlarged corners when few iterations are expected;
                                   1: always form it (H_d H_u) first */
+  int precision;               /* CTM_PREC_FP64 (default) or CTM_PREC_FP32 */
   unsigned long long seed;     /* seed of the subspace-iteration start blocks */
   int profile;                 /* 1: time every GEMM launch with HIP events (ctm_gemm_stats) */
   void* stream;                /* hipStream_t or NULL */
@@ -107,6 +116,10 @@ int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, const ctm_op
  * previous ones (see ctm_converged).
  */
 int ctm_step(ctm_ctx* c, int n_iter);
+
+/* Precision of the block products of the following ctm_step calls
+ * (CTM_PREC_FP64 or CTM_PREC_FP32); the environment is kept. */
+int ctm_set_precision(ctm_ctx* c, int precision);
 
 /*
  * delta = max over the four corners of every site of || s_new - s_old ||_2,

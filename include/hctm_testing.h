@@ -21,6 +21,12 @@ int hctm_dev_gemm(const double* A, const double* B, double* C, int M, int N, int
                   int ta, int tb, double alpha, double beta, const double* cscale, double* scratch,
                   long long scratch_doubles, void* stream);
 
+/* The same with the operands rounded to FP32 and FP32 matrix-core products
+ * and accumulation (CTM_PREC_FP32); C, alpha, beta and cscale stay FP64. */
+int hctm_dev_gemm_f32(const double* A, const double* B, double* C, int M, int N, int K, int lda, int ldb, int ldc,
+                      int ta, int tb, double alpha, double beta, const double* cscale, double* scratch,
+                      long long scratch_doubles, void* stream);
+
 /* Strided copy of a dense box of rank r <= 6: out[sum x_j ostr_j] =
  * in[sum x_j istr_j] (the permute-and-reshape step between block products). */
 int hctm_dev_copy(const double* in, double* out, int r, const int* dims, const long long* istr,

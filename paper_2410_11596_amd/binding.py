@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libhctm.so")
 
 CTM_OK, CTM_E_ARG, CTM_E_NOMEM, CTM_E_HIP, CTM_E_NUMERIC, CTM_E_STATE = range(6)
 CTM_FORM_Z2, CTM_FORM_DENSE = 0, 1
+CTM_PREC_FP64, CTM_PREC_FP32 = 0, 1
 ERROR_NAMES = {1: "CTM_E_ARG", 2: "CTM_E_NOMEM", 3: "CTM_E_HIP", 4: "CTM_E_NUMERIC", 5: "CTM_E_STATE"}
 
 # every C symbol that include/hctm.h and include/hctm_testing.h declare
@@ -22,8 +23,8 @@ EXPORTS = [
     "ctm_opts_default", "ctm_workspace_size", "ctm_init", "ctm_step", "ctm_converged",
     "ctm_rdm_1site", "ctm_rdm_2site", "ctm_energy", "ctm_free", "ctm_last_error",
     "ctm_env_epsilon", "ctm_s_err", "ctm_log_kappa", "ctm_num_records", "ctm_record",
-    "ctm_sector_dims", "ctm_timing", "ctm_gemm_stats",
-    "hctm_dev_gemm", "hctm_dev_copy", "hctm_dev_chol_inv", "hctm_dev_jacobi", "hctm_dev_jacobi_log_doubles",
+    "ctm_sector_dims", "ctm_timing", "ctm_gemm_stats", "ctm_set_precision",
+    "hctm_dev_gemm", "hctm_dev_gemm_f32", "hctm_dev_copy", "hctm_dev_chol_inv", "hctm_dev_jacobi", "hctm_dev_jacobi_log_doubles",
 ]
 
 
@@ -36,6 +37,7 @@ class CtmOpts(ctypes.Structure):
         ("svd_rel_cutoff", ctypes.c_double),
         ("svd_iters", ctypes.c_int),
         ("form_m", ctypes.c_int),
+        ("precision", ctypes.c_int),
         ("seed", ctypes.c_ulonglong),
         ("profile", ctypes.c_int),
         ("stream", ctypes.c_void_p),
@@ -85,6 +87,9 @@ def lib():
         "ctm_gemm_stats": ([ctx, dp, dp, P(ctypes.c_longlong), ctypes.c_int], ctypes.c_int),
         "hctm_dev_gemm": ([vp, vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.c_double, vp, vp,
                                                                ctypes.c_longlong, vp], ctypes.c_int),
+        "hctm_dev_gemm_f32": ([vp, vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.c_double, vp, vp,
+                                                                   ctypes.c_longlong, vp], ctypes.c_int),
+        "ctm_set_precision": ([ctx, ctypes.c_int], ctypes.c_int),
         "hctm_dev_copy": ([vp, vp, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_longlong), P(ctypes.c_longlong), vp],
                           ctypes.c_int),
         "hctm_dev_chol_inv": ([vp, vp, ctypes.c_int, ctypes.c_double, vp, vp], ctypes.c_int),
@@ -145,6 +150,13 @@ def _cell_array(A):
     return np.ascontiguousarray(A)
 
 
+def _precision_code(p):
+    codes = {"fp64": CTM_PREC_FP64, "fp32": CTM_PREC_FP32}
+    if p not in codes:
+        raise ValueError(f"precision must be one of {sorted(codes)}")
+    return codes[p]
+
+
 class CTMRG:
     """One CTMRG solve on the GPU (Z2 or plain form).
 
@@ -156,7 +168,7 @@ class CTMRG:
     """
 
     def __init__(self, A, chi, form="z2", boundary=None, svd_rel_cutoff=1e-12, svd_iters=12, seed=0x5EED,
-                 stream=None, torch_workspace=True, profile=False, form_m=False):
+                 stream=None, torch_workspace=True, profile=False, form_m=False, precision="fp64"):
         torch = _torch()
         A = _cell_array(A)
         self.Ly, self.Lx = A.shape[0], A.shape[1]
@@ -169,6 +181,7 @@ class CTMRG:
         o.svd_rel_cutoff = svd_rel_cutoff
         o.svd_iters = svd_iters
         o.form_m = 1 if form_m else 0
+        o.precision = _precision_code(precision)
         o.seed = seed
         o.profile = 1 if profile else 0
         self._b = None
@@ -207,6 +220,11 @@ class CTMRG:
 
     def __exit__(self, *exc):
         self.close()
+
+    def set_precision(self, precision):
+        """'fp64' or 'fp32' for the block products of the following steps."""
+        _check(lib().ctm_set_precision(self._ctx, _precision_code(precision)), self._ctx)
+        return self
 
     def step(self, n=1):
         _check(lib().ctm_step(self._ctx, int(n)), self._ctx)
@@ -304,13 +322,14 @@ def _stream_ptr(torch):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def dev_gemm(A, B, C, M, N, K, lda, ldb, ldc, ta=0, tb=0, alpha=1.0, beta=0.0, cscale=None, scratch=None):
+def dev_gemm(A, B, C, M, N, K, lda, ldb, ldc, ta=0, tb=0, alpha=1.0, beta=0.0, cscale=None, scratch=None,
+             f32=False):
     torch = _torch()
     cs = _ptr(cscale) if cscale is not None else None
     sp = _ptr(scratch) if scratch is not None else None
     sn = scratch.numel() if scratch is not None else 0
-    _check(lib().hctm_dev_gemm(_ptr(A), _ptr(B), _ptr(C), M, N, K, lda, ldb, ldc, ta, tb, alpha, beta, cs, sp, sn,
-                               _stream_ptr(torch)))
+    f = lib().hctm_dev_gemm_f32 if f32 else lib().hctm_dev_gemm
+    _check(f(_ptr(A), _ptr(B), _ptr(C), M, N, K, lda, ldb, ldc, ta, tb, alpha, beta, cs, sp, sn, _stream_ptr(torch)))
 
 
 def dev_copy(src, dst, dims, istr, ostr, in_offset=0, out_offset=0):

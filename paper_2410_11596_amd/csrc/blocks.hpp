@@ -174,7 +174,7 @@ inline void plan_contract(const BT& A, const BT& B, BT& C, double alpha, double 
   if (Lc.size > C.capacity) throw Error(2, "plan_contract: output capacity");
   for (int P = 0; P < 2; ++P) {
     const int Pk = P ^ La.tp;
-    GemmDesc d;
+    GemmDesc d{};
     d.M = (int)La.rows[P];
     d.K = (int)La.cols[Pk];
     d.N = (int)Lb.cols[Pk ^ Lb.tp];

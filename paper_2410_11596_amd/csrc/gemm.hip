@@ -17,9 +17,11 @@
 // contiguous row per 16 lanes; loads for step k+1 are issued into registers
 // before the MFMAs of step k.
 //
-// MFMA 16x16x4 f64 operand layout (measured on gfx950): lane l supplies
+// MFMA 16x16x4 operand layout (measured on gfx950): lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; its four accumulator values are
-// D[l / 16 + 4 * v][l % 16], v = 0..3.
+// D[l / 16 + 4 * v][l % 16] (FP64) or D[4 * (l / 16) + v][l % 16] (FP32),
+// v = 0..3.  The same kernel runs with FP32 operands in LDS and FP32 MFMAs
+// (CTM_PREC_FP32); the epilogue is FP64 either way.
 #include <algorithm>
 
 #include "hctm_internal.hpp"
@@ -97,8 +99,8 @@ __device__ __forceinline__ void load_tile(const double* __restrict__ X, int ld, 
   }
 }
 
-template <int ROWS>
-__device__ __forceinline__ void store_tile(double* __restrict__ S, int trans, const double (&reg)[ROWS * BK / NT]) {
+template <int ROWS, typename CT>
+__device__ __forceinline__ void store_tile(CT* __restrict__ S, int trans, const double (&reg)[ROWS * BK / NT]) {
   constexpr int PER = ROWS * BK / NT;
   constexpr int PITCH = ROWS + 4;
   const int t = threadIdx.x;
@@ -107,22 +109,49 @@ __device__ __forceinline__ void store_tile(double* __restrict__ S, int trans, co
     const int r = t / TPR;
     const int kb = (t % TPR) * PER;
 #pragma unroll
-    for (int i = 0; i < PER; ++i) S[(kb + i) * PITCH + r] = reg[i];
+    for (int i = 0; i < PER; ++i) S[(kb + i) * PITCH + r] = (CT)reg[i];
   } else {
     const int k = t / 16;
     const int rb = (t % 16) * PER;
 #pragma unroll
-    for (int i = 0; i < PER; ++i) S[k * PITCH + rb + i] = reg[i];
+    for (int i = 0; i < PER; ++i) S[k * PITCH + rb + i] = (CT)reg[i];
   }
 }
 
-template <int BM, int BN>
-__global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(Group g) {
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// MFMA 16x16x4 in the compute type: FP64 (v_mfma_f64_16x16x4f64) or FP32
+// (v_mfma_f32_16x16x4f32, FP32 products and accumulation); both take one
+// element of A and of B per lane and give four accumulator values per lane
+template <typename CT>
+struct Mfma;
+// Accumulator value v of lane (lk = l / 16, l % 16) holds row row(lk, v) of
+// the 16 x 16 block (measured on gfx950: lk + 4v for FP64, 4 lk + v for FP32).
+template <>
+struct Mfma<double> {
+  typedef v4d acc_t;
+  static __device__ __forceinline__ v4d op(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  typedef v4f acc_t;
+  static __device__ __forceinline__ v4f op(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+
+// One output tile of the grouped GEMM; CT = type of the staged operands and
+// of the MFMA (the output is FP64 either way).
+template <int BM, int BN, typename CT>
+__device__ __forceinline__ void gemm_tile(const Group& g, CT* As, CT* Bs) {
   constexpr int PA = BM + 4, PB = BN + 4;
   constexpr int WM = BM / 2, WN = BN / 2;  // per-wave sub-tile
   constexpr int TI = WM / 16, TJ = WN / 16;
-  __shared__ double As[BK * PA];
-  __shared__ double Bs[BK * PB];
+  typedef typename Mfma<CT>::acc_t acc_t;
 
   // XCD-aware order: blocks are dealt to the 8 XCDs round robin; give each
   // XCD a contiguous range of tiles so that neighbouring tiles share its L2.
@@ -149,11 +178,11 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(Group g) {
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
   const int li = lane & 15, lk = lane >> 4;
 
-  v4d acc[TI][TJ];
+  acc_t acc[TI][TJ];
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < TJ; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < TJ; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
   double ra[BM * BK / NT], rb[BN * BK / NT];
   load_tile<BM>(P.A, P.lda, P.ta, P.M, kend, m0, kbeg, ra);
@@ -173,7 +202,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(Group g) {
     }
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      double af[TI], bf[TJ];
+      CT af[TI], bf[TJ];
 #pragma unroll
       for (int i = 0; i < TI; ++i) af[i] = As[(kk + lk) * PA + wm + i * 16 + li];
 #pragma unroll
@@ -181,7 +210,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(Group g) {
 #pragma unroll
       for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < TJ; ++j) acc[i][j] = Mfma<CT>::op(af[i], bf[j], acc[i][j]);
     }
     __syncthreads();
     if (more) {
@@ -191,7 +220,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(Group g) {
     __syncthreads();
   }
 
-  // epilogue: lane holds D[lk + 4*v][li] of every 16x16 tile
+  // epilogue: lane holds D[row(lk, v)][li] of every 16x16 tile
   if (P.ksplit > 1) {
     double* part = P.part + (long long)ks * P.M * P.N;
 #pragma unroll
@@ -202,8 +231,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(Group g) {
         if (col >= P.N) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int row = m0 + wm + i * 16 + lk + 4 * v;
-          if (row < P.M) part[(long long)row * P.N + col] = acc[i][j][v];
+          const int row = m0 + wm + i * 16 + Mfma<CT>::row(lk, v);
+          if (row < P.M) part[(long long)row * P.N + col] = (double)acc[i][j][v];
         }
       }
     return;
@@ -217,9 +246,9 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(Group g) {
       const double cs = P.cscale ? P.cscale[col] : 1.0;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm + i * 16 + lk + 4 * v;
+        const int row = m0 + wm + i * 16 + Mfma<CT>::row(lk, v);
         if (row >= P.M) continue;
-        double val = P.alpha * acc[i][j][v] * cs;
+        double val = P.alpha * (double)acc[i][j][v] * cs;
         if (P.rscale) val *= P.rscale[row];
         double* c = P.C + (long long)row * P.ldc + col;
         if (P.beta != 0.0) val += P.beta * *c;
@@ -227,6 +256,20 @@ __global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(Group g) {
       }
     }
   }
+}
+
+template <int BM, int BN>
+__global__ __launch_bounds__(NT, 2) void gemm_f64_kernel(Group g) {
+  __shared__ double As[BK * (BM + 4)];
+  __shared__ double Bs[BK * (BN + 4)];
+  gemm_tile<BM, BN, double>(g, As, Bs);
+}
+
+template <int BM, int BN>
+__global__ __launch_bounds__(NT, 2) void gemm_f32_kernel(Group g) {
+  __shared__ float As[BK * (BM + 4)];
+  __shared__ float Bs[BK * (BN + 4)];
+  gemm_tile<BM, BN, float>(g, As, Bs);
 }
 
 // Sum the K slices of split problems in slice order and apply the epilogue.
@@ -262,7 +305,9 @@ long long tiles(const GemmDesc& d, int bm, int bn) {
 
 }  // namespace
 
-void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch, long long scratch_cap) {
+namespace {
+void gemm_one_type(const std::vector<GemmDesc>& probs, bool f32, hipStream_t s, double* scratch,
+                   long long scratch_cap) {
   // tile shape for the whole call, from how many workgroups it yields
   constexpr long long kFill = 240;  // about one workgroup per CU
   long long t128 = 0, t64 = 0;
@@ -282,10 +327,14 @@ void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch, lo
   long long split_mn = 0;
   auto flush = [&]() {
     if (g.n == 0) return;
-    if (cfg == 0)
+    if (cfg == 0 && !f32)
       hipLaunchKernelGGL((gemm_f64_kernel<128, 128>), dim3(g.total), dim3(NT), 0, s, g);
-    else
+    else if (!f32)
       hipLaunchKernelGGL((gemm_f64_kernel<64, 64>), dim3(g.total), dim3(NT), 0, s, g);
+    else if (cfg == 0)
+      hipLaunchKernelGGL((gemm_f32_kernel<128, 128>), dim3(g.total), dim3(NT), 0, s, g);
+    else
+      hipLaunchKernelGGL((gemm_f32_kernel<64, 64>), dim3(g.total), dim3(NT), 0, s, g);
     HCTM_HIP(hipGetLastError());
     if (any_split) {
       // one thread per output element of the largest split problem
@@ -351,6 +400,16 @@ void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch, lo
     g.n++;
   }
   flush();
+}
+}  // namespace
+
+void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch, long long scratch_cap) {
+  // FP64 and FP32-compute problems go to separate launches (all problems of
+  // one call are independent)
+  std::vector<GemmDesc> p64, p32;
+  for (const GemmDesc& d : probs) (d.f32 ? p32 : p64).push_back(d);
+  if (!p64.empty()) gemm_one_type(p64, false, s, scratch, scratch_cap);
+  if (!p32.empty()) gemm_one_type(p32, true, s, scratch, scratch_cap);
 }
 
 }  // namespace hctm

@@ -36,6 +36,7 @@ struct GemmDesc {
   double alpha, beta;
   const double* cscale;
   const double* rscale;  // optional per-row scale of the product
+  int f32;               // 1: operands rounded to FP32, FP32 MFMA and accumulation
 };
 // scratch (optional): device doubles for split-K partial tiles.
 void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch = nullptr, long long scratch_cap = 0);

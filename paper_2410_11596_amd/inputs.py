@@ -72,3 +72,13 @@ def ising_classical(beta):
     eb = np.exp(beta)
     Q = _sym_sqrt(np.array([[eb, 1.0 / eb], [1.0 / eb, eb]]))
     return np.einsum("su,sl,sd,sr->uldr", Q, Q, Q, Q)
+
+
+def heisenberg_bond_matrix():
+    """The Heisenberg bond S.S (J = 1) of two spins 1/2 in the basis
+    |uu>, |ud>, |du>, |dd>: 1/4 on the aligned states, -1/4 and the exchange
+    1/2 on the antialigned pair."""
+    return np.array([[0.25, 0.0, 0.0, 0.0],
+                     [0.0, -0.25, 0.5, 0.0],
+                     [0.0, 0.5, -0.25, 0.0],
+                     [0.0, 0.0, 0.0, 0.25]])

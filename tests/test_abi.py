@@ -56,6 +56,7 @@ def test_opts_default(L):
     assert o.svd_iters == 12
     assert not o.boundary and not o.stream and not o.workspace
     assert o.Lx == 1 and o.Ly == 1
+    assert o.precision == binding.CTM_PREC_FP64
     assert L.ctm_opts_default(None) == binding.CTM_E_ARG
 
 
@@ -99,6 +100,8 @@ def test_option_checks(L):
     assert _ws(L, 2, 2, 8, svd_iters=0)[0] == binding.CTM_E_ARG
     assert _ws(L, 2, 2, 8, Lx=0)[0] == binding.CTM_E_ARG
     assert _ws(L, 2, 2, 8, Ly=5)[0] == binding.CTM_E_ARG
+    assert _ws(L, 2, 2, 8, precision=2)[0] == binding.CTM_E_ARG
+    assert _ws(L, 2, 2, 8, precision=binding.CTM_PREC_FP32)[0] == 0
     # the Z2 form needs a swap-symmetric boundary vector; the plain form does not
     b = np.array([1.0, 0.5, 0.0, 1.0])
     assert _ws(L, 2, 2, 8, boundary=b)[0] == binding.CTM_E_ARG
@@ -125,6 +128,7 @@ def test_init_rejects_bad_arguments_before_touching_a_device(L):
 def test_null_context(L):
     L.ctm_free(None)
     assert L.ctm_step(None, 1) == binding.CTM_E_ARG
+    assert L.ctm_set_precision(None, binding.CTM_PREC_FP32) == binding.CTM_E_ARG
     n = ctypes.c_int(0)
     assert L.ctm_num_records(None, ctypes.byref(n)) == binding.CTM_E_ARG
     assert isinstance(L.ctm_last_error(None), bytes)

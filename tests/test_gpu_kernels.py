@@ -39,6 +39,32 @@ def test_gemm_matches_numpy(hc, M, N, K, ta, tb):
     assert np.abs(out - ref).max() <= 1e-14 * scale
 
 
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 33, 5), (130, 129, 257), (300, 260, 1000), (2600, 100, 2600)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_f32_matches_rounded_operands(hc, M, N, K, ta, tb):
+    """FP32 products (CTM_PREC_FP32): equal to the product of the operands
+    rounded to FP32, up to FP32 accumulation, K * 2^-24 |A||B| per entry."""
+    rng = np.random.default_rng(M * 1000 + N * 10 + K + 7 * ta + 3 * tb)
+    A = rng.standard_normal((K, M) if ta else (M, K))
+    B = rng.standard_normal((N, K) if tb else (K, N))
+    C0 = rng.standard_normal((M, N))
+    cs = rng.standard_normal(N)
+    A32, B32 = A.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64)
+    opA, opB = (A32.T if ta else A32), (B32.T if tb else B32)
+    ref = 1.5 * (opA @ opB) * cs[None, :] - 0.5 * C0
+    bound = 1.5 * K * 2.0 ** -24 * (np.abs(opA) @ np.abs(opB)) * np.abs(cs)[None, :] + 1e-14 * np.abs(C0)
+    dA, dB, dC, dcs = _dev(A), _dev(B), _dev(C0), _dev(cs)
+    scratch = torch.zeros(16 * M * N, dtype=torch.float64, device="cuda")
+    hc.dev_gemm(dA, dB, dC, M, N, K, A.shape[1], B.shape[1], N, ta, tb, 1.5, -0.5, dcs, scratch, f32=True)
+    torch.cuda.synchronize()
+    out = dC.cpu().numpy()
+    assert np.all(np.abs(out - ref) <= bound)
+    # and it is not the FP64 product: the operand rounding shows at K >= 5
+    if K >= 5:
+        ref64 = 1.5 * ((A.T if ta else A) @ (B.T if tb else B)) * cs[None, :] - 0.5 * C0
+        assert np.abs(out - ref64).max() > 1e-12
+
+
 @pytest.mark.parametrize("M,N,K,ta", [(126, 126, 2600, 1), (60, 84, 5000, 0), (7, 300, 3000, 1)])
 def test_gemm_split_k(hc, M, N, K, ta):
     """Small outputs with a long reduction are split over K (Gram matrices)."""
