@@ -933,8 +933,9 @@ void Ctm::move(int r) {
       // Form H_u, H_d and M only when the subspace iteration is expected to
       // be long (the last truncation at this cut needed many iterations) or
       // a sector is small enough to be decomposed directly; otherwise apply
-      // M through the corners.
-      bool implicit = !opt_.form_m && iters_prev_[key] > 0 && iters_prev_[key] <= kImplicitIters;
+      // M through the corners.  The first truncation at a cut (bonds still
+      // growing, blocks and subspace large) applies it too.
+      bool implicit = !opt_.form_m && iters_prev_[key] <= kImplicitIters;
       for (int P = 0; P < 2; ++P) {
         const int n = (int)Q2.L.cols[P];
         if (n == 0) continue;
