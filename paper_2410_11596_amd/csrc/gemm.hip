@@ -378,7 +378,7 @@ void gemm_one_type(const std::vector<GemmDesc>& probs, bool f32, hipStream_t s, 
     p.tiles_n = (d.N + bn - 1) / bn;
     // split K when the call has too few output tiles and this K is long
     int ks = 1;
-    if (cfg == 1 && t64 < kFill && scratch) {
+    if (cfg == 1 && t64 < 4 * kFill && scratch) {
       const long long want = (4 * kFill + t64 - 1) / t64;  // about 4 workgroups per CU
       const long long maxk = d.K / 64;  // at least 64 of K per slice
       ks = (int)std::max<long long>(1, std::min(want, maxk));
