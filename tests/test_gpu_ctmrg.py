@@ -139,3 +139,18 @@ def test_corner_applied_matrix_matches_formed_matrix_d6():
     assert np.abs(ga.rdm2("h") - gf.rdm2("h")).max() < TOL
     assert np.abs(ga.rdm2("v") - gf.rdm2("v")).max() < TOL
     assert ga.s_err() <= 1e-15
+
+
+@pytest.mark.parametrize("D,chi", [(1, 1), (1, 4), (2, 1), (3, 2)])
+@pytest.mark.parametrize("form", ["z2", "dense"])
+def test_degenerate_sizes(D, chi, form):
+    """Bond dimension one (a product state: no odd sector at all), and
+    truncation to one or two states (the kept count below the sector sizes)."""
+    A = inputs.iid_tensor(2, D, 3)
+    o = ctmrg.Run(chi, form, A=A).step(3)
+    g = _gpu_run(A, chi, form, 3)
+    _compare(g, o)
+    assert [tuple(r["kept"]) for r in g.records()] == [tuple(r["kept"]) for r in o.records]
+    if D == 1:
+        a = A.reshape(2)
+        assert np.abs(g.rdm1() - np.outer(a, a) / (a @ a)).max() < 1e-14

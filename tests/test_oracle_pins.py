@@ -285,3 +285,17 @@ def test_dense_and_z2_forms_agree(D, chi, iters):
     assert np.array_equal(z2.rho1(), z2.rho1().T)
     assert np.array_equal(z2.rho2("h"), z2.rho2("h").T)
     assert z2.s_err() <= 1e-15
+
+
+def test_bond_dimension_one_is_a_product_state():
+    """D = 1: every site is the vector A[:, 0, 0, 0, 0], so rho1 is its
+    projector and rho2 the product of two, in both forms."""
+    from paper_2410_11596_amd import inputs
+
+    A = inputs.iid_tensor(2, 1, 3)
+    a = A.reshape(2)
+    p = np.outer(a, a) / (a @ a)
+    for form in ("z2", "dense"):
+        o = ctmrg.Run(3, form, A=A).step(2)
+        assert np.abs(o.rho1() - p).max() < 1e-14
+        assert np.abs(o.rho2("h") - np.kron(p, p)).max() < 1e-14
