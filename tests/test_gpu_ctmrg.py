@@ -154,3 +154,27 @@ def test_degenerate_sizes(D, chi, form):
     if D == 1:
         a = A.reshape(2)
         assert np.abs(g.rdm1() - np.outer(a, a) / (a @ a)).max() < 1e-14
+
+
+def test_largest_shape_d8_chi256_forms_agree():
+    """D = 8 (36 + 28), chi = 256, the largest configuration: two iterations
+    of the Z2 and plain forms agree (kept spectra, sector sizes, RDMs), and
+    the Z2 RDMs are Hermitian bit for bit with S_err = 0.  Too large for the
+    oracle; the two forms share the code but not the block structure."""
+    A = inputs.iid_tensor(2, 8, 0)
+    gz = _gpu_run(A, 256, "z2", 2)
+    gd = _gpu_run(A, 256, "dense", 2)
+    rz, rd = gz.records(), gd.records()
+    assert len(rz) == len(rd) == 8
+    for a, b in zip(rz, rd):
+        k = sum(a["kept"])
+        assert k == sum(b["kept"])
+        assert np.allclose(a["spectrum"][:k], b["spectrum"][:k], rtol=1e-8, atol=1e-13)
+    for dr in ("h", "v"):
+        assert np.abs(gz.rdm2(dr) - gd.rdm2(dr)).max() < TOL
+        r2 = gz.rdm2(dr)
+        assert np.array_equal(r2, r2.T) and abs(np.trace(r2) - 1.0) < 1e-12
+    assert np.abs(gz.rdm1() - gd.rdm1()).max() < TOL
+    assert gz.s_err() == 0.0
+    gz.close()
+    gd.close()
