@@ -24,6 +24,7 @@ EXPORTS = [
     "ctm_rdm_1site", "ctm_rdm_2site", "ctm_energy", "ctm_free", "ctm_last_error",
     "ctm_env_epsilon", "ctm_s_err", "ctm_log_kappa", "ctm_num_records", "ctm_record",
     "ctm_sector_dims", "ctm_timing", "ctm_gemm_stats", "ctm_set_precision",
+    "ctm_server_create", "ctm_server_submit", "ctm_server_wait", "ctm_server_load", "ctm_server_destroy",
     "hctm_dev_gemm", "hctm_dev_gemm_f32", "hctm_dev_copy", "hctm_dev_chol_inv", "hctm_dev_jacobi", "hctm_dev_jacobi_log_doubles",
 ]
 
@@ -43,6 +44,19 @@ class CtmOpts(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("iterations", ctypes.c_int),
+        ("converged", ctypes.c_int),
+        ("delta", ctypes.c_double),
+        ("t_submit", ctypes.c_double),
+        ("t_start", ctypes.c_double),
+        ("t_end", ctypes.c_double),
+        ("message", ctypes.c_char * 160),
     ]
 
 
@@ -90,6 +104,12 @@ def lib():
         "hctm_dev_gemm_f32": ([vp, vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.c_double, vp, vp,
                                                                    ctypes.c_longlong, vp], ctypes.c_int),
         "ctm_set_precision": ([ctx, ctypes.c_int], ctypes.c_int),
+        "ctm_server_create": ([P(ctypes.c_void_p), ctypes.c_size_t, ctypes.c_int], ctypes.c_int),
+        "ctm_server_submit": ([ctypes.c_void_p, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                               ctypes.c_double, ctypes.c_int, P(ctypes.c_longlong)], ctypes.c_int),
+        "ctm_server_wait": ([ctypes.c_void_p, ctypes.c_longlong, dp, dp, dp, P(SolveInfo)], ctypes.c_int),
+        "ctm_server_load": ([ctypes.c_void_p, ip, ip], ctypes.c_int),
+        "ctm_server_destroy": ([ctypes.c_void_p], None),
         "hctm_dev_copy": ([vp, vp, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_longlong), P(ctypes.c_longlong), vp],
                           ctypes.c_int),
         "hctm_dev_chol_inv": ([vp, vp, ctypes.c_int, ctypes.c_double, vp, vp], ctypes.c_int),
@@ -359,3 +379,54 @@ def dev_jacobi(X, m, n, tol, max_sweeps, sv, perm, sweeps, V=None, vlog=None, pr
 
 def jacobi_log_doubles(n, max_sweeps):
     return int(lib().hctm_dev_jacobi_log_doubles(n, max_sweeps))
+
+
+class Server:
+    """Concurrent CTMRG solves on one GPU (include/hctm_serve.h): solves are
+    admitted first come, first served, by their workspace in a device pool
+    of pool_bytes, at most max_active at a time, each on its own stream and
+    host worker thread inside the library."""
+
+    def __init__(self, pool_bytes, max_active=8):
+        s = ctypes.c_void_p()
+        _check(lib().ctm_server_create(ctypes.byref(s), int(pool_bytes), int(max_active)))
+        self._s = s
+        self._d = {}
+
+    def submit(self, A, chi, form="z2", tol=1e-10, max_iter=100):
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        d, D = A.shape[0], A.shape[1]
+        i = ctypes.c_longlong()
+        code = CTM_FORM_Z2 if form == "z2" else CTM_FORM_DENSE
+        _check(lib().ctm_server_submit(self._s, _dptr(A), d, D, int(chi), code, float(tol), int(max_iter),
+                                       ctypes.byref(i)))
+        self._d[i.value] = d
+        return i.value
+
+    def wait(self, sid):
+        d = self._d.pop(sid)
+        r1 = np.zeros((d * d,))
+        rh = np.zeros((d ** 4,))
+        rv = np.zeros((d ** 4,))
+        info = SolveInfo()
+        _check(lib().ctm_server_wait(self._s, sid, _dptr(r1), _dptr(rh), _dptr(rv), ctypes.byref(info)))
+        return {"status": info.status, "message": info.message.decode(errors="replace"),
+                "iterations": info.iterations, "converged": bool(info.converged), "delta": info.delta,
+                "t_submit": info.t_submit, "t_start": info.t_start, "t_end": info.t_end,
+                "rho1": r1.reshape(d, d), "rho2_h": rh.reshape(d * d, d * d), "rho2_v": rv.reshape(d * d, d * d)}
+
+    def load(self):
+        w, r = ctypes.c_int(), ctypes.c_int()
+        _check(lib().ctm_server_load(self._s, ctypes.byref(w), ctypes.byref(r)))
+        return w.value, r.value
+
+    def close(self):
+        if getattr(self, "_s", None):
+            lib().ctm_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

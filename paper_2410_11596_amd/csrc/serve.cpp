@@ -1,0 +1,301 @@
+// Serving of independent CTMRG solves on one GPU (include/hctm_serve.h).
+//
+// Each admitted solve runs on its own host thread, HIP stream and context,
+// with its workspace carved from one device pool, so that the host
+// synchronisations inside a solve (the convergence tests of the truncated
+// SVD, the kept counts) never hold up the others and their kernels overlap
+// on the device.  Admission is first come, first served, by pool space and a
+// cap on concurrent solves.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "hctm.h"
+#include "hctm_serve.h"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+struct Request {
+  long long id = 0;
+  std::vector<double> A;
+  int d = 0, D = 0, chi = 0, form = 0, max_iter = 0;
+  double tol = 0.0;
+  size_t ws = 0;   // workspace bytes (ctm_workspace_size)
+  size_t off = 0;  // its place in the pool
+  bool done = false;
+  bool claimed = false;  // a caller waits for it
+  ctm_solve_info info{};
+  std::vector<double> rho1, rho2h, rho2v;
+};
+
+// First-fit allocator over the pool: free ranges by offset, merged on return.
+class Pool {
+ public:
+  void reset(size_t n) {
+    free_.clear();
+    free_[0] = n;
+  }
+  bool take(size_t n, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      const size_t o = it->first, rest = it->second - n;
+      free_.erase(it);
+      if (rest) free_[o + n] = rest;
+      *off = o;
+      return true;
+    }
+    return false;
+  }
+  void give(size_t off, size_t n) {
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+};
+
+void set_message(ctm_solve_info& info, const std::string& m) {
+  std::strncpy(info.message, m.c_str(), sizeof(info.message) - 1);
+  info.message[sizeof(info.message) - 1] = '\0';
+}
+
+}  // namespace
+
+struct ctm_server {
+  int device = 0;
+  char* pool_base = nullptr;
+  size_t pool_bytes = 0;
+  int max_active = 1;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Request*> waiting;
+  std::map<long long, std::unique_ptr<Request>> all;
+  int running = 0;
+  long long next_id = 1;
+  Pool pool;
+  std::vector<std::thread> threads;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+
+  // Start the oldest waiting solves while they fit (called with mu held).
+  void admit_locked() {
+    while (!waiting.empty() && running < max_active) {
+      Request* r = waiting.front();
+      size_t off = 0;
+      if (!pool.take(round_up(r->ws), &off)) break;
+      waiting.pop_front();
+      r->off = off;
+      r->info.t_start = now();
+      ++running;
+      try {
+        threads.emplace_back(&ctm_server::run, this, r);
+      } catch (const std::exception& e) {
+        --running;
+        pool.give(off, round_up(r->ws));
+        r->info.status = CTM_E_NOMEM;
+        set_message(r->info, std::string("could not start a worker thread: ") + e.what());
+        r->info.t_end = now();
+        r->done = true;
+        cv.notify_all();
+      }
+    }
+  }
+
+  void run(Request* r) {
+    int rc = CTM_OK;
+    std::string msg;
+    hipStream_t st = nullptr;
+    ctm_ctx* c = nullptr;
+    int it = 0, conv = 0;
+    double delta = INFINITY;
+    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      rc = CTM_E_HIP;
+      msg = "could not create a stream for the solve";
+      st = nullptr;
+    }
+    try {
+      if (rc == CTM_OK) {
+        ctm_opts o;
+        ctm_opts_default(&o);
+        o.form = r->form;
+        o.stream = st;
+        o.workspace = pool_base + r->off;
+        o.workspace_bytes = r->ws;
+        rc = ctm_init(&c, r->A.data(), r->d, r->D, r->chi, &o);
+        if (rc != CTM_OK) msg = ctm_last_error(nullptr);
+      }
+      while (rc == CTM_OK && it < r->max_iter) {
+        rc = ctm_step(c, 1);
+        if (rc != CTM_OK) break;
+        ++it;
+        rc = ctm_converged(c, r->tol, &conv, &delta);
+        if (rc != CTM_OK || conv) break;
+      }
+      if (rc == CTM_OK) {
+        const size_t d2 = (size_t)r->d * r->d;
+        r->rho1.resize(d2);
+        r->rho2h.resize(d2 * d2);
+        r->rho2v.resize(d2 * d2);
+        rc = ctm_rdm_1site(c, 0, 0, r->rho1.data());
+        if (rc == CTM_OK) rc = ctm_rdm_2site(c, 0, 0, 0, r->rho2h.data());
+        if (rc == CTM_OK) rc = ctm_rdm_2site(c, 0, 0, 1, r->rho2v.data());
+      }
+      if (rc != CTM_OK && c) msg = ctm_last_error(c);
+    } catch (const std::exception& e) {
+      rc = CTM_E_NOMEM;
+      msg = std::string("host allocation failed: ") + e.what();
+    }
+    ctm_free(c);
+    if (st) {
+      // nothing of this solve may still run when its pool space is reused
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    pool.give(r->off, round_up(r->ws));
+    --running;
+    r->info.status = rc;
+    r->info.iterations = it;
+    r->info.converged = conv;
+    r->info.delta = delta;
+    r->info.t_end = now();
+    if (rc != CTM_OK) set_message(r->info, msg);
+    r->done = true;
+    admit_locked();
+    cv.notify_all();
+  }
+};
+
+extern "C" {
+
+int ctm_server_create(ctm_server** out, size_t pool_bytes, int max_active) {
+  if (!out) return CTM_E_ARG;
+  *out = nullptr;
+  if (pool_bytes == 0 || max_active < 1 || max_active > 64) return CTM_E_ARG;
+  std::unique_ptr<ctm_server> s;
+  try {
+    s.reset(new ctm_server());
+  } catch (const std::bad_alloc&) {
+    return CTM_E_NOMEM;
+  }
+  if (hipGetDevice(&s->device) != hipSuccess) return CTM_E_HIP;
+  void* p = nullptr;
+  if (hipMalloc(&p, pool_bytes) != hipSuccess) return CTM_E_NOMEM;
+  s->pool_base = static_cast<char*>(p);
+  s->pool_bytes = pool_bytes;
+  s->max_active = max_active;
+  s->pool.reset(pool_bytes);
+  *out = s.release();
+  return CTM_OK;
+}
+
+int ctm_server_submit(ctm_server* s, const double* A, int d, int D, int chi, int form, double tol, int max_iter,
+                      long long* id) {
+  if (!s || !A || !id) return CTM_E_ARG;
+  if (form != CTM_FORM_Z2 && form != CTM_FORM_DENSE) return CTM_E_ARG;
+  if (!(tol > 0.0) || max_iter < 1) return CTM_E_ARG;
+  ctm_opts o;
+  ctm_opts_default(&o);
+  o.form = form;
+  size_t ws = 0;
+  const int rc = ctm_workspace_size(d, D, chi, &o, &ws);  // checks d, D, chi
+  if (rc != CTM_OK) return rc;
+  if (round_up(ws) > s->pool_bytes) return CTM_E_NOMEM;
+  try {
+    std::unique_ptr<Request> r(new Request());
+    const size_t n = (size_t)d * D * D * D * D;
+    r->A.assign(A, A + n);
+    for (double x : r->A)
+      if (!std::isfinite(x)) return CTM_E_NUMERIC;
+    r->d = d;
+    r->D = D;
+    r->chi = chi;
+    r->form = form;
+    r->tol = tol;
+    r->max_iter = max_iter;
+    r->ws = ws;
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->id = s->next_id++;
+    r->info.t_submit = s->now();
+    *id = r->id;
+    Request* raw = r.get();
+    s->all[r->id] = std::move(r);
+    s->waiting.push_back(raw);
+    s->admit_locked();
+  } catch (const std::bad_alloc&) {
+    return CTM_E_NOMEM;
+  }
+  return CTM_OK;
+}
+
+int ctm_server_wait(ctm_server* s, long long id, double* rho1, double* rho2_h, double* rho2_v,
+                    ctm_solve_info* info) {
+  if (!s) return CTM_E_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return CTM_E_ARG;
+  Request* r = it->second.get();
+  if (r->claimed) return CTM_E_ARG;  // another caller waits for it
+  r->claimed = true;
+  s->cv.wait(lk, [r] { return r->done; });
+  if (r->info.status == CTM_OK) {
+    if (rho1) std::memcpy(rho1, r->rho1.data(), sizeof(double) * r->rho1.size());
+    if (rho2_h) std::memcpy(rho2_h, r->rho2h.data(), sizeof(double) * r->rho2h.size());
+    if (rho2_v) std::memcpy(rho2_v, r->rho2v.data(), sizeof(double) * r->rho2v.size());
+  }
+  if (info) *info = r->info;
+  s->all.erase(it);
+  return CTM_OK;
+}
+
+int ctm_server_load(ctm_server* s, int* waiting, int* running) {
+  if (!s) return CTM_E_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (waiting) *waiting = (int)s->waiting.size();
+  if (running) *running = s->running;
+  return CTM_OK;
+}
+
+void ctm_server_destroy(ctm_server* s) {
+  if (!s) return;
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv.wait(lk, [s] { return s->waiting.empty() && s->running == 0; });
+  }
+  for (std::thread& t : s->threads)
+    if (t.joinable()) t.join();
+  if (s->pool_base) (void)hipFree(s->pool_base);
+  delete s;
+}
+
+}  // extern "C"

@@ -11,7 +11,7 @@ import pytest
 from paper_2410_11596_amd import binding
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("hctm.h", "hctm_testing.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("hctm.h", "hctm_testing.h", "hctm_serve.h")]
 DECL = re.compile(r"^\s*(?:const\s+)?(?:int|void|char|long long|size_t)\s*\**\s*(\w+)\s*\(", re.M)
 
 
@@ -132,3 +132,21 @@ def test_null_context(L):
     n = ctypes.c_int(0)
     assert L.ctm_num_records(None, ctypes.byref(n)) == binding.CTM_E_ARG
     assert isinstance(L.ctm_last_error(None), bytes)
+
+
+def test_server_argument_checks(L):
+    """The serving calls reject bad arguments before touching a device."""
+    s = ctypes.c_void_p()
+    assert L.ctm_server_create(None, 1 << 20, 2) == binding.CTM_E_ARG
+    assert L.ctm_server_create(ctypes.byref(s), 0, 2) == binding.CTM_E_ARG
+    assert L.ctm_server_create(ctypes.byref(s), 1 << 20, 0) == binding.CTM_E_ARG
+    assert L.ctm_server_create(ctypes.byref(s), 1 << 20, 65) == binding.CTM_E_ARG
+    assert s.value is None
+    A = np.ones(2 * 2 ** 4)
+    i = ctypes.c_longlong()
+    dp = A.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.ctm_server_submit(None, dp, 2, 2, 8, 0, 1e-10, 10, ctypes.byref(i)) == binding.CTM_E_ARG
+    info = binding.SolveInfo()
+    assert L.ctm_server_wait(None, 1, None, None, None, ctypes.byref(info)) == binding.CTM_E_ARG
+    assert L.ctm_server_load(None, None, None) == binding.CTM_E_ARG
+    L.ctm_server_destroy(None)

@@ -1,0 +1,77 @@
+"""Serving (include/hctm_serve.h): solves of mixed sizes and forms, submitted
+together into a pool that holds only a few of them at once, run
+concurrently, are admitted first come, first served, and give bit for bit
+the results of the same solve run alone."""
+import numpy as np
+import pytest
+
+from paper_2410_11596_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL, MAX_ITER = 1e-10, 60
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_11596_amd import binding
+
+    binding.lib()
+
+
+REQUESTS = [(2, 16, "z2", 0), (3, 16, "dense", 1), (2, 8, "dense", 2), (4, 32, "z2", 3),
+            (3, 24, "z2", 4), (2, 16, "z2", 5), (4, 16, "dense", 6), (3, 9, "z2", 7)]
+
+
+def _alone(A, chi, form):
+    from paper_2410_11596_amd import CTMRG
+
+    g = CTMRG(A, chi, form=form)
+    it = 0
+    while it < MAX_ITER:
+        g.step(1)
+        it += 1
+        if g.converged(TOL)[0]:
+            break
+    out = (it, g.rdm1(), g.rdm2("h"), g.rdm2("v"))
+    g.close()
+    return out
+
+
+def test_mixed_requests_match_solo_runs():
+    from paper_2410_11596_amd import Server, workspace_size
+
+    sizes = [workspace_size(2, D, chi, form=form) for (D, chi, form, _) in REQUESTS]
+    pool = sum(sorted(sizes)[-3:]) + (1 << 20)  # about three solves at a time
+    srv = Server(pool, max_active=4)
+    tensors = [inputs.iid_tensor(2, D, s) for (D, _, _, s) in REQUESTS]
+    ids = [srv.submit(A, chi, form=form, tol=TOL, max_iter=MAX_ITER)
+           for A, (D, chi, form, _) in zip(tensors, REQUESTS)]
+    res = [srv.wait(i) for i in ids]
+    srv.close()
+    for r in res:
+        assert r["status"] == 0, r["message"]
+        assert r["t_submit"] <= r["t_start"] <= r["t_end"]
+    # first come, first served
+    starts = [r["t_start"] for r in res]
+    assert starts == sorted(starts)
+    # some solves ran at the same time
+    assert any(res[i]["t_start"] < res[j]["t_end"] and res[j]["t_start"] < res[i]["t_end"]
+               for i in range(len(res)) for j in range(i + 1, len(res)))
+    for A, (D, chi, form, _), r in zip(tensors, REQUESTS, res):
+        it, r1, rh, rv = _alone(A, chi, form)
+        assert r["iterations"] == it
+        assert np.array_equal(r["rho1"], r1)
+        assert np.array_equal(r["rho2_h"], rh) and np.array_equal(r["rho2_v"], rv)
+
+
+def test_too_large_request_is_refused():
+    from paper_2410_11596_amd import HctmError, Server
+
+    srv = Server(1 << 20, max_active=2)
+    with pytest.raises(HctmError):
+        srv.submit(inputs.iid_tensor(2, 4, 0), 64)
+    srv.close()
