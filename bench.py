@@ -155,6 +155,44 @@ def mixed_precision(A, chi, steps, warmup, refine_max=40, tol=1e-10):
     return res
 
 
+def serving(n_req, rate, max_active=8, tol=1e-10, max_iter=40, seed=11):
+    """A stream of n_req solves with Poisson arrivals (rate per second), D
+    uniform in {2, 3, 4, 5} and chi in {16, 32, 64, 100} with chi >= D^2,
+    i.i.d. tensors, Z2 form, converged to tol (at most max_iter iterations):
+    latency = result ready - submitted, through the server with up to
+    max_active concurrent solves and one at a time (max_active = 1)."""
+    from paper_2410_11596_amd import Server, inputs, workspace_size
+
+    rng = np.random.default_rng(seed)
+    reqs = []
+    while len(reqs) < n_req:
+        D = int(rng.integers(2, 6))
+        chi = int(rng.choice([16, 32, 64, 100]))
+        if chi >= D * D:
+            reqs.append((D, chi, inputs.iid_tensor(2, D, 1000 + len(reqs))))
+    gaps = rng.exponential(1.0 / rate, n_req)
+    pool = max_active * max(workspace_size(2, D, chi) for D, chi, _ in reqs) + (1 << 24)
+    out = {"requests": n_req, "arrival_rate_per_s": rate,
+           "mix": "D uniform in {2,3,4,5}, chi in {16,32,64,100} with chi >= D^2, i.i.d. N(0,1) tensors, Z2, "
+                  f"tol {tol:g}, at most {max_iter} iterations"}
+    for label, act in (("concurrent", max_active), ("one_at_a_time", 1)):
+        srv = Server(pool, max_active=act)
+        t0 = time.perf_counter()
+        ids = []
+        for (D, chi, A), gap in zip(reqs, gaps):
+            time.sleep(gap)
+            ids.append(srv.submit(A, chi, tol=tol, max_iter=max_iter))
+        res = [srv.wait(i) for i in ids]
+        t1 = time.perf_counter()
+        srv.close()
+        lat = np.array([r["t_end"] - r["t_submit"] for r in res])
+        out[label] = {"max_active": act, "p50_latency_s": float(np.percentile(lat, 50)),
+                      "p99_latency_s": float(np.percentile(lat, 99)), "solves_per_s": n_req / (t1 - t0),
+                      "wall_s": t1 - t0, "failed": int(sum(r["status"] != 0 for r in res)),
+                      "iterations": int(sum(r["iterations"] for r in res))}
+    return out
+
+
 def cpu_baseline(D, chi, split, seed=0):
     """The oracle's Z2 left move on a random saturated environment (timed once)."""
     from oracle import basis, ctmrg
@@ -200,6 +238,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-block-product run")
+    ap.add_argument("--serve", type=int, default=24, metavar="N",
+                    help="solves in the serving run (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run (1/s)")
     ap.add_argument("--copy-check", type=int, default=0, metavar="BYTES",
                     help="before timing, copy BYTES three times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -275,6 +316,8 @@ def main():
                                            zip(["corners", "halves", "svd", "renormalise"], dphases.tolist())}
     if not args.no_mixed:
         out["mixed"] = mixed_precision(A, args.chi, args.steps, args.warmup)
+    if args.serve > 0:
+        out["serving"] = serving(args.serve, args.serve_rate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.D, args.chi, (84, 60))
     print(json.dumps(out), flush=True)
