@@ -103,7 +103,7 @@ def time_form(A, chi, form, steps, warmup, profile):
     return (t1 - t0), stats, phases, split
 
 
-def mixed_precision(A, chi, steps, warmup, refine_max=40, tol=1e-10):
+def mixed_precision(A, chi, steps, warmup, refine_max=40, tol=1e-10, precision="fp32"):
     """Block products of the moves in FP32 (CTM_PREC_FP32), timed like the
     FP64 form; then the error of its RDMs and energy against the FP64 form
     after the same iterations, and after FP64 refinement iterations against
@@ -117,7 +117,7 @@ def mixed_precision(A, chi, steps, warmup, refine_max=40, tol=1e-10):
     def obs(g):
         return np.concatenate([g.rdm1().ravel(), g.rdm2("h").ravel(), g.rdm2("v").ravel()]), g.energy(h)
 
-    g32 = CTMRG(A, chi, precision="fp32")
+    g32 = CTMRG(A, chi, precision=precision)
     g32.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -128,8 +128,9 @@ def mixed_precision(A, chi, steps, warmup, refine_max=40, tol=1e-10):
     o32, e32 = obs(g32)
     o64, e64 = obs(g64)
     res = {"value": steps / (t1 - t0), "unit": "CTMRG iterations/s", "ms_per_step": 1e3 * (t1 - t0) / steps,
-           "precision": "fp32 block products of the moves (FP32 MFMA, FP32 accumulation); FP64 SVD, "
-                        "normalisation and observables",
+           "precision": {"fp32": "FP32 block products of the moves (FP32 MFMA, FP32 accumulation)",
+                         "bf16x3": "BF16x3 block products of the moves (hi*hi + hi*lo + lo*hi on BF16 MFMA, "
+                                   "FP32 accumulation)"}[precision] + "; FP64 SVD, normalisation and observables",
            "max_abs_err_rdm_vs_fp64_same_iterations": float(np.abs(o32 - o64).max()),
            "abs_err_energy_vs_fp64_same_iterations": float(abs(e32 - e64))}
     n64 = warmup + steps
@@ -316,6 +317,7 @@ def main():
                                            zip(["corners", "halves", "svd", "renormalise"], dphases.tolist())}
     if not args.no_mixed:
         out["mixed"] = mixed_precision(A, args.chi, args.steps, args.warmup)
+        out["mixed_bf16x3"] = mixed_precision(A, args.chi, args.steps, args.warmup, precision="bf16x3")
     if args.serve > 0:
         out["serving"] = serving(args.serve, args.serve_rate)
     if not args.no_cpu_baseline:

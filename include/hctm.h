@@ -64,11 +64,14 @@ enum { CTM_FORM_Z2 = 0, CTM_FORM_DENSE = 1 };
 
 /* Arithmetic of the block products of the moves (enlarged corners, halves,
  * projectors, renormalisation).  CTM_PREC_FP32: operands rounded to FP32,
- * FP32 matrix-core products and accumulation, FP64 results; the truncated
- * SVD, the normalisations and the observables stay FP64.  A run in FP32 is
- * brought back to the FP64 fixed point by further iterations in FP64
+ * FP32 matrix-core products and accumulation, FP64 results.
+ * CTM_PREC_BF16X3: each operand split into BF16 parts x = hi + lo, the
+ * products hi*hi + hi*lo + lo*hi on the BF16 matrix cores with FP32
+ * accumulation (about 2^-16 relative per product).  In both the truncated
+ * SVD, the normalisations and the observables stay FP64, and a run is brought
+ * back to the FP64 fixed point by further iterations in FP64
  * (ctm_set_precision). */
-enum { CTM_PREC_FP64 = 0, CTM_PREC_FP32 = 1 };
+enum { CTM_PREC_FP64 = 0, CTM_PREC_FP32 = 1, CTM_PREC_BF16X3 = 2 };
 
 typedef struct {
   int form;                    /* CTM_FORM_Z2 (default) or CTM_FORM_DENSE */
@@ -83,7 +86,7 @@ typedef struct {
   int form_m;                  /* 0 (default): apply the decomposed matrix through the
                                   enlarged corners when few iterations are expected;
                                   1: always form it (H_d H_u) first */
-  int precision;               /* CTM_PREC_FP64 (default) or CTM_PREC_FP32 */
+  int precision;               /* CTM_PREC_FP64 (default), CTM_PREC_FP32 or CTM_PREC_BF16X3 */
   unsigned long long seed;     /* seed of the subspace-iteration start blocks */
   int profile;                 /* 1: time every GEMM launch with HIP events (ctm_gemm_stats) */
   void* stream;                /* hipStream_t or NULL */
@@ -118,7 +121,8 @@ int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, const ctm_op
 int ctm_step(ctm_ctx* c, int n_iter);
 
 /* Precision of the block products of the following ctm_step calls
- * (CTM_PREC_FP64 or CTM_PREC_FP32); the environment is kept. */
+ * (CTM_PREC_FP64, CTM_PREC_FP32 or CTM_PREC_BF16X3); the environment is
+ * kept. */
 int ctm_set_precision(ctm_ctx* c, int precision);
 
 /*

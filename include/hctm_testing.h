@@ -27,6 +27,11 @@ int hctm_dev_gemm_f32(const double* A, const double* B, double* C, int M, int N,
                       int ta, int tb, double alpha, double beta, const double* cscale, double* scratch,
                       long long scratch_doubles, void* stream);
 
+/* The same with BF16x3 split products (CTM_PREC_BF16X3). */
+int hctm_dev_gemm_bf16x3(const double* A, const double* B, double* C, int M, int N, int K, int lda, int ldb,
+                         int ldc, int ta, int tb, double alpha, double beta, const double* cscale, double* scratch,
+                         long long scratch_doubles, void* stream);
+
 /* Strided copy of a dense box of rank r <= 6: out[sum x_j ostr_j] =
  * in[sum x_j istr_j] (the permute-and-reshape step between block products). */
 int hctm_dev_copy(const double* in, double* out, int r, const int* dims, const long long* istr,

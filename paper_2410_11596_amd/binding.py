@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libhctm.so")
 
 CTM_OK, CTM_E_ARG, CTM_E_NOMEM, CTM_E_HIP, CTM_E_NUMERIC, CTM_E_STATE = range(6)
 CTM_FORM_Z2, CTM_FORM_DENSE = 0, 1
-CTM_PREC_FP64, CTM_PREC_FP32 = 0, 1
+CTM_PREC_FP64, CTM_PREC_FP32, CTM_PREC_BF16X3 = 0, 1, 2
 ERROR_NAMES = {1: "CTM_E_ARG", 2: "CTM_E_NOMEM", 3: "CTM_E_HIP", 4: "CTM_E_NUMERIC", 5: "CTM_E_STATE"}
 
 # every C symbol that include/hctm.h and include/hctm_testing.h declare
@@ -25,7 +25,7 @@ EXPORTS = [
     "ctm_env_epsilon", "ctm_s_err", "ctm_log_kappa", "ctm_num_records", "ctm_record",
     "ctm_sector_dims", "ctm_timing", "ctm_gemm_stats", "ctm_set_precision",
     "ctm_server_create", "ctm_server_submit", "ctm_server_wait", "ctm_server_load", "ctm_server_destroy",
-    "hctm_dev_gemm", "hctm_dev_gemm_f32", "hctm_dev_copy", "hctm_dev_chol_inv", "hctm_dev_jacobi", "hctm_dev_jacobi_log_doubles",
+    "hctm_dev_gemm", "hctm_dev_gemm_f32", "hctm_dev_gemm_bf16x3", "hctm_dev_copy", "hctm_dev_chol_inv", "hctm_dev_jacobi", "hctm_dev_jacobi_log_doubles",
 ]
 
 
@@ -103,6 +103,8 @@ def lib():
                                                                ctypes.c_longlong, vp], ctypes.c_int),
         "hctm_dev_gemm_f32": ([vp, vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.c_double, vp, vp,
                                                                    ctypes.c_longlong, vp], ctypes.c_int),
+        "hctm_dev_gemm_bf16x3": ([vp, vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.c_double, vp, vp,
+                                                                      ctypes.c_longlong, vp], ctypes.c_int),
         "ctm_set_precision": ([ctx, ctypes.c_int], ctypes.c_int),
         "ctm_server_create": ([P(ctypes.c_void_p), ctypes.c_size_t, ctypes.c_int], ctypes.c_int),
         "ctm_server_submit": ([ctypes.c_void_p, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -171,7 +173,7 @@ def _cell_array(A):
 
 
 def _precision_code(p):
-    codes = {"fp64": CTM_PREC_FP64, "fp32": CTM_PREC_FP32}
+    codes = {"fp64": CTM_PREC_FP64, "fp32": CTM_PREC_FP32, "bf16x3": CTM_PREC_BF16X3}
     if p not in codes:
         raise ValueError(f"precision must be one of {sorted(codes)}")
     return codes[p]
@@ -242,7 +244,7 @@ class CTMRG:
         self.close()
 
     def set_precision(self, precision):
-        """'fp64' or 'fp32' for the block products of the following steps."""
+        """'fp64', 'fp32' or 'bf16x3' for the block products of the following steps."""
         _check(lib().ctm_set_precision(self._ctx, _precision_code(precision)), self._ctx)
         return self
 
@@ -343,12 +345,14 @@ def _stream_ptr(torch):
 
 
 def dev_gemm(A, B, C, M, N, K, lda, ldb, ldc, ta=0, tb=0, alpha=1.0, beta=0.0, cscale=None, scratch=None,
-             f32=False):
+             f32=False, precision=None):
+    """precision: 'fp64' (default), 'fp32' or 'bf16x3' (f32=True is 'fp32')."""
     torch = _torch()
     cs = _ptr(cscale) if cscale is not None else None
     sp = _ptr(scratch) if scratch is not None else None
     sn = scratch.numel() if scratch is not None else 0
-    f = lib().hctm_dev_gemm_f32 if f32 else lib().hctm_dev_gemm
+    p = precision or ("fp32" if f32 else "fp64")
+    f = {"fp64": lib().hctm_dev_gemm, "fp32": lib().hctm_dev_gemm_f32, "bf16x3": lib().hctm_dev_gemm_bf16x3}[p]
     _check(f(_ptr(A), _ptr(B), _ptr(C), M, N, K, lda, ldb, ldc, ta, tb, alpha, beta, cs, sp, sn, _stream_ptr(torch)))
 
 

@@ -61,8 +61,8 @@ hctm::Options to_options(const ctm_opts* o, int D) {
   opt.svd_iters = o->svd_iters;
   if (o->form_m != 0 && o->form_m != 1) throw hctm::Error(CTM_E_ARG, "form_m must be 0 or 1");
   opt.form_m = o->form_m;
-  if (o->precision != CTM_PREC_FP64 && o->precision != CTM_PREC_FP32)
-    throw hctm::Error(CTM_E_ARG, "precision must be CTM_PREC_FP64 or CTM_PREC_FP32");
+  if (o->precision != CTM_PREC_FP64 && o->precision != CTM_PREC_FP32 && o->precision != CTM_PREC_BF16X3)
+    throw hctm::Error(CTM_E_ARG, "precision must be CTM_PREC_FP64, CTM_PREC_FP32 or CTM_PREC_BF16X3");
   opt.precision = o->precision;
   opt.seed = o->seed;
   opt.profile = o->profile ? 1 : 0;
@@ -153,8 +153,8 @@ int ctm_step(ctm_ctx* c, int n_iter) {
 int ctm_set_precision(ctm_ctx* c, int precision) {
   if (!c) return CTM_E_ARG;
   return guarded(c, [&] {
-    if (precision != CTM_PREC_FP64 && precision != CTM_PREC_FP32)
-      throw hctm::Error(CTM_E_ARG, "precision must be CTM_PREC_FP64 or CTM_PREC_FP32");
+    if (precision != CTM_PREC_FP64 && precision != CTM_PREC_FP32 && precision != CTM_PREC_BF16X3)
+      throw hctm::Error(CTM_E_ARG, "precision must be CTM_PREC_FP64, CTM_PREC_FP32 or CTM_PREC_BF16X3");
     c->ctm->set_precision(precision);
   });
 }
@@ -294,7 +294,7 @@ int ctm_gemm_stats(ctm_ctx* c, double* flops, double* seconds, long long* launch
 // ---------------------------------------------------------- test hooks ----
 static int dev_gemm(const double* A, const double* B, double* C, int M, int N, int K, int lda, int ldb, int ldc, int ta,
                     int tb, double alpha, double beta, const double* cscale, double* scratch, long long scratch_doubles,
-                    void* stream, int f32) {
+                    void* stream, int prec) {
   return guarded(nullptr, [&] {
     if (M < 0 || N < 0 || K < 0) throw hctm::Error(CTM_E_ARG, "negative size");
     hctm::GemmDesc d{};
@@ -313,7 +313,7 @@ static int dev_gemm(const double* A, const double* B, double* C, int M, int N, i
     d.beta = beta;
     d.cscale = cscale;
     d.rscale = nullptr;
-    d.f32 = f32;
+    d.prec = prec;
     hctm::gemm({d}, reinterpret_cast<hipStream_t>(stream), scratch, scratch_doubles);
   });
 }
@@ -328,6 +328,12 @@ int hctm_dev_gemm_f32(const double* A, const double* B, double* C, int M, int N,
                       int ta, int tb, double alpha, double beta, const double* cscale, double* scratch,
                       long long scratch_doubles, void* stream) {
   return dev_gemm(A, B, C, M, N, K, lda, ldb, ldc, ta, tb, alpha, beta, cscale, scratch, scratch_doubles, stream, 1);
+}
+
+int hctm_dev_gemm_bf16x3(const double* A, const double* B, double* C, int M, int N, int K, int lda, int ldb,
+                         int ldc, int ta, int tb, double alpha, double beta, const double* cscale, double* scratch,
+                         long long scratch_doubles, void* stream) {
+  return dev_gemm(A, B, C, M, N, K, lda, ldb, ldc, ta, tb, alpha, beta, cscale, scratch, scratch_doubles, stream, 2);
 }
 
 int hctm_dev_copy(const double* in, double* out, int r, const int* dims, const long long* istr, const long long* ostr,

@@ -44,9 +44,10 @@ constexpr int kDirectMax = 160;  // sectors up to this size are decomposed direc
 constexpr int kJacobiSweeps = 40;
 // relative residual of the leading columns that ends the subspace iteration
 constexpr double kSubspaceTol = 1e-12;
-// with the block products in FP32 the decomposed matrix itself carries
-// relative errors of order 1e-7: resolving its subspace further buys nothing
-constexpr double kSubspaceTolF32 = 1e-8;
+// with the block products in FP32 (BF16x3) the decomposed matrix itself
+// carries relative errors of order 1e-7 (1e-5): resolving its subspace
+// further buys nothing
+constexpr double kSubspaceTolPrec[3] = {kSubspaceTol, 1e-8, 1e-6};
 // apply M through the corners when the cut's last truncation took at most
 // this many subspace iterations (forming M costs about as much as 8 of them)
 constexpr int kImplicitIters = 7;
@@ -261,8 +262,8 @@ void Ctm::launch_copies(std::vector<CopyJob>& jobs) {
 }
 
 void Ctm::launch_gemms(std::vector<GemmDesc>& g) {
-  if (f32_)
-    for (GemmDesc& d : g) d.f32 = 1;
+  if (low_prec_)
+    for (GemmDesc& d : g) d.prec = opt_.precision;
   if (!opt_.profile) {
     gemm(g, st_, gemm_scratch_, gemm_scratch_cap_);
     g.clear();
@@ -727,7 +728,7 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
           sync();
           for (size_t c = 0; c < chk.size(); ++c) {
             const double e = host_d_[4096 + 2 * c], ymax = host_d_[4096 + 2 * c + 1];
-            if (e <= (opt_.precision == 1 ? kSubspaceTolF32 : kSubspaceTol) * ymax) chk[c]->fin = true;
+            if (e <= kSubspaceTolPrec[opt_.precision] * ymax) chk[c]->fin = true;
           }
         }
         for (SvdSector* S : act) {
@@ -902,10 +903,10 @@ void Ctm::mark(int phase) {
   }
   HCTM_HIP(hipEventRecord(ev_[i], st_));
   ev_phase_.push_back(phase);
-  // with precision 1 the block products of the corners, halves, projectors
-  // and renormalisation run in FP32; the truncated SVD (phase 2), the
-  // normalisations and everything outside the moves stay FP64
-  f32_ = opt_.precision == 1 && (phase == 0 || phase == 1 || phase == 3);
+  // with precision 1 (2) the block products of the corners, halves,
+  // projectors and renormalisation run in FP32 (BF16x3); the truncated SVD
+  // (phase 2), the normalisations and everything outside the moves stay FP64
+  low_prec_ = opt_.precision != 0 && (phase == 0 || phase == 1 || phase == 3);
 }
 
 void Ctm::move(int r) {

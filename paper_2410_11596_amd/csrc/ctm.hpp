@@ -44,7 +44,7 @@ struct Options {
   double tau = 1e-12;
   int svd_iters = 12;
   int form_m = 0;  // 1: always form the decomposed matrix
-  int precision = 0;  // 0: FP64 throughout; 1: block products of the moves in FP32
+  int precision = 0;  // 0: FP64 throughout; block products of the moves in 1: FP32, 2: BF16x3
   unsigned long long seed = 0x5eed;
   int profile = 0;  // 1: time every GEMM launch with HIP events
 };
@@ -172,7 +172,7 @@ class Ctm {
   SvdSector sec_[2];
   std::vector<std::array<int, 2>> kg_;  // kept-state guess per (frame, column, row)
   std::vector<int> iters_prev_;           // subspace iterations of the last truncation per cut
-  bool f32_ = false;  // block products launched now compute in FP32 (set per move phase)
+  bool low_prec_ = false;  // block products launched now use opt_.precision (set per move phase)
   bool implicit_ = false;                 // M applied through the corners impl_q_
   const BT* impl_q_[4] = {nullptr, nullptr, nullptr, nullptr};
   struct WarmV {

@@ -144,9 +144,31 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
 };
 
+// BF16x3: x = hi + lo with hi = bf16(x) and lo = bf16(x - hi) (round to
+// nearest even); the MFMA v_mfma_f32_16x16x16bf16 takes four consecutive k
+// per lane: lane l supplies A[l % 16][4 (l / 16) + q] and B[4 (l / 16) + q][l % 16],
+// q = 0..3, and holds D[4 (l / 16) + v][l % 16] as the FP32 MFMA does.
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_rn(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_float(short h) {
+  return __uint_as_float(((unsigned)(unsigned short)h) << 16);
+}
+
+__device__ __forceinline__ void split_bf16(float x, short& hi, short& lo) {
+  hi = bf16_rn(x);
+  lo = bf16_rn(x - bf16_to_float(hi));
+}
+
 // One output tile of the grouped GEMM; CT = type of the staged operands and
-// of the MFMA (the output is FP64 either way).
-template <int BM, int BN, typename CT>
+// of the MFMA (the output is FP64 either way); SPLIT (with CT = float): the
+// BF16x3 products.
+template <int BM, int BN, typename CT, bool SPLIT = false>
 __device__ __forceinline__ void gemm_tile(const Group& g, CT* As, CT* Bs) {
   constexpr int PA = BM + 4, PB = BN + 4;
   constexpr int WM = BM / 2, WN = BN / 2;  // per-wave sub-tile
@@ -200,17 +222,50 @@ __device__ __forceinline__ void gemm_tile(const Group& g, CT* As, CT* Bs) {
       load_tile<BM>(P.A, P.lda, P.ta, P.M, kend, m0, k0 + BK, ra);
       load_tile<BN>(P.B, P.ldb, !P.tb, P.N, kend, n0, k0 + BK, rb);
     }
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      CT af[TI], bf[TJ];
-#pragma unroll
-      for (int i = 0; i < TI; ++i) af[i] = As[(kk + lk) * PA + wm + i * 16 + li];
-#pragma unroll
-      for (int j = 0; j < TJ; ++j) bf[j] = Bs[(kk + lk) * PB + wn + j * 16 + li];
+    if constexpr (SPLIT) {
+      // one BF16 MFMA covers the 16 k of the slab: lane takes k = 4 lk + q
+      static_assert(BK == 16, "one BF16 MFMA per K step");
+      v4s ah[TI], al[TI], bh[TJ], bl[TJ];
 #pragma unroll
       for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < TJ; ++j) acc[i][j] = Mfma<CT>::op(af[i], bf[j], acc[i][j]);
+        for (int q = 0; q < 4; ++q) {
+          short h, l;
+          split_bf16(As[(4 * lk + q) * PA + wm + i * 16 + li], h, l);
+          ah[i][q] = h;
+          al[i][q] = l;
+        }
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          short h, l;
+          split_bf16(Bs[(4 * lk + q) * PB + wn + j * 16 + li], h, l);
+          bh[j][q] = h;
+          bl[j][q] = l;
+        }
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+          // the small terms first
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        CT af[TI], bf[TJ];
+#pragma unroll
+        for (int i = 0; i < TI; ++i) af[i] = As[(kk + lk) * PA + wm + i * 16 + li];
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) bf[j] = Bs[(kk + lk) * PB + wn + j * 16 + li];
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) acc[i][j] = Mfma<CT>::op(af[i], bf[j], acc[i][j]);
+      }
     }
     __syncthreads();
     if (more) {
@@ -272,6 +327,13 @@ __global__ __launch_bounds__(NT, 2) void gemm_f32_kernel(Group g) {
   gemm_tile<BM, BN, float>(g, As, Bs);
 }
 
+template <int BM, int BN>
+__global__ __launch_bounds__(NT, 2) void gemm_bf16x3_kernel(Group g) {
+  __shared__ float As[BK * (BM + 4)];
+  __shared__ float Bs[BK * (BN + 4)];
+  gemm_tile<BM, BN, float, true>(g, As, Bs);
+}
+
 // Sum the K slices of split problems in slice order and apply the epilogue.
 __global__ void splitk_reduce_kernel(Group g) {
   const Prob& P = g.p[blockIdx.y];
@@ -306,7 +368,7 @@ long long tiles(const GemmDesc& d, int bm, int bn) {
 }  // namespace
 
 namespace {
-void gemm_one_type(const std::vector<GemmDesc>& probs, bool f32, hipStream_t s, double* scratch,
+void gemm_one_type(const std::vector<GemmDesc>& probs, int prec, hipStream_t s, double* scratch,
                    long long scratch_cap) {
   // tile shape for the whole call, from how many workgroups it yields
   constexpr long long kFill = 240;  // about one workgroup per CU
@@ -327,14 +389,18 @@ void gemm_one_type(const std::vector<GemmDesc>& probs, bool f32, hipStream_t s, 
   long long split_mn = 0;
   auto flush = [&]() {
     if (g.n == 0) return;
-    if (cfg == 0 && !f32)
+    if (prec == 0 && cfg == 0)
       hipLaunchKernelGGL((gemm_f64_kernel<128, 128>), dim3(g.total), dim3(NT), 0, s, g);
-    else if (!f32)
+    else if (prec == 0)
       hipLaunchKernelGGL((gemm_f64_kernel<64, 64>), dim3(g.total), dim3(NT), 0, s, g);
-    else if (cfg == 0)
+    else if (prec == 1 && cfg == 0)
       hipLaunchKernelGGL((gemm_f32_kernel<128, 128>), dim3(g.total), dim3(NT), 0, s, g);
-    else
+    else if (prec == 1)
       hipLaunchKernelGGL((gemm_f32_kernel<64, 64>), dim3(g.total), dim3(NT), 0, s, g);
+    else if (cfg == 0)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128>), dim3(g.total), dim3(NT), 0, s, g);
+    else
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 64>), dim3(g.total), dim3(NT), 0, s, g);
     HCTM_HIP(hipGetLastError());
     if (any_split) {
       // one thread per output element of the largest split problem
@@ -404,12 +470,12 @@ void gemm_one_type(const std::vector<GemmDesc>& probs, bool f32, hipStream_t s, 
 }  // namespace
 
 void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch, long long scratch_cap) {
-  // FP64 and FP32-compute problems go to separate launches (all problems of
-  // one call are independent)
-  std::vector<GemmDesc> p64, p32;
-  for (const GemmDesc& d : probs) (d.f32 ? p32 : p64).push_back(d);
-  if (!p64.empty()) gemm_one_type(p64, false, s, scratch, scratch_cap);
-  if (!p32.empty()) gemm_one_type(p32, true, s, scratch, scratch_cap);
+  // problems of different arithmetic go to separate launches (all problems
+  // of one call are independent)
+  std::vector<GemmDesc> by[3];
+  for (const GemmDesc& d : probs) by[(d.prec >= 0 && d.prec <= 2) ? d.prec : 0].push_back(d);
+  for (int p = 0; p < 3; ++p)
+    if (!by[p].empty()) gemm_one_type(by[p], p, s, scratch, scratch_cap);
 }
 
 }  // namespace hctm

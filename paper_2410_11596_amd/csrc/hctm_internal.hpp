@@ -36,7 +36,9 @@ struct GemmDesc {
   double alpha, beta;
   const double* cscale;
   const double* rscale;  // optional per-row scale of the product
-  int f32;               // 1: operands rounded to FP32, FP32 MFMA and accumulation
+  int prec;              // 0: FP64; 1: operands rounded to FP32, FP32 MFMA and accumulation;
+                         // 2: BF16x3 (operands split into BF16 hi + lo, hi*hi + hi*lo + lo*hi
+                         //    on BF16 MFMA with FP32 accumulation)
 };
 // scratch (optional): device doubles for split-K partial tiles.
 void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch = nullptr, long long scratch_cap = 0);

@@ -100,7 +100,8 @@ def test_option_checks(L):
     assert _ws(L, 2, 2, 8, svd_iters=0)[0] == binding.CTM_E_ARG
     assert _ws(L, 2, 2, 8, Lx=0)[0] == binding.CTM_E_ARG
     assert _ws(L, 2, 2, 8, Ly=5)[0] == binding.CTM_E_ARG
-    assert _ws(L, 2, 2, 8, precision=2)[0] == binding.CTM_E_ARG
+    assert _ws(L, 2, 2, 8, precision=3)[0] == binding.CTM_E_ARG
+    assert _ws(L, 2, 2, 8, precision=binding.CTM_PREC_BF16X3)[0] == 0
     assert _ws(L, 2, 2, 8, precision=binding.CTM_PREC_FP32)[0] == 0
     # the Z2 form needs a swap-symmetric boundary vector; the plain form does not
     b = np.array([1.0, 0.5, 0.0, 1.0])

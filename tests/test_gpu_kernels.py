@@ -65,6 +65,43 @@ def test_gemm_f32_matches_rounded_operands(hc, M, N, K, ta, tb):
         assert np.abs(out - ref64).max() > 1e-12
 
 
+def _bf16(x):
+    """Round FP32 values to BF16 (nearest, ties to even) in FP64."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 33, 5), (130, 129, 257), (300, 260, 1000)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 1)])
+def test_gemm_bf16x3_matches_split_operands(hc, M, N, K, ta, tb):
+    """BF16x3 products (CTM_PREC_BF16X3): each FP32-rounded operand x = hi +
+    lo in BF16, hi*hi + hi*lo + lo*hi accumulated in FP32; equal to that sum
+    computed in FP64 up to FP32 accumulation, and within 2^-15 relative of
+    the FP64 product."""
+    rng = np.random.default_rng(M * 1000 + N * 10 + K + 7 * ta + 3 * tb)
+    A = rng.standard_normal((K, M) if ta else (M, K))
+    B = rng.standard_normal((N, K) if tb else (K, N))
+    C0 = rng.standard_normal((M, N))
+    def parts(X):
+        x = X.astype(np.float32).astype(np.float64)
+        hi = _bf16(x)
+        return hi, _bf16(x - hi)
+    ah, al = parts(A)
+    bh, bl = parts(B)
+    op = lambda X, t: X.T if t else X
+    ref3 = op(ah, ta) @ op(bh, tb) + op(ah, ta) @ op(bl, tb) + op(al, ta) @ op(bh, tb)
+    absAB = np.abs(op(A, ta)) @ np.abs(op(B, tb))
+    dA, dB, dC = _dev(A), _dev(B), _dev(C0)
+    scratch = torch.zeros(16 * M * N, dtype=torch.float64, device="cuda")
+    hc.dev_gemm(dA, dB, dC, M, N, K, A.shape[1], B.shape[1], N, ta, tb, 1.0, 0.0, None, scratch, precision="bf16x3")
+    torch.cuda.synchronize()
+    out = dC.cpu().numpy()
+    assert np.all(np.abs(out - ref3) <= (K + 2) * 2.0 ** -24 * 3 * absAB + 1e-300)
+    ref64 = op(A, ta) @ op(B, tb)
+    assert np.all(np.abs(out - ref64) <= 2.0 ** -15 * absAB + 1e-300)
+
+
 @pytest.mark.parametrize("M,N,K,ta", [(126, 126, 2600, 1), (60, 84, 5000, 0), (7, 300, 3000, 1)])
 def test_gemm_split_k(hc, M, N, K, ta):
     """Small outputs with a long reduction are split over K (Gram matrices)."""
