@@ -156,6 +156,48 @@ def mixed_precision(A, chi, steps, warmup, refine_max=40, tol=1e-10, precision="
     return res
 
 
+def c4v_scheme(D, chi, steps, warmup, tol=1e-10, max_iter=200):
+    """The C4v scheme (one corner, one edge, one truncation per iteration)
+    against the directional moves, both Z2 FP64, on a C4v-symmetric tensor of
+    the same size: time per iteration, then iterations and wall time to
+    delta < tol from the start and the largest RDM difference there."""
+    import torch
+
+    from paper_2410_11596_amd import CTMRG, inputs
+
+    A = inputs.c4v_iid_tensor(2, D, 0)
+    res = {"workload": f"C4v-symmetrised real iPEPS d=2 D={D}, chi={chi}, Z2 FP64"}
+    conv = {}
+    for name, c4 in (("c4v", True), ("directional", False)):
+        g = CTMRG(A, chi, c4v=c4)
+        g.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res[name + "_ms_per_iteration"] = 1e3 * (t1 - t0) / steps
+        g.close()
+        g = CTMRG(A, chi, c4v=c4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = 0
+        while n < max_iter:
+            g.step(1)
+            n += 1
+            if g.converged(tol)[0]:
+                break
+        t1 = time.perf_counter()
+        res[name + "_iterations_to_delta_1e-10"] = n
+        res[name + "_seconds_to_delta_1e-10"] = t1 - t0
+        conv[name] = np.concatenate([g.rdm1().ravel(), g.rdm2("h").ravel(), g.rdm2("v").ravel()])
+        g.close()
+    res["speedup_per_iteration"] = res["directional_ms_per_iteration"] / res["c4v_ms_per_iteration"]
+    res["speedup_to_solution"] = res["directional_seconds_to_delta_1e-10"] / res["c4v_seconds_to_delta_1e-10"]
+    res["max_abs_rdm_diff_at_solution"] = float(np.abs(conv["c4v"] - conv["directional"]).max())
+    return res
+
+
 def serving(n_req, rate, max_active=8, tol=1e-10, max_iter=40, seed=11):
     """A stream of n_req solves with Poisson arrivals (rate per second), D
     uniform in {2, 3, 4, 5} and chi in {16, 32, 64, 100} with chi >= D^2,
@@ -239,6 +281,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-block-product run")
+    ap.add_argument("--no-c4v", action="store_true", help="skip the C4v-scheme comparison")
     ap.add_argument("--serve", type=int, default=24, metavar="N",
                     help="solves in the serving run (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run (1/s)")
@@ -318,6 +361,8 @@ def main():
     if not args.no_mixed:
         out["mixed"] = mixed_precision(A, args.chi, args.steps, args.warmup)
         out["mixed_bf16x3"] = mixed_precision(A, args.chi, args.steps, args.warmup, precision="bf16x3")
+    if not args.no_c4v:
+        out["c4v"] = c4v_scheme(args.D, args.chi, args.steps, args.warmup)
     if args.serve > 0:
         out["serving"] = serving(args.serve, args.serve_rate)
     if not args.no_cpu_baseline:

@@ -82,11 +82,21 @@ typedef struct {
                                   form b must be swap symmetric, b[k*D+l] = b[l*D+k]. */
   double svd_rel_cutoff;       /* keep singular values > cutoff * largest (default 1e-12) */
   int svd_iters;               /* at most this many subspace iterations per truncated
-                                  SVD (default 12); fewer once the basis has converged */
+                                  SVD (default 12; twice that in the C4v scheme); fewer
+                                  once the basis has converged */
   int form_m;                  /* 0 (default): apply the decomposed matrix through the
                                   enlarged corners when few iterations are expected;
                                   1: always form it (H_d H_u) first */
   int precision;               /* CTM_PREC_FP64 (default), CTM_PREC_FP32 or CTM_PREC_BF16X3 */
+  int c4v;                     /* 1: the C4v-symmetric scheme (Sec. II A) for a tensor
+                                  invariant under the rotations and reflections of the
+                                  square (checked to 1e-12 relative; 1 x 1 cell only):
+                                  one corner C and one edge T stand for all four, and an
+                                  iteration is one absorption C' = V^T Q V,
+                                  T' = V^T (T a) V with V the dominant eigenvectors
+                                  (largest |eigenvalue|) of the symmetric enlarged
+                                  corner Q = C T T a, per sector in the Z2 form.
+                                  0 (default): the directional moves */
   unsigned long long seed;     /* seed of the subspace-iteration start blocks */
   int profile;                 /* 1: time every GEMM launch with HIP events (ctm_gemm_stats) */
   void* stream;                /* hipStream_t or NULL */

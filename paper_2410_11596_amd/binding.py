@@ -39,6 +39,7 @@ class CtmOpts(ctypes.Structure):
         ("svd_iters", ctypes.c_int),
         ("form_m", ctypes.c_int),
         ("precision", ctypes.c_int),
+        ("c4v", ctypes.c_int),
         ("seed", ctypes.c_ulonglong),
         ("profile", ctypes.c_int),
         ("stream", ctypes.c_void_p),
@@ -186,11 +187,12 @@ class CTMRG:
     cell, or the tensors of an Lx x Ly cell as an array (Ly, Lx, d, D, D, D,
     D) or a dict {(x, y): tensor}.  Device memory is a torch uint8 tensor
     handed to the library as its workspace; work runs on torch's current HIP
-    stream.
+    stream.  c4v=True selects the C4v-symmetric scheme (one corner, one edge)
+    for a tensor invariant under the symmetries of the square.
     """
 
     def __init__(self, A, chi, form="z2", boundary=None, svd_rel_cutoff=1e-12, svd_iters=12, seed=0x5EED,
-                 stream=None, torch_workspace=True, profile=False, form_m=False, precision="fp64"):
+                 stream=None, torch_workspace=True, profile=False, form_m=False, precision="fp64", c4v=False):
         torch = _torch()
         A = _cell_array(A)
         self.Ly, self.Lx = A.shape[0], A.shape[1]
@@ -204,6 +206,7 @@ class CTMRG:
         o.svd_iters = svd_iters
         o.form_m = 1 if form_m else 0
         o.precision = _precision_code(precision)
+        o.c4v = 1 if c4v else 0
         o.seed = seed
         o.profile = 1 if profile else 0
         self._b = None

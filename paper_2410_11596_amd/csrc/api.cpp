@@ -64,6 +64,9 @@ hctm::Options to_options(const ctm_opts* o, int D) {
   if (o->precision != CTM_PREC_FP64 && o->precision != CTM_PREC_FP32 && o->precision != CTM_PREC_BF16X3)
     throw hctm::Error(CTM_E_ARG, "precision must be CTM_PREC_FP64, CTM_PREC_FP32 or CTM_PREC_BF16X3");
   opt.precision = o->precision;
+  if (o->c4v != 0 && o->c4v != 1) throw hctm::Error(CTM_E_ARG, "c4v must be 0 or 1");
+  if (o->c4v && (o->Lx != 1 || o->Ly != 1)) throw hctm::Error(CTM_E_ARG, "c4v needs a 1 x 1 cell");
+  opt.c4v = o->c4v;
   opt.seed = o->seed;
   opt.profile = o->profile ? 1 : 0;
   if (o->boundary) {
@@ -83,6 +86,27 @@ hctm::Options to_options(const ctm_opts* o, int D) {
     }
   }
   return opt;
+}
+
+// A[s,u,l,d,r] unchanged (to tol relative to its largest entry) by the
+// rotation (u,l,d,r) -> (l,d,r,u) and the reflection l <-> r, which generate
+// the symmetry group of the square
+bool is_c4v(const double* A, int d, int D, double tol) {
+  const long long D2 = (long long)D * D, D3 = D2 * D, D4 = D3 * D;
+  double mx = 0.0;
+  for (long long i = 0; i < d * D4; ++i) mx = std::max(mx, std::fabs(A[i]));
+  const double lim = tol * mx;
+  for (int s = 0; s < d; ++s)
+    for (int u = 0; u < D; ++u)
+      for (int l = 0; l < D; ++l)
+        for (int dn = 0; dn < D; ++dn)
+          for (int r = 0; r < D; ++r) {
+            const double* a = A + s * D4;
+            const double x = a[u * D3 + l * D2 + dn * D + r];
+            if (std::fabs(x - a[l * D3 + dn * D2 + r * D + u]) > lim) return false;
+            if (std::fabs(x - a[u * D3 + r * D2 + dn * D + l]) > lim) return false;
+          }
+  return true;
 }
 
 void check_sizes(int d, int D, int chi) {
@@ -127,6 +151,8 @@ int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, const ctm_op
     const long long n = (long long)d * D * D * D * D * opt.Lx * opt.Ly;
     for (long long i = 0; i < n; ++i)
       if (!std::isfinite(A[i])) throw hctm::Error(CTM_E_NUMERIC, "A has a non-finite entry");
+    if (opt.c4v && !is_c4v(A, d, D, 1e-12))
+      throw hctm::Error(CTM_E_ARG, "c4v: A is not invariant under the rotations and reflections of the square");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) throw hctm::Error(CTM_E_HIP, "no HIP device");
     std::unique_ptr<ctm_ctx> c(new ctm_ctx);

@@ -675,7 +675,10 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
       // basis is formed, the residual of the leading columns of Y = M Q_r
       // outside the previous left basis (relative to the largest column)
       // decides whether this iterate is the final one.
-      const int T = std::max(1, opt_.svd_iters);
+      // the C4v scheme decomposes the enlarged corner itself, whose relative
+      // spectral gaps are about the square roots of those of H_d H_u: twice
+      // the iterations for the same damping of the discarded part
+      const int T = std::max(1, opt_.svd_iters) * (opt_.c4v ? 2 : 1);
       std::vector<SvdSector*> act = sub;
       for (int t = 0; t < T && !act.empty(); ++t) {
         apply_M(act, false);  // Y = M Qr
@@ -1144,6 +1147,145 @@ void Ctm::move(int r) {
   eps_site_ = -1;
 }
 
+// ------------------------------------------------------------ C4v move ----
+// One iteration of the C4v-symmetric scheme (Sec. II A) on a 1 x 1 cell: the
+// environment is one corner C and one edge T, the same tensor in every corner
+// (edge) slot in that slot's own leg order.  The enlarged corner
+// Q = C T T a ([w d | t r], rows and columns over the same fused legs) is
+// symmetric, so its right singular vectors V (columns of largest singular
+// value = |eigenvalue|) span its dominant eigenvectors and serve as the
+// projector from both sides: C' = V^T Q V, T' = V^T (T a) V.
+void Ctm::move_c4v() {
+  const int s = 0, key = 0;
+  mark(0);
+  quadrant(s, 0);
+  BT& Q = quad(s, 0);
+  mark(2);
+  truncated_svd(&Q, chi_, key, (uint64_t)records_.size());
+  iters_prev_[key] = std::max(sec_[0].iters, sec_[1].iters);
+  mark(3);
+  const Leg kn{sec_[0].k, sec_[1].k};
+  BT& Pa = Pa_[0];
+  BT& Pb = Pb_[0];
+  Pa.L = Layout({Q.L.leg[0], lq_, kn}, 2);  // V as [w d | k]
+  Pb.L = Layout({kn, Q.L.leg[0], lq_}, 1);  // V^T as [k | w d]
+  if (Pa.L.size > proj_cap_ || Pb.L.size > proj_cap_) throw Error(2, "projector capacity");
+  BT& C = env(s, 0);
+  C.L = Layout({kn, kn}, 1);
+  std::vector<CopyJob> jobs;
+  std::vector<GemmDesc> g;
+  for (int P = 0; P < 2; ++P) {
+    SvdSector& S = sec_[P];
+    if (S.k == 0) continue;
+    if (Q.L.rows[P] != Q.L.cols[P] || Pa.L.rows[P] != S.n) throw Error(1, "C4v move: enlarged corner is not square");
+    CopyJob a{};  // Pa = V
+    a.in = S.V;
+    a.out = Pa.p + Pa.L.off[P];
+    a.r = 1;
+    a.dims[0] = S.n * S.k;
+    a.istr[0] = 1;
+    a.ostr[0] = 1;
+    jobs.push_back(a);
+    CopyJob b{};  // Pb = V^T
+    b.in = S.V;
+    b.out = Pb.p + Pb.L.off[P];
+    b.r = 2;
+    b.dims[0] = S.k;
+    b.dims[1] = S.n;
+    b.istr[0] = 1;
+    b.istr[1] = S.k;
+    b.ostr[0] = S.n;
+    b.ostr[1] = 1;
+    jobs.push_back(b);
+    GemmDesc d{};  // Q V
+    d.A = Q.p + Q.L.off[P];
+    d.B = S.V;
+    d.C = S.C1;
+    d.M = S.n;
+    d.N = S.k;
+    d.K = S.n;
+    d.lda = (int)Q.L.ld(P);
+    d.ldb = S.k;
+    d.ldc = S.k;
+    d.alpha = 1.0;
+    g.push_back(d);
+  }
+  launch_copies(jobs);
+  launch_gemms(g);
+  for (int P = 0; P < 2; ++P) {
+    SvdSector& S = sec_[P];
+    if (S.k == 0) continue;
+    GemmDesc e{};  // C' = V^T (Q V)
+    e.A = S.V;
+    e.B = S.C1;
+    e.C = C.p + C.L.off[P];
+    e.M = S.k;
+    e.N = S.k;
+    e.K = S.n;
+    e.lda = S.k;
+    e.ldb = S.k;
+    e.ldc = S.k;
+    e.ta = 1;
+    e.alpha = 1.0;
+    g.push_back(e);
+  }
+  launch_gemms(g);
+
+  // T' = V^T (T a) V, the edge renormalisation of a move with both
+  // projectors taken from the one cut
+  BT& T4 = env(s, 7);
+  BT T4s{Layout(), mid3_, mid_cap_};
+  permute(T4, T4s, {0, 1, 2}, 2);        // [w l | c]
+  BT Pas{Layout(), big2_, big_cap_};
+  permute(Pa, Pas, {0, 1, 2}, 1);        // [c | u k]
+  BT G{Layout(), big1_, big_cap_};
+  contract(T4s, Pas, G);                 // [w l | u k]
+  BT Gp{Layout(), big2_, big_cap_};
+  permute(G, Gp, {0, 3, 2, 1}, 2);       // [w k | u l]
+  BT H{Layout(), big1_, big_cap_};
+  contract(Gp, a_rot(s, 0), H);          // [w k | e r]
+  BT Hp{Layout(), big2_, big_cap_};
+  permute(H, Hp, {0, 2, 3, 1}, 2);       // [w e | r k]
+  contract(Pb, Hp, T4);                  // [k | r k]
+  normalise(C);
+  normalise(T4);
+  // the same corner and edge in every slot
+  for (int i = 1; i < 4; ++i) {
+    BT& Ci = env(s, 2 * i);
+    BT& Ti = env(s, 2 * i + 7);
+    Ci.L = C.L;
+    Ti.L = T4.L;
+    for (int w = 0; w < 2; ++w) {
+      CopyJob j{};
+      j.in = w == 0 ? C.p : T4.p;
+      j.out = w == 0 ? Ci.p : Ti.p;
+      j.r = 1;
+      j.dims[0] = (int)(w == 0 ? C.L.size : T4.L.size);
+      j.istr[0] = 1;
+      j.ostr[0] = 1;
+      jobs.push_back(j);
+    }
+  }
+  launch_copies(jobs);
+  for (int o = 0; o < 4; ++o) quad_ok_[s * 4 + o] = 0;
+  mark(-1);
+
+  MoveRecord rec;
+  rec.k_even = opt_.form == 0 ? kn.e : kn.e + kn.o;
+  rec.k_odd = opt_.form == 0 ? kn.o : 0;
+  for (int P = 0; P < 2; ++P) {
+    rec.iters[P] = sec_[P].iters;
+    rec.sweeps[P] = sec_[P].sweeps;
+  }
+  for (int P = 0; P < 2; ++P)
+    for (int i = 0; i < sec_[P].k; ++i) rec.spectrum.push_back(host_d_[2048 * P + i]);
+  std::sort(rec.spectrum.begin(), rec.spectrum.end(), [](double a, double b) { return a > b; });
+  const double s0 = rec.spectrum.empty() ? 1.0 : rec.spectrum[0];
+  for (double& v : rec.spectrum) v /= s0;
+  records_.push_back(std::move(rec));
+  eps_site_ = -1;
+}
+
 // --------------------------------------------------- corner spectra ----
 void Ctm::corner_spectra() {
   std::vector<SmallProb> jp;
@@ -1194,7 +1336,11 @@ void Ctm::step(int n_iter) {
   ev_phase_.clear();
   static const int order[4] = {0, 2, 1, 3};
   for (int it = 0; it < n_iter; ++it) {
-    for (int m = 0; m < 4; ++m) move(order[m]);
+    if (opt_.c4v) {
+      move_c4v();
+    } else {
+      for (int m = 0; m < 4; ++m) move(order[m]);
+    }
     corner_spectra();
   }
   HCTM_HIP(hipMemcpyAsync(host_d_, misc_ + 16, sizeof(double), hipMemcpyDeviceToHost, st_));

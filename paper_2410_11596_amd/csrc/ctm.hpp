@@ -45,6 +45,7 @@ struct Options {
   int svd_iters = 12;
   int form_m = 0;  // 1: always form the decomposed matrix
   int precision = 0;  // 0: FP64 throughout; block products of the moves in 1: FP32, 2: BF16x3
+  int c4v = 0;        // 1: one corner and one edge for a C4v-symmetric tensor (1 x 1 cell)
   unsigned long long seed = 0x5eed;
   int profile = 0;  // 1: time every GEMM launch with HIP events
 };
@@ -121,6 +122,7 @@ class Ctm {
   BT& a_rot(int s, int r) { return a_rot_[s * 4 + (r % 4)]; }
   void quadrant(int s, int o);
   void move(int r);
+  void move_c4v();
   void mark(int phase);
   void truncated_svd(const BT* M, int chi, int key, uint64_t salt);  // M null: apply via impl_q_
   void apply_M(std::vector<SvdSector*>& ss, bool trans);

@@ -16,6 +16,18 @@ def iid_tensor(d, D, seed):
     return A / np.abs(A).max()
 
 
+def c4v_iid_tensor(d, D, seed):
+    """iid_tensor(d, D, seed) averaged over the eight symmetries of the square
+    (the rotations of the virtual legs [u, l, d, r], each with and without the
+    left-right reflection): a tensor with the C4v symmetry."""
+    A = iid_tensor(d, D, seed)
+    out = np.zeros_like(A)
+    for B in (A, A.transpose(0, 1, 4, 3, 2)):
+        for r in range(4):
+            out += B.transpose((0,) + tuple(1 + (np.arange(4) + r) % 4))
+    return out / 8.0
+
+
 def iid_cell(d, D, seeds):
     """Several independent tensors (one per unit-cell site)."""
     return [iid_tensor(d, D, s) for s in seeds]

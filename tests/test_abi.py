@@ -57,6 +57,7 @@ def test_opts_default(L):
     assert not o.boundary and not o.stream and not o.workspace
     assert o.Lx == 1 and o.Ly == 1
     assert o.precision == binding.CTM_PREC_FP64
+    assert o.c4v == 0
     assert L.ctm_opts_default(None) == binding.CTM_E_ARG
 
 
@@ -103,6 +104,10 @@ def test_option_checks(L):
     assert _ws(L, 2, 2, 8, precision=3)[0] == binding.CTM_E_ARG
     assert _ws(L, 2, 2, 8, precision=binding.CTM_PREC_BF16X3)[0] == 0
     assert _ws(L, 2, 2, 8, precision=binding.CTM_PREC_FP32)[0] == 0
+    assert _ws(L, 2, 2, 8, c4v=2)[0] == binding.CTM_E_ARG
+    assert _ws(L, 2, 2, 8, c4v=1)[0] == 0
+    assert _ws(L, 2, 2, 8, c4v=1, Lx=2)[0] == binding.CTM_E_ARG
+    assert b"1 x 1" in L.ctm_last_error(None)
     # the Z2 form needs a swap-symmetric boundary vector; the plain form does not
     b = np.array([1.0, 0.5, 0.0, 1.0])
     assert _ws(L, 2, 2, 8, boundary=b)[0] == binding.CTM_E_ARG
@@ -151,3 +156,32 @@ def test_server_argument_checks(L):
     assert L.ctm_server_wait(None, 1, None, None, None, ctypes.byref(info)) == binding.CTM_E_ARG
     assert L.ctm_server_load(None, None, None) == binding.CTM_E_ARG
     L.ctm_server_destroy(None)
+
+
+def test_c4v_init_rejects_a_tensor_without_the_symmetries_before_touching_a_device(L):
+    from oracle import c4v
+    from paper_2410_11596_amd import inputs
+
+    o = binding.CtmOpts()
+    L.ctm_opts_default(ctypes.byref(o))
+    o.c4v = 1
+    ctx = ctypes.c_void_p(1234)
+    A = np.ascontiguousarray(inputs.iid_tensor(2, 3, 4))
+    rc = L.ctm_init(ctypes.byref(ctx), A.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 2, 3, 8, ctypes.byref(o))
+    assert rc == binding.CTM_E_ARG and ctx.value is None
+    assert b"not invariant" in L.ctm_last_error(None)
+    # a tensor with the rotations but not the reflection is refused too
+    B = inputs.iid_tensor(2, 3, 5)
+    R = sum(np.transpose(B, (0,) + tuple(1 + (np.arange(4) + r) % 4)) for r in range(4)) / 4.0
+    assert np.abs(np.transpose(R, (0, 2, 3, 4, 1)) - R).max() < 1e-15
+    assert not c4v.is_c4v(R)
+    R = np.ascontiguousarray(R)
+    rc = L.ctm_init(ctypes.byref(ctx), R.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 2, 3, 8, ctypes.byref(o))
+    assert rc == binding.CTM_E_ARG
+    # the symmetrised tensor passes the check (on a machine without a device
+    # the call then fails at the device, not at the argument check)
+    S = np.ascontiguousarray(c4v.c4v_symmetrize(inputs.iid_tensor(2, 3, 4)))
+    rc = L.ctm_init(ctypes.byref(ctx), S.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 2, 3, 8, ctypes.byref(o))
+    assert rc != binding.CTM_E_ARG
+    if rc == binding.CTM_OK:
+        L.ctm_free(ctx)

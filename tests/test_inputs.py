@@ -19,3 +19,12 @@ def test_iid_tensor_is_seeded_and_normalised():
     assert np.array_equal(a, inputs.iid_tensor(2, 3, 7))
     assert not np.array_equal(a, inputs.iid_tensor(2, 3, 8))
     assert a.shape == (2, 3, 3, 3, 3) and np.abs(a).max() == 1.0
+
+
+def test_c4v_iid_tensor_has_the_eight_symmetries():
+    from oracle import c4v
+
+    A = inputs.c4v_iid_tensor(2, 3, 7)
+    assert c4v.is_c4v(A)
+    assert np.abs(A - inputs.c4v_iid_tensor(2, 3, 7)).max() == 0.0
+    assert np.abs(A - c4v.c4v_symmetrize(inputs.iid_tensor(2, 3, 7))).max() < 1e-15
