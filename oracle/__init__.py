@@ -12,6 +12,9 @@ ctmrg       directional CTMRG, in the plain (unrotated, one-sector) form and
             in the rotated Z2 form with per-sector truncated SVDs, plus the
             observables: one-site environment, RDMs, energy, Hermitian
             symmetry error, partition function per site (Sec. II A, II B, III A).
+c4v         the C4v-symmetric CTMRG (one corner, one edge; Sec. II A).
+hotrg       HOTRG in the plain and Z2 forms, with the symmetry probe b
+            (Sec. II A, III A); its readings are listed in its docstring.
 bruteforce  exact contraction of small finite open networks by row transfer,
             used to pin the CTMRG recursion where it is exact.
 
