@@ -198,6 +198,37 @@ def c4v_scheme(D, chi, steps, warmup, tol=1e-10, max_iter=200):
     return res
 
 
+def hotrg_speedup(chi=32, D=2, steps=6, warmup=6):
+    """HOTRG (include/hctm_hotrg.h): time per step of the Z2 and the plain
+    form once the bonds have reached chi, their ratio (Fig. 4(c) of the
+    paper), and the symmetry error of both forms with the probe b."""
+    import torch
+
+    from paper_2410_11596_amd import HOTRG, inputs
+
+    A = inputs.iid_tensor(2, D, 0)
+    res = {"workload": f"HOTRG on the double layer of an i.i.d. d=2 D={D} tensor, chi={chi}, FP64; "
+                       f"{warmup} steps to reach chi, then {steps} timed steps"}
+    for form in ("z2", "dense"):
+        h = HOTRG(A, chi, form=form)
+        h.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res[form + "_ms_per_step"] = 1e3 * (t1 - t0) / steps
+        res[form + "_kept_last"] = list(h.records()[-1]["kept"])
+        h.close()
+        p = HOTRG(A, chi, form=form, probes=True)
+        p.step(warmup + steps)
+        res[form + "_sym_error"] = p.sym_error()
+        res[form + "_log_z"] = p.log_z()
+        p.close()
+    res["z2_over_dense"] = res["dense_ms_per_step"] / res["z2_ms_per_step"]
+    return res
+
+
 def serving(n_req, rate, max_active=8, tol=1e-10, max_iter=40, seed=11):
     """A stream of n_req solves with Poisson arrivals (rate per second), D
     uniform in {2, 3, 4, 5} and chi in {16, 32, 64, 100} with chi >= D^2,
@@ -282,6 +313,7 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-block-product run")
     ap.add_argument("--no-c4v", action="store_true", help="skip the C4v-scheme comparison")
+    ap.add_argument("--no-hotrg", action="store_true", help="skip the HOTRG Z2/plain comparison")
     ap.add_argument("--serve", type=int, default=24, metavar="N",
                     help="solves in the serving run (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run (1/s)")
@@ -363,6 +395,8 @@ def main():
         out["mixed_bf16x3"] = mixed_precision(A, args.chi, args.steps, args.warmup, precision="bf16x3")
     if not args.no_c4v:
         out["c4v"] = c4v_scheme(args.D, args.chi, args.steps, args.warmup)
+    if not args.no_hotrg:
+        out["hotrg"] = hotrg_speedup()
     if args.serve > 0:
         out["serving"] = serving(args.serve, args.serve_rate)
     if not args.no_cpu_baseline:

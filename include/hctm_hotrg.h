@@ -1,0 +1,109 @@
+/*
+ * hctm_hotrg.h -- HOTRG on the double-layer network of a real iPEPS, in the
+ * eigenbasis of the bra-ket swap (Z2 form) or in the plain basis.
+ *
+ * The paper treats HOTRG (higher-order tensor renormalisation group) beside
+ * CTMRG and states that the Z2 structure of the rotated double layer carries
+ * over to its steps (Sec. II A); it measures HOTRG's Hermitian symmetry error
+ * with a probe tensor b (Sec. III A, Fig. 3) and its speed-up (Fig. 4(c),
+ * (d)).  The steps are those of the standard method:
+ *
+ *  - A step joins two copies of the current tensor T[u,l,d,r] along the
+ *    vertical bond, M[u,l1,l2,d,r1,r2] = sum_m T[u,l1,m,r1] T[m,l2,d,r2], and
+ *    cuts the fused left legs (l1,l2) and right legs (r1,r2) back to chi with
+ *    one isometry U: T'[u,x,d,y] = sum U[(l1 l2),x] M U[(r1 r2),y].
+ *  - U holds the dominant eigenvectors of the Gram matrix of M with rows
+ *    (l1,l2), or of the one with rows (r1,r2), whichever discards the smaller
+ *    sum of eigenvalues (the left one on a tie, i.e. when the two differ by
+ *    at most 1e-10 of their common trace ||M||_F^2).  Kept: min(chi,
+ *    #{lambda > cutoff * lambda_max}) over the merged spectrum of both
+ *    sectors, ties even first.  In the Z2 form the Gram matrices are block
+ *    diagonal and each sector is decomposed on its own: up to 256 rows by
+ *    one-sided Jacobi, larger sectors (up to 1024 rows) by subspace iteration
+ *    with Rayleigh-Ritz until the leading chi Ritz pairs have residuals
+ *    below 1e-12 of the largest eigenvalue.
+ *  - T' is divided by its Frobenius norm n_j and turned by a quarter turn
+ *    (the right leg becomes the upper one), so that steps alternate between
+ *    the two lattice directions.
+ *  - After k steps T stands for a torus of 2^k sites:
+ *    ln Z / N = ln n_0 + sum_j ln(n_j) / 2^j + ln(Tr T) / 2^k,
+ *    Tr T = sum T[u,l,u,l], n_0 the norm of the initial double layer.
+ *  - Symmetry probe (optional): one tensor of the network replaced by b
+ *    (as a D^4 x D^4 matrix between the ket and the bra indices of
+ *    [u,l,d,r]: +1 above the diagonal, -1 below) or by |b| (1 off the
+ *    diagonal).  In each step the impurity is joined (above) with a pure
+ *    tensor using the pure step's U and n_j.  The symmetry error is
+ *    |Z_b| / Z_|b|.  b is odd under the bra-ket swap, so in the Z2 form it
+ *    has only blocks of odd total parity and Z_b vanishes identically.
+ *
+ * Memory: the context allocates its device memory at hotrg_init (largest
+ * buffers (max(chi, D^2))^5 doubles, two of them).  Errors are the CTM_E_*
+ * codes of hctm.h; an error raised while GPU work ran poisons the context.
+ * One context may be used by one host thread at a time.
+ */
+#ifndef HCTM_HOTRG_H
+#define HCTM_HOTRG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hotrg_ctx hotrg_ctx;
+
+typedef struct {
+  int form;              /* CTM_FORM_Z2 (default) or CTM_FORM_DENSE */
+  double svd_rel_cutoff; /* eigenvalues kept above cutoff * largest (default 1e-12) */
+  int probes;            /* 1: carry the impurities b and |b| (hotrg_sym_error) */
+  void* stream;          /* hipStream_t or NULL (a stream owned by the context) */
+} hotrg_opts;
+
+/* Fill *o with the defaults above. */
+int hotrg_opts_default(hotrg_opts* o);
+
+/*
+ * Create a context: copies A (host, d*D^4 doubles, legs [s,u,l,d,r]) and
+ * forms the double layer (in the rotated basis in the Z2 form) as the
+ * initial tensor, divided by its norm.  Requires 1 <= d <= 16, 1 <= D <= 6,
+ * 1 <= chi, max(chi, D^2) <= 44 in the Z2 form and <= 32 in the plain form;
+ * finite A.  *out is NULL on failure.
+ */
+int hotrg_init(hotrg_ctx** out, const double* A, int d, int D, int chi, const hotrg_opts* o);
+
+/* Run n >= 0 steps.  A step fails with CTM_E_ARG (before any GPU work of
+ * that step) if a sector of a Gram matrix exceeds 1024 rows, the limit of
+ * the eigensolver. */
+int hotrg_step(hotrg_ctx* c, int n);
+
+/* ln Z per site of the torus of 2^k sites after k steps.  Synchronises. */
+int hotrg_log_z(hotrg_ctx* c, double* lnz);
+
+/* Probe mode only: z_b = Z_b / Z, z_abs = Z_|b| / Z and err = |z_b| / |z_abs|
+ * (any pointer may be NULL).  Synchronises. */
+int hotrg_sym_error(hotrg_ctx* c, double* err, double* z_b, double* z_abs);
+
+/* Number of steps run. */
+int hotrg_num_records(hotrg_ctx* c, int* n);
+
+/*
+ * Step i: the kept eigenvalues (merged, descending, divided by the largest;
+ * at most cap written, *n the full count), kept states per sector (plain
+ * form: all in k_even), side = 0 if the left Gram matrix gave U, 1 the right;
+ * discarded[0..1] = discarded weight of the left and the right one.
+ */
+int hotrg_record(hotrg_ctx* c, int i, double* spectrum, int cap, int* n, int* k_even, int* k_odd, int* side,
+                 double* discarded);
+
+/* Last error message of c (or of the calling thread's last failed init for
+ * NULL). */
+const char* hotrg_last_error(const hotrg_ctx* c);
+
+/* Release everything; NULL is accepted. */
+void hotrg_free(hotrg_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HCTM_HOTRG_H */

@@ -17,7 +17,10 @@ is silent:
   H2  U holds the dominant eigenvectors of the left Gram matrix
       ML = M_L M_L^T (M_L = M as a matrix with rows (l1,l2)) or of the right
       one MR (rows (r1,r2)), whichever discards the smaller weight (the sum
-      of the eigenvalues not kept); on a tie the left one.
+      of the eigenvalues not kept); on a tie the left one.  Both Gram
+      matrices have the trace ||M||_F^2; weights within 1e-10 of it count
+      as tied (a side that keeps every state discards exactly nothing, which
+      rounding must not turn into a preference).
   H3  Kept: min(chi, #{lambda > tau lambda_max}) over the merged spectrum of
       both sectors, ties even sector first (as in the CTMRG truncation).
       Columns of U: even sector first, each by decreasing eigenvalue.
@@ -117,7 +120,7 @@ def isometry(M, chi, tau, ph=None):
             col += len(sel)
         spec = np.sort(lam_all[kept])[::-1]
         cand = (U, side, tuple(kcount), spec / spec[0])
-        if best is None or err < errs[0]:
+        if best is None or err < errs[0] - 1e-10 * np.sum(lam_all):
             best = cand
     return best + (tuple(errs),)
 

@@ -5,4 +5,4 @@ include/hctm.h); `binding` is a thin ctypes layer over it and `inputs` draws
 the seeded synthetic tensors used by the tests and the benchmark.
 """
 from . import inputs  # noqa: F401
-from .binding import CTMRG, HctmError, Server, lib, workspace_size  # noqa: F401
+from .binding import CTMRG, HOTRG, HctmError, Server, lib, workspace_size  # noqa: F401

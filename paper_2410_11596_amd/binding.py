@@ -18,13 +18,15 @@ CTM_FORM_Z2, CTM_FORM_DENSE = 0, 1
 CTM_PREC_FP64, CTM_PREC_FP32, CTM_PREC_BF16X3 = 0, 1, 2
 ERROR_NAMES = {1: "CTM_E_ARG", 2: "CTM_E_NOMEM", 3: "CTM_E_HIP", 4: "CTM_E_NUMERIC", 5: "CTM_E_STATE"}
 
-# every C symbol that include/hctm.h and include/hctm_testing.h declare
+# every C symbol that the headers under include/ declare
 EXPORTS = [
     "ctm_opts_default", "ctm_workspace_size", "ctm_init", "ctm_step", "ctm_converged",
     "ctm_rdm_1site", "ctm_rdm_2site", "ctm_energy", "ctm_free", "ctm_last_error",
     "ctm_env_epsilon", "ctm_s_err", "ctm_log_kappa", "ctm_num_records", "ctm_record",
     "ctm_sector_dims", "ctm_timing", "ctm_gemm_stats", "ctm_set_precision",
     "ctm_server_create", "ctm_server_submit", "ctm_server_wait", "ctm_server_load", "ctm_server_destroy",
+    "hotrg_opts_default", "hotrg_init", "hotrg_step", "hotrg_log_z", "hotrg_sym_error", "hotrg_num_records",
+    "hotrg_record", "hotrg_last_error", "hotrg_free",
     "hctm_dev_gemm", "hctm_dev_gemm_f32", "hctm_dev_gemm_bf16x3", "hctm_dev_copy", "hctm_dev_chol_inv", "hctm_dev_jacobi", "hctm_dev_jacobi_log_doubles",
 ]
 
@@ -45,6 +47,15 @@ class CtmOpts(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class HotrgOpts(ctypes.Structure):
+    _fields_ = [
+        ("form", ctypes.c_int),
+        ("svd_rel_cutoff", ctypes.c_double),
+        ("probes", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
     ]
 
 
@@ -120,6 +131,15 @@ def lib():
                              vp, vp, vp],
                             ctypes.c_int),
         "hctm_dev_jacobi_log_doubles": ([ctypes.c_int, ctypes.c_int], ctypes.c_longlong),
+        "hotrg_opts_default": ([P(HotrgOpts)], ctypes.c_int),
+        "hotrg_init": ([P(vp), dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(HotrgOpts)], ctypes.c_int),
+        "hotrg_step": ([vp, ctypes.c_int], ctypes.c_int),
+        "hotrg_log_z": ([vp, dp], ctypes.c_int),
+        "hotrg_sym_error": ([vp, dp, dp, dp], ctypes.c_int),
+        "hotrg_num_records": ([vp, ip], ctypes.c_int),
+        "hotrg_record": ([vp, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, ip, dp], ctypes.c_int),
+        "hotrg_last_error": ([vp], ctypes.c_char_p),
+        "hotrg_free": ([vp], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -386,6 +406,88 @@ def dev_jacobi(X, m, n, tol, max_sweeps, sv, perm, sweeps, V=None, vlog=None, pr
 
 def jacobi_log_doubles(n, max_sweeps):
     return int(lib().hctm_dev_jacobi_log_doubles(n, max_sweeps))
+
+
+def _hcheck(code, ctx=None):
+    if code != CTM_OK:
+        msg = lib().hotrg_last_error(ctx).decode(errors="replace")
+        raise HctmError(code, msg)
+
+
+class HOTRG:
+    """HOTRG on the double layer of A (d, D, D, D, D) on the GPU, Z2 or
+    plain form; probes=True carries the symmetry probes b and |b|.  Work runs
+    on torch's current HIP stream; the context allocates its own device
+    memory."""
+
+    def __init__(self, A, chi, form="z2", svd_rel_cutoff=1e-12, probes=False, stream=None):
+        torch = _torch()
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        if A.ndim != 5:
+            raise ValueError("A must have shape (d, D, D, D, D)")
+        self.d, self.D, self.chi, self.form = A.shape[0], A.shape[1], int(chi), form
+        o = HotrgOpts()
+        _hcheck(lib().hotrg_opts_default(ctypes.byref(o)))
+        o.form = CTM_FORM_Z2 if form == "z2" else CTM_FORM_DENSE
+        o.svd_rel_cutoff = svd_rel_cutoff
+        o.probes = 1 if probes else 0
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        o.stream = ctypes.c_void_p(stream.cuda_stream)
+        ctx = ctypes.c_void_p()
+        _hcheck(lib().hotrg_init(ctypes.byref(ctx), _dptr(A), self.d, self.D, self.chi, ctypes.byref(o)))
+        self._ctx = ctx
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().hotrg_free(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def step(self, n=1):
+        _hcheck(lib().hotrg_step(self._ctx, int(n)), self._ctx)
+        return self
+
+    def log_z(self):
+        v = ctypes.c_double()
+        _hcheck(lib().hotrg_log_z(self._ctx, ctypes.byref(v)), self._ctx)
+        return v.value
+
+    def impurity_ratios(self):
+        e, zb, za = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _hcheck(lib().hotrg_sym_error(self._ctx, ctypes.byref(e), ctypes.byref(zb), ctypes.byref(za)), self._ctx)
+        return zb.value, za.value
+
+    def sym_error(self):
+        zb, za = self.impurity_ratios()
+        return abs(zb) / abs(za)
+
+    def records(self):
+        n = ctypes.c_int()
+        _hcheck(lib().hotrg_num_records(self._ctx, ctypes.byref(n)), self._ctx)
+        out = []
+        for i in range(n.value):
+            cap = 4096
+            s = np.zeros(cap)
+            m, ke, ko, side = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            disc = np.zeros(2)
+            _hcheck(lib().hotrg_record(self._ctx, i, _dptr(s), cap, ctypes.byref(m), ctypes.byref(ke),
+                                       ctypes.byref(ko), ctypes.byref(side), _dptr(disc)), self._ctx)
+            out.append({"spectrum": s[: m.value].copy(), "kept": (ke.value, ko.value), "side": side.value,
+                        "discarded": tuple(disc)})
+        return out
 
 
 class Server:

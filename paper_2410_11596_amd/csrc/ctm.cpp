@@ -331,40 +331,9 @@ void Ctm::normalise(BT& t) {
 void Ctm::setup(const double* A_host) {
   const int q = q_, D = D_;
   // basis U (rows) and U^T, at most two entries per row
-  std::vector<int> ti(2 * q, -1), tti(2 * q, -1);
-  std::vector<double> tc(2 * q, 0.0), ttc(2 * q, 0.0);
-  if (opt_.form == 0) {
-    const double r2 = 1.0 / std::sqrt(2.0);
-    int row = 0;
-    for (int k = 0; k < D; ++k) {
-      ti[2 * row] = k * D + k;
-      tc[2 * row] = 1.0;
-      ++row;
-    }
-    for (int sgn = 0; sgn < 2; ++sgn)
-      for (int k = 0; k < D; ++k)
-        for (int l = k + 1; l < D; ++l) {
-          ti[2 * row] = k * D + l;
-          tc[2 * row] = r2;
-          ti[2 * row + 1] = l * D + k;
-          tc[2 * row + 1] = sgn ? -r2 : r2;
-          ++row;
-        }
-  } else {
-    for (int a = 0; a < q; ++a) {
-      ti[2 * a] = a;
-      tc[2 * a] = 1.0;
-    }
-  }
-  std::vector<int> cnt(q, 0);
-  for (int a = 0; a < q; ++a)
-    for (int w = 0; w < 2; ++w) {
-      const int K = ti[2 * a + w];
-      if (K < 0) continue;
-      tti[2 * K + cnt[K]] = a;
-      ttc[2 * K + cnt[K]] = tc[2 * a + w];
-      ++cnt[K];
-    }
+  std::vector<int> ti, tti;
+  std::vector<double> tc, ttc;
+  basis_table(D, opt_.form == 0, ti, tc, tti, ttc);
   HCTM_HIP(hipMemcpy(tab_idx_, ti.data(), sizeof(int) * 2 * q, hipMemcpyHostToDevice));
   HCTM_HIP(hipMemcpy(tab_c_, tc.data(), sizeof(double) * 2 * q, hipMemcpyHostToDevice));
   HCTM_HIP(hipMemcpy(tabT_idx_, tti.data(), sizeof(int) * 2 * q, hipMemcpyHostToDevice));

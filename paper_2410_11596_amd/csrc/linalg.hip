@@ -697,6 +697,7 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(SmallBatch b) {
   const int n2 = n + (n & 1);
   const int mr = n2 - 1;  // rotating players; player n2-1 fixed
   const double tol = P.rel;
+  const int pairabs = P.flags & kJacPairAbs;
   // columns below m*eps*||X||_F are rounding noise: pairs involving them are
   // not rotated (their norms are kept as the singular values)
   __shared__ double red[16];
@@ -737,7 +738,7 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(SmallBatch b) {
         a = wave_sum(a);
         bb = wave_sum(bb);
         g = wave_sum(g);
-        if (fmin(a, bb) <= small2 || fabs(g) <= tol * sqrt(a) * sqrt(bb)) continue;
+        if (fmin(a, bb) <= small2 || fabs(g) <= (pairabs ? tol * fmax(a, bb) : tol * sqrt(a) * sqrt(bb))) continue;
         const double zeta = (bb - a) / (2.0 * g);
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t);
@@ -842,7 +843,7 @@ constexpr int kJacRows = 20;  // rows per lane, m <= 160
 // (sweep, round, pair) from lg.  Returns the sweeps done (the converged one
 // included), negated when max_sweeps ran out first.
 __device__ int jacobi_sweeps(double* Xs, double* nrm, int* any_rot, int m, int c0, int nn, double tol,
-                             double small2, int max_sweeps, double2* lg) {
+                             double small2, int pairabs, int max_sweeps, double2* lg) {
   const int tid = threadIdx.x;
   const int n2 = nn + (nn & 1), npairs = n2 / 2, rounds = n2 - 1;
   const int sub = tid & (kJacLanes - 1), grp = tid / kJacLanes, ngrp = NT / kJacLanes;
@@ -873,7 +874,7 @@ __device__ int jacobi_sweeps(double* Xs, double* nrm, int* any_rot, int m, int c
           const double a = nrm[i], bb = nrm[j];
           // sqrt(a) sqrt(b), not sqrt(a b): near-zero blocks (a sector that
           // the state leaves empty up to rounding) would underflow the product
-          if (fmin(a, bb) > small2 && fabs(g) > tol * sqrt(a) * sqrt(bb)) {
+          if (fmin(a, bb) > small2 && fabs(g) > (pairabs ? tol * fmax(a, bb) : tol * sqrt(a) * sqrt(bb))) {
             const double zeta = (bb - a) * rcp_nr(2.0 * g);
             const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
             c = rsq_nr(fma(t, t, 1.0));
@@ -959,7 +960,7 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
   for (int ph = pre ? 0 : 1; ph < 2; ++ph) {
     const int c0 = ph == 0 ? n - pre : 0, nn = ph == 0 ? pre : n;
     double2* lg = (rlog && ph == 0) ? rlog + jacobi_pre_log_offset(n, P.max_sweeps) : rlog;
-    const int sw = jacobi_sweeps(Xs, nrm, &any_rot, m, c0, nn, tol, small2, P.max_sweeps, lg);
+    const int sw = jacobi_sweeps(Xs, nrm, &any_rot, m, c0, nn, tol, small2, P.flags & kJacPairAbs, P.max_sweeps, lg);
     if (tid == 0 && P.info) {
       if (ph == 0)
         P.info[1] = sw < 0 ? -sw : sw;
@@ -1000,7 +1001,7 @@ constexpr int kJacL2Rows = kJacL2Max / 64;  // rows per lane
 constexpr int kJacL2Batch = 4;              // pairs loaded together by a wave
 
 __device__ int jacobi_l2_sweeps(double* Xc, double* nrm, int* any_rot, int m, int c0, int nn, double tol,
-                                double small2, int max_sweeps, double2* lg) {
+                                double small2, int pairabs, int max_sweeps, double2* lg) {
   constexpr int NW = kJacL2Threads / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n2 = nn + (nn & 1), npairs = n2 / 2, rounds = n2 - 1;
@@ -1041,7 +1042,7 @@ __device__ int jacobi_l2_sweeps(double* Xc, double* nrm, int* any_rot, int m, in
             for (int q = 0; q < kJacL2Rows; ++q) g = fma(u[bq][q], v[bq][q], g);
             g = wave_sum(g);
             const double a = nrm[i], bb = nrm[j];
-            if (fmin(a, bb) > small2 && fabs(g) > tol * sqrt(a) * sqrt(bb)) {
+            if (fmin(a, bb) > small2 && fabs(g) > (pairabs ? tol * fmax(a, bb) : tol * sqrt(a) * sqrt(bb))) {
               const double zeta = (bb - a) * rcp_nr(2.0 * g);
               const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
               c = rsq_nr(fma(t, t, 1.0));
@@ -1111,7 +1112,8 @@ __global__ __launch_bounds__(kJacL2Threads) void jacobi_l2_kernel(SmallBatch b) 
   for (int ph = pre ? 0 : 1; ph < 2; ++ph) {
     const int c0 = ph == 0 ? n - pre : 0, nn = ph == 0 ? pre : n;
     double2* lg = (rlog && ph == 0) ? rlog + jacobi_pre_log_offset(n, P.max_sweeps) : rlog;
-    const int sw = jacobi_l2_sweeps(Xc, nrm, &any_rot, m, c0, nn, tol, small2, P.max_sweeps, lg);
+    const int sw = jacobi_l2_sweeps(Xc, nrm, &any_rot, m, c0, nn, tol, small2, P.flags & kJacPairAbs, P.max_sweeps,
+                                    lg);
     if (tid == 0 && P.info) {
       if (ph == 0)
         P.info[1] = sw < 0 ? -sw : sw;
@@ -1253,6 +1255,26 @@ __global__ __launch_bounds__(256) void col_resid_kernel(const double* __restrict
     atomicMax(out, (unsigned long long)__double_as_longlong(sqrt(d2)));
     atomicMax(out + 1, (unsigned long long)__double_as_longlong(sqrt(a2)));
   }
+}
+
+// Ritz residuals: out[c] = || GU[:, c] - lam[c] U[:, c] ||_2 for c < k (n rows,
+// row-major, leading dim ld); one block per column, no atomics.
+__global__ __launch_bounds__(256) void ritz_resid_kernel(const double* __restrict__ GU, const double* __restrict__ U,
+                                                         const double* __restrict__ lam, int n, int ld,
+                                                         double* __restrict__ out) {
+  const int c = blockIdx.x;
+  __shared__ double red[4];
+  const double l = lam[c];
+  double d2 = 0.0;
+  for (int r = threadIdx.x; r < n; r += 256) {
+    const double x = GU[(long long)r * ld + c] - l * U[(long long)r * ld + c];
+    d2 += x * x;
+  }
+  d2 = wave_sum(d2);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = d2;
+  __syncthreads();
+  if (threadIdx.x == 0) out[c] = sqrt(red[0] + red[1] + red[2] + red[3]);
 }
 
 // --------------------------------------------------------- truncation ----
@@ -1479,6 +1501,13 @@ void col_resid(const double* A, int lda, const double* B, int ldb, int n, int k,
   if (k <= 0) return;
   hipLaunchKernelGGL(col_resid_kernel, dim3(k), dim3(256), 0, s, A, lda, B, ldb, n,
                      reinterpret_cast<unsigned long long*>(out));
+  HCTM_HIP(hipGetLastError());
+}
+
+void ritz_resid(const double* GU, const double* U, const double* lam, int n, int ld, int k, double* out,
+                hipStream_t s) {
+  if (k <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(ritz_resid_kernel, dim3(k), dim3(256), 0, s, GU, U, lam, n, ld, out);
   HCTM_HIP(hipGetLastError());
 }
 

@@ -15,11 +15,21 @@ struct SmallProb {
   int* perm;       // Jacobi: column of the j-th largest
   double* vlog;    // Jacobi: rotation log (jacobi_log_doubles), enables the LDS kernel with V
   int flags;       // Cholesky: 1 = factor the unit-diagonal Gram D^-1 G D^-1 (D = sqrt diag G);
-                   // Rinv is then D^-1 R^-1 (sv must point to n doubles of scratch)
+                   // Rinv is then D^-1 R^-1 (sv must point to n doubles of scratch).
+                   // Jacobi: kJacPairAbs = a pair of columns counts as orthogonal once
+                   // |x_i . x_j| <= rel * max(|x_i|^2, |x_j|^2) (instead of rel |x_i| |x_j|)
   int pre;         // Jacobi (LDS kernel): the last pre columns are first orthogonalised among
                    // themselves (0: not); their sweep count goes to info[1]
   double* work;    // Jacobi: m*n doubles of device scratch (enables the L2 kernel for n <= 256)
 };
+
+// For the eigenvectors of a symmetric positive semi-definite X (X V = V L):
+// one-sided Jacobi on X orthogonalises the columns of X V, whose norms are the
+// eigenvalues, so relative orthogonality of two columns of very different
+// norms lies below the rounding floor; measured against the larger of the two
+// it is reached, and it bounds the mixing of two eigenvectors by about
+// rel / (1 - (lambda_j / lambda_i)^2).
+constexpr int kJacPairAbs = 2;
 
 constexpr int kMaxSmall = 16;
 struct SmallBatch {
@@ -69,6 +79,9 @@ size_t jacobi_log_doubles(int n, int max_sweeps);
 void col_resid(const double* A, int lda, const double* B, int ldb, int n, int k, double* out, hipStream_t s);
 void gather_cols(const double* X, int ldx, const int* perm, const double* sv, int m, int k, double* U, int ldu,
                  hipStream_t s);
+// out[c] = || GU[:, c] - lam[c] U[:, c] ||_2 for the first k columns (n rows, leading dim ld)
+void ritz_resid(const double* GU, const double* U, const double* lam, int n, int ld, int k, double* out,
+                hipStream_t s);
 void select_states(const SelectArgs& a, hipStream_t s);
 
 }  // namespace hctm

@@ -1,8 +1,57 @@
 // Construction kernels (double layer, basis change, initial environment, dots).
 #pragma once
+#include <cmath>
+#include <vector>
+
 #include "hctm_internal.hpp"
 
 namespace hctm {
+
+// Rows of the leg basis as a table: row a of U has the plain indices
+// ti[2a], ti[2a+1] (-1 if absent) with coefficients tc[2a], tc[2a+1].
+// rotated: the eigenbasis of the bra-ket swap (Sec. II B; even sector first:
+// |k k>, then (|k l> + |l k>)/sqrt2 for k < l; odd: (|k l> - |l k>)/sqrt2);
+// otherwise the identity.  tti/ttc: the same table for U^T.
+inline void basis_table(int D, bool rotated, std::vector<int>& ti, std::vector<double>& tc, std::vector<int>& tti,
+                        std::vector<double>& ttc) {
+  const int q = D * D;
+  ti.assign(2 * q, -1);
+  tti.assign(2 * q, -1);
+  tc.assign(2 * q, 0.0);
+  ttc.assign(2 * q, 0.0);
+  if (rotated) {
+    const double r2 = 1.0 / std::sqrt(2.0);
+    int row = 0;
+    for (int k = 0; k < D; ++k) {
+      ti[2 * row] = k * D + k;
+      tc[2 * row] = 1.0;
+      ++row;
+    }
+    for (int sgn = 0; sgn < 2; ++sgn)
+      for (int k = 0; k < D; ++k)
+        for (int l = k + 1; l < D; ++l) {
+          ti[2 * row] = k * D + l;
+          tc[2 * row] = r2;
+          ti[2 * row + 1] = l * D + k;
+          tc[2 * row + 1] = sgn ? -r2 : r2;
+          ++row;
+        }
+  } else {
+    for (int a = 0; a < q; ++a) {
+      ti[2 * a] = a;
+      tc[2 * a] = 1.0;
+    }
+  }
+  std::vector<int> cnt(q, 0);
+  for (int a = 0; a < q; ++a)
+    for (int w = 0; w < 2; ++w) {
+      const int K = ti[2 * a + w];
+      if (K < 0) continue;
+      tti[2 * K + cnt[K]] = a;
+      ttc[2 * K + cnt[K]] = tc[2 * a + w];
+      ++cnt[K];
+    }
+}
 
 constexpr int kMaxPairs = 16;
 struct DLArgs {

@@ -11,7 +11,7 @@ import pytest
 from paper_2410_11596_amd import binding
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("hctm.h", "hctm_testing.h", "hctm_serve.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("hctm.h", "hctm_testing.h", "hctm_serve.h", "hctm_hotrg.h")]
 DECL = re.compile(r"^\s*(?:const\s+)?(?:int|void|char|long long|size_t)\s*\**\s*(\w+)\s*\(", re.M)
 
 
@@ -185,3 +185,31 @@ def test_c4v_init_rejects_a_tensor_without_the_symmetries_before_touching_a_devi
     assert rc != binding.CTM_E_ARG
     if rc == binding.CTM_OK:
         L.ctm_free(ctx)
+
+
+def test_hotrg_argument_checks_before_touching_a_device(L):
+    o = binding.HotrgOpts()
+    assert L.hotrg_opts_default(ctypes.byref(o)) == binding.CTM_OK
+    assert o.form == binding.CTM_FORM_Z2 and o.svd_rel_cutoff == 1e-12 and o.probes == 0 and not o.stream
+    A = np.ones((2, 2, 2, 2, 2))
+    dp = A.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    ctx = ctypes.c_void_p(99)
+    assert L.hotrg_init(ctypes.byref(ctx), dp, 2, 7, 8, ctypes.byref(o)) == binding.CTM_E_ARG
+    assert ctx.value is None
+    assert L.hotrg_init(ctypes.byref(ctx), dp, 2, 2, 45, ctypes.byref(o)) == binding.CTM_E_ARG
+    assert b"at most 44" in L.hotrg_last_error(None)
+    o.form = binding.CTM_FORM_DENSE
+    assert L.hotrg_init(ctypes.byref(ctx), dp, 2, 2, 33, ctypes.byref(o)) == binding.CTM_E_ARG
+    assert b"at most 32" in L.hotrg_last_error(None)
+    o.form = 5
+    assert L.hotrg_init(ctypes.byref(ctx), dp, 2, 2, 8, ctypes.byref(o)) == binding.CTM_E_ARG
+    o.form = binding.CTM_FORM_Z2
+    o.probes = 2
+    assert L.hotrg_init(ctypes.byref(ctx), dp, 2, 2, 8, ctypes.byref(o)) == binding.CTM_E_ARG
+    o.probes = 0
+    A[1, 0, 0, 0, 0] = np.nan
+    assert L.hotrg_init(ctypes.byref(ctx), dp, 2, 2, 8, ctypes.byref(o)) == binding.CTM_E_NUMERIC
+    assert L.hotrg_init(ctypes.byref(ctx), None, 2, 2, 8, ctypes.byref(o)) == binding.CTM_E_ARG
+    assert L.hotrg_step(None, 1) == binding.CTM_E_ARG
+    assert L.hotrg_log_z(None, None) == binding.CTM_E_ARG
+    L.hotrg_free(None)
