@@ -198,34 +198,39 @@ def c4v_scheme(D, chi, steps, warmup, tol=1e-10, max_iter=200):
     return res
 
 
-def hotrg_speedup(chi=32, D=2, steps=6, warmup=6):
+def hotrg_speedup(chis=(32, 48, 64), D=2, steps=4, warmup=6, probe_chi=32):
     """HOTRG (include/hctm_hotrg.h): time per step of the Z2 and the plain
-    form once the bonds have reached chi, their ratio (Fig. 4(c) of the
-    paper), and the symmetry error of both forms with the probe b."""
+    form once the bonds have reached chi, and their ratio, for several chi
+    (Fig. 4(c) of the paper); the symmetry error of both forms with the probe
+    b at probe_chi."""
     import torch
 
     from paper_2410_11596_amd import HOTRG, inputs
 
     A = inputs.iid_tensor(2, D, 0)
-    res = {"workload": f"HOTRG on the double layer of an i.i.d. d=2 D={D} tensor, chi={chi}, FP64; "
-                       f"{warmup} steps to reach chi, then {steps} timed steps"}
+    res = {"workload": f"HOTRG on the double layer of an i.i.d. d=2 D={D} tensor, FP64; {warmup} steps to "
+                       f"reach chi, then {steps} timed steps", "chi": list(chis)}
     for form in ("z2", "dense"):
-        h = HOTRG(A, chi, form=form)
-        h.step(warmup)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        h.step(steps)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        res[form + "_ms_per_step"] = 1e3 * (t1 - t0) / steps
-        res[form + "_kept_last"] = list(h.records()[-1]["kept"])
-        h.close()
-        p = HOTRG(A, chi, form=form, probes=True)
+        ms, kept = [], []
+        for chi in chis:
+            h = HOTRG(A, chi, form=form)
+            h.step(warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h.step(steps)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ms.append(1e3 * (t1 - t0) / steps)
+            kept.append(list(h.records()[-1]["kept"]))
+            h.close()
+        res[form + "_ms_per_step"] = ms
+        res[form + "_kept_last"] = kept
+        p = HOTRG(A, probe_chi, form=form, probes=True)
         p.step(warmup + steps)
-        res[form + "_sym_error"] = p.sym_error()
-        res[form + "_log_z"] = p.log_z()
+        res[form + "_sym_error_chi%d" % probe_chi] = p.sym_error()
+        res[form + "_log_z_chi%d" % probe_chi] = p.log_z()
         p.close()
-    res["z2_over_dense"] = res["dense_ms_per_step"] / res["z2_ms_per_step"]
+    res["z2_over_dense"] = [d / z for d, z in zip(res["dense_ms_per_step"], res["z2_ms_per_step"])]
     return res
 
 

@@ -19,7 +19,7 @@
  *    #{lambda > cutoff * lambda_max}) over the merged spectrum of both
  *    sectors, ties even first.  In the Z2 form the Gram matrices are block
  *    diagonal and each sector is decomposed on its own: up to 256 rows by
- *    one-sided Jacobi, larger sectors (up to 1024 rows) by subspace iteration
+ *    one-sided Jacobi, larger sectors (up to 4096 rows) by subspace iteration
  *    with Rayleigh-Ritz until the leading chi Ritz pairs have residuals
  *    below 1e-12 of the largest eigenvalue.
  *  - T' is divided by its Frobenius norm n_j and turned by a quarter turn
@@ -66,14 +66,13 @@ int hotrg_opts_default(hotrg_opts* o);
  * Create a context: copies A (host, d*D^4 doubles, legs [s,u,l,d,r]) and
  * forms the double layer (in the rotated basis in the Z2 form) as the
  * initial tensor, divided by its norm.  Requires 1 <= d <= 16, 1 <= D <= 6,
- * 1 <= chi, max(chi, D^2) <= 44 in the Z2 form and <= 32 in the plain form;
- * finite A.  *out is NULL on failure.
+ * 1 <= chi, max(chi, D^2) <= 64; finite A.  *out is NULL on failure.
  */
 int hotrg_init(hotrg_ctx** out, const double* A, int d, int D, int chi, const hotrg_opts* o);
 
 /* Run n >= 0 steps.  A step fails with CTM_E_ARG (before any GPU work of
- * that step) if a sector of a Gram matrix exceeds 1024 rows, the limit of
- * the eigensolver. */
+ * that step) if a sector of a Gram matrix exceeds 4096 rows, the limit of
+ * the eigensolver (only the plain form at chi = 64 reaches it exactly). */
 int hotrg_step(hotrg_ctx* c, int n);
 
 /* ln Z per site of the torus of 2^k sites after k steps.  Synchronises. */

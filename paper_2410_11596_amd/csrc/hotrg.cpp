@@ -27,9 +27,9 @@ namespace hctm {
 namespace {
 
 constexpr int kSweeps = 40;
-constexpr int kEigMax = 1024;   // rows of a Gram sector the Jacobi eigensolver takes
+constexpr int kEigMax = 4096;   // rows of a Gram sector the eigensolver takes
 constexpr int kJacSmall = 256;  // sectors up to this size are decomposed directly (LDS or L2 Jacobi)
-constexpr int kSubL = 128;      // largest subspace of the iterative eigensolver (chi + 32 <= 76)
+constexpr int kSubL = 128;      // largest subspace of the iterative eigensolver (chi + 32 <= 96)
 constexpr int kSubMaxIter = 300;
 constexpr double kRitzTol = 1e-12;  // converged: ||G u - lam u|| <= kRitzTol * lam_1 for the leading chi pairs
 constexpr double kRitzAccept = 1e-9;
@@ -514,7 +514,7 @@ void Hotrg::step(int n) {
     for (int P = 0; P < 2; ++P)
       if (nsec[P] > kEigMax)
         throw Error(1, "HOTRG: a Gram sector of " + std::to_string(nsec[P]) +
-                           " rows exceeds the eigensolver's 1024; lower chi");
+                           " rows exceeds the eigensolver's 4096; lower chi");
     gram(0);
     gram(1);
     // eigenpairs of both Gram matrices: sectors up to kJacSmall rows by one
@@ -779,9 +779,9 @@ int hotrg_init(hotrg_ctx** out, const double* A, int d, int D, int chi, const ho
     if (o->form != CTM_FORM_Z2 && o->form != CTM_FORM_DENSE) throw hctm::Error(CTM_E_ARG, "unknown form");
     if (d < 1 || d > 16) throw hctm::Error(CTM_E_ARG, "d must be in [1, 16]");
     if (D < 1 || D > 6) throw hctm::Error(CTM_E_ARG, "D must be in [1, 6]");
-    const int cmax = o->form == CTM_FORM_Z2 ? 44 : 32;
+    const int cmax = 64;
     if (chi < 1 || std::max(chi, D * D) > cmax)
-      throw hctm::Error(CTM_E_ARG, "max(chi, D^2) must be at most " + std::to_string(cmax) + " in this form");
+      throw hctm::Error(CTM_E_ARG, "max(chi, D^2) must be at most " + std::to_string(cmax));
     if (!(o->svd_rel_cutoff >= 0.0) || o->svd_rel_cutoff >= 1.0)
       throw hctm::Error(CTM_E_ARG, "svd_rel_cutoff out of range");
     if (o->probes != 0 && o->probes != 1) throw hctm::Error(CTM_E_ARG, "probes must be 0 or 1");

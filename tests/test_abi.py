@@ -196,11 +196,10 @@ def test_hotrg_argument_checks_before_touching_a_device(L):
     ctx = ctypes.c_void_p(99)
     assert L.hotrg_init(ctypes.byref(ctx), dp, 2, 7, 8, ctypes.byref(o)) == binding.CTM_E_ARG
     assert ctx.value is None
-    assert L.hotrg_init(ctypes.byref(ctx), dp, 2, 2, 45, ctypes.byref(o)) == binding.CTM_E_ARG
-    assert b"at most 44" in L.hotrg_last_error(None)
+    assert L.hotrg_init(ctypes.byref(ctx), dp, 2, 2, 65, ctypes.byref(o)) == binding.CTM_E_ARG
+    assert b"at most 64" in L.hotrg_last_error(None)
     o.form = binding.CTM_FORM_DENSE
-    assert L.hotrg_init(ctypes.byref(ctx), dp, 2, 2, 33, ctypes.byref(o)) == binding.CTM_E_ARG
-    assert b"at most 32" in L.hotrg_last_error(None)
+    assert L.hotrg_init(ctypes.byref(ctx), dp, 2, 2, 65, ctypes.byref(o)) == binding.CTM_E_ARG
     o.form = 5
     assert L.hotrg_init(ctypes.byref(ctx), dp, 2, 2, 8, ctypes.byref(o)) == binding.CTM_E_ARG
     o.form = binding.CTM_FORM_Z2

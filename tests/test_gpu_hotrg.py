@@ -116,3 +116,16 @@ def test_subspace_eigensolver_against_oracle(form, chi, steps):
     o = hotrg.Run(chi, form, A=A).step(steps)
     g = _gpu(A, chi, form, steps)
     _compare(g, o)
+
+
+def test_forms_agree_at_chi48_subspace_sectors():
+    """chi = 48: plain Gram matrices of 2304 rows, Z2 sectors of about 1150,
+    all by subspace iteration."""
+    A = inputs.iid_tensor(2, 2, 11)
+    z = _gpu(A, 48, "z2", 6)
+    p = _gpu(A, 48, "dense", 6)
+    assert abs(z.log_z() - p.log_z()) < 1e-9 * max(1.0, abs(p.log_z()))
+    for rz, rp in zip(z.records(), p.records()):
+        assert sum(rz["kept"]) == sum(rp["kept"])
+        k = len(rz["spectrum"])
+        assert np.allclose(rz["spectrum"], rp["spectrum"][:k], rtol=1e-7, atol=1e-13)
