@@ -123,3 +123,22 @@ def test_mixed_precision_refines_to_the_fp64_fixed_point():
     g.run(300, tol=1e-12)
     assert np.abs(g.rdm1() - ref.rdm1()).max() < 1e-10
     assert np.abs(g.rdm2("h") - ref.rdm2("h")).max() < 1e-10
+
+
+@pytest.mark.parametrize("form", ["z2", "dense"])
+def test_degenerate_sizes(form):
+    """chi = 1, D = 1 and a product state: exact RDMs and the oracle."""
+    A = c4v_tensor(2, 5)
+    o = c4v.C4vRun(1, form, A=A).step(5)
+    g = _gpu(A, 1, form, 5)
+    _compare(g, o)
+    A1 = inputs.iid_tensor(3, 1, 2)
+    g = _gpu(A1, 4, form, 3)
+    r1 = g.rdm1()
+    v = A1.reshape(3)
+    assert np.allclose(r1, np.outer(v, v) / (v @ v), atol=1e-14)
+    P = inputs.product_state(np.array([0.6, -0.8]), 2)
+    g = _gpu(P, 4, form, 3)
+    w = np.array([0.6, -0.8])
+    assert np.allclose(g.rdm1(), np.outer(w, w), atol=1e-14)
+    assert all(sum(r["kept"]) == 1 for r in g.records())

@@ -129,3 +129,24 @@ def test_forms_agree_at_chi48_subspace_sectors():
         assert sum(rz["kept"]) == sum(rp["kept"])
         k = len(rz["spectrum"])
         assert np.allclose(rz["spectrum"], rp["spectrum"][:k], rtol=1e-7, atol=1e-13)
+
+
+@pytest.mark.parametrize("form", ["z2", "dense"])
+def test_degenerate_sizes(form):
+    """D = 1 (the double layer is a number: ln Z = ln a exactly), chi = 1
+    (one state per step) and a product state (rank-one network) against the
+    oracle and the closed forms."""
+    A1 = inputs.iid_tensor(3, 1, 2)
+    g = _gpu(A1, 4, form, 3)
+    a = float(np.sum(A1.reshape(3) ** 2))
+    assert abs(g.log_z() - np.log(a)) < 1e-13
+    A = inputs.iid_tensor(2, 2, 4)
+    o = hotrg.Run(1, form, A=A).step(6)
+    g = _gpu(A, 1, form, 6)
+    _compare(g, o)
+    assert all(sum(r["kept"]) == 1 for r in g.records())
+    v = np.array([0.6, -0.8, 0.3])
+    P = inputs.product_state(v, 3)
+    g = _gpu(P, 8, form, 5, probes=True)
+    assert abs(g.log_z() - np.log(v @ v)) < 1e-13
+    assert all(sum(r["kept"]) == 1 for r in g.records())
