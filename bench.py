@@ -319,6 +319,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-block-product run")
     ap.add_argument("--no-c4v", action="store_true", help="skip the C4v-scheme comparison")
     ap.add_argument("--no-hotrg", action="store_true", help="skip the HOTRG Z2/plain comparison")
+    ap.add_argument("--hotrg-only", type=int, default=0, metavar="CHI",
+                    help="run only the HOTRG comparison at this chi and print its JSON")
     ap.add_argument("--serve", type=int, default=24, metavar="N",
                     help="solves in the serving run (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run (1/s)")
@@ -326,9 +328,12 @@ def main():
                     help="before timing, copy BYTES three times (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
-              "DESIGN.md and is not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solver is built for a single GPU "
+              "and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.hotrg_only:
+        print(json.dumps(hotrg_speedup(chis=(args.hotrg_only,), probe_chi=min(args.hotrg_only, 32))))
+        return
 
     import torch
 
