@@ -28,7 +28,7 @@ namespace {
 
 constexpr int kSweeps = 40;
 constexpr int kEigMax = 4096;   // rows of a Gram sector the eigensolver takes
-constexpr int kJacSmall = 256;  // sectors up to this size are decomposed directly (LDS or L2 Jacobi)
+constexpr int kJacSmall = 128;  // sectors up to this size are decomposed directly (LDS Jacobi)
 constexpr int kSubL = 128;      // largest subspace of the iterative eigensolver (chi + 32 <= 96)
 constexpr int kSubMaxIter = 300;
 constexpr double kRitzTol = 1e-12;  // converged: ||G u - lam u|| <= kRitzTol * lam_1 for the leading chi pairs
@@ -368,7 +368,7 @@ void Hotrg::orth(std::vector<EigJob*>& js, bool from_y) {
 }
 
 // Leading eigenpairs of Gram sectors too large for a direct decomposition:
-// subspace iteration Y = G Q, Q = orth(Y), and every other iteration a
+// subspace iteration Y = G Q, Q = orth(Y), and every third iteration a
 // Rayleigh-Ritz step (B = Q^T G Q, Jacobi on B, U = Q V) whose residuals
 // ||G u - lam u|| over the leading kc pairs decide convergence.  The result
 // of job J is in its slot: Ritz vectors Uf (n x l, by decreasing value) and
@@ -403,7 +403,7 @@ void Hotrg::eig_subspace(std::vector<EigJob>& jobs, uint64_t salt) {
     gemm(g, st_, gscratch_, gscratch_cap_);
     g.clear();
     for (EigJob* J : act) J->iters = t + 1;
-    const bool check = t >= 2 && (t % 2 == 0 || t == kSubMaxIter - 1);
+    const bool check = t >= 2 && (t % 3 == 2 || t == kSubMaxIter - 1);
     if (check) {
       std::vector<SmallProb> jp;
       for (EigJob* J : act) {

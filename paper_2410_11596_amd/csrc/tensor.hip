@@ -265,12 +265,21 @@ struct TraceArgs {
   int nb;
 };
 
-__global__ void trace_blocks_kernel(TraceArgs a, double* out) {
-  if (threadIdx.x != 0) return;
+// one block of 256 threads: thread t sums the diagonal entries i = t mod 256
+// of every block, then a fixed-order tree reduction (deterministic)
+__global__ __launch_bounds__(256) void trace_blocks_kernel(TraceArgs a, double* out) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
   double s = 0.0;
   for (int b = 0; b < a.nb; ++b)
-    for (int i = 0; i < a.n[b]; ++i) s += a.p[b][(long long)i * a.ld[b] + i];
-  *out = s;
+    for (int i = t; i < a.n[b]; i += 256) s += a.p[b][(long long)i * a.ld[b] + i];
+  red[t] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) *out = red[0];
 }
 
 __global__ void log_ratio_kernel(const double* __restrict__ z, double* __restrict__ out) {
@@ -299,14 +308,15 @@ void swap_asym(const double* x, int D, double* part, double* out, hipStream_t s)
 }
 
 void trace_blocks(const double* const* p, const int* n, const int* ld, int nb, double* out, hipStream_t s) {
+  if (nb < 0 || nb > 8) throw Error(1, "trace_blocks: at most 8 blocks");
   TraceArgs a;
   a.nb = nb;
-  for (int i = 0; i < nb && i < 8; ++i) {
+  for (int i = 0; i < nb; ++i) {
     a.p[i] = p[i];
     a.n[i] = n[i];
     a.ld[i] = ld[i];
   }
-  hipLaunchKernelGGL(trace_blocks_kernel, dim3(1), dim3(64), 0, s, a, out);
+  hipLaunchKernelGGL(trace_blocks_kernel, dim3(1), dim3(256), 0, s, a, out);
   HCTM_HIP(hipGetLastError());
 }
 
