@@ -38,8 +38,6 @@ constexpr double kRitzAccept = 1e-9;
 struct EigJob {
   int side = 0, P = 0, n = 0, l = 0, kc = 0, slot = 0;
   const double* G = nullptr;  // n x n, ld n
-  bool done = false;
-  int iters = 0;
   std::vector<double> lam;    // Ritz values, descending (host)
 };
 
@@ -57,7 +55,6 @@ class Hotrg {
   double log_z();
   void impurity_ratios(double* zb, double* zab);
   const std::vector<StepRecord>& records() const { return rec_; }
-  int probes() const { return nimp_; }
 
  private:
   void plan(bool counting);
@@ -402,7 +399,6 @@ void Hotrg::eig_subspace(std::vector<EigJob>& jobs, uint64_t salt) {
     }
     gemm(g, st_, gscratch_, gscratch_cap_);
     g.clear();
-    for (EigJob* J : act) J->iters = t + 1;
     const bool check = t >= 2 && (t % 3 == 2 || t == kSubMaxIter - 1);
     if (check) {
       std::vector<SmallProb> jp;
@@ -482,7 +478,6 @@ void Hotrg::eig_subspace(std::vector<EigJob>& jobs, uint64_t salt) {
         const bool last = t == kSubMaxIter - 1;
         if (rmax <= kRitzTol * lam1 || (last && rmax <= kRitzAccept * lam1)) {
           J->lam.assign(h, h + J->l);
-          J->done = true;
         } else if (last) {
           throw Error(4, "HOTRG: the subspace iteration did not converge");
         } else {
