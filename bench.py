@@ -103,6 +103,27 @@ def time_form(A, chi, form, steps, warmup, profile):
     return (t1 - t0), stats, phases, split
 
 
+def late_iterations(A, chi, skip, steps):
+    """Time per iteration later in the same solve (iterations skip+1 ..
+    skip+steps): the cost of an iteration falls as the cuts converge (the
+    decomposed matrix is applied through the corners, fewer subspace
+    iterations)."""
+    import torch
+
+    from paper_2410_11596_amd import CTMRG
+
+    g = CTMRG(A, chi)
+    g.step(skip)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.close()
+    return {"iterations": [skip + 1, skip + steps], "ms_per_step": 1e3 * (t1 - t0) / steps,
+            "value": steps / (t1 - t0), "unit": "CTMRG iterations/s"}
+
+
 def mixed_precision(A, chi, steps, warmup, refine_max=40, tol=1e-10, precision="fp32"):
     """Block products of the moves in FP32 (CTM_PREC_FP32), timed like the
     FP64 form; then the error of its RDMs and energy against the FP64 form
@@ -234,6 +255,30 @@ def hotrg_speedup(chis=(32, 48, 64), D=2, steps=4, warmup=6, probe_chi=32):
     return res
 
 
+def hotrg_by_d(Ds=(2, 4, 6), chi=64, steps=4, warmup=6):
+    """HOTRG Z2 / plain time per step at one chi for several D (the paper:
+    the speed-up hardly depends on D, which only enters the first step)."""
+    import torch
+
+    from paper_2410_11596_amd import HOTRG, inputs
+
+    res = {"chi": chi, "D": list(Ds), "z2_ms_per_step": [], "dense_ms_per_step": []}
+    for D in Ds:
+        A = inputs.iid_tensor(2, D, 0)
+        for form in ("z2", "dense"):
+            h = HOTRG(A, chi, form=form)
+            h.step(warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h.step(steps)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            res[form + "_ms_per_step"].append(1e3 * (t1 - t0) / steps)
+            h.close()
+    res["z2_over_dense"] = [d / z for d, z in zip(res["dense_ms_per_step"], res["z2_ms_per_step"])]
+    return res
+
+
 def serving(n_req, rate, max_active=8, tol=1e-10, max_iter=40, seed=11):
     """A stream of n_req solves with Poisson arrivals (rate per second), D
     uniform in {2, 3, 4, 5} and chi in {16, 32, 64, 100} with chi >= D^2,
@@ -319,6 +364,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-block-product run")
     ap.add_argument("--no-c4v", action="store_true", help="skip the C4v-scheme comparison")
     ap.add_argument("--no-hotrg", action="store_true", help="skip the HOTRG Z2/plain comparison")
+    ap.add_argument("--hotrg-by-d", action="store_true", help="run only the HOTRG comparison over D at chi 64")
     ap.add_argument("--hotrg-only", type=int, default=0, metavar="CHI",
                     help="run only the HOTRG comparison at this chi and print its JSON")
     ap.add_argument("--serve", type=int, default=24, metavar="N",
@@ -333,6 +379,9 @@ def main():
         sys.exit(2)
     if args.hotrg_only:
         print(json.dumps(hotrg_speedup(chis=(args.hotrg_only,), probe_chi=min(args.hotrg_only, 32))))
+        return
+    if args.hotrg_by_d:
+        print(json.dumps(hotrg_by_d()))
         return
 
     import torch
@@ -392,6 +441,7 @@ def main():
             "achieved_uncorrected": stats["flops"] / stats["seconds"] / 1e12,
             "gemm_share_of_step": stats["seconds"] / tz,
         }
+    out["late_iterations"] = late_iterations(A, args.chi, args.warmup + args.steps, args.steps)
     if not args.no_dense:
         td, dstats, dphases, _ = time_form(A, args.chi, "dense", args.dense_steps, args.warmup, profile=False)
         dense_rate = args.dense_steps / td
@@ -407,6 +457,7 @@ def main():
         out["c4v"] = c4v_scheme(args.D, args.chi, args.steps, args.warmup)
     if not args.no_hotrg:
         out["hotrg"] = hotrg_speedup()
+        out["hotrg"]["by_D"] = hotrg_by_d()
     if args.serve > 0:
         out["serving"] = serving(args.serve, args.serve_rate)
     if not args.no_cpu_baseline:

@@ -18,7 +18,7 @@
  *    at most 1e-10 of their common trace ||M||_F^2).  Kept: min(chi,
  *    #{lambda > cutoff * lambda_max}) over the merged spectrum of both
  *    sectors, ties even first.  In the Z2 form the Gram matrices are block
- *    diagonal and each sector is decomposed on its own: up to 128 rows by
+ *    diagonal and each sector is decomposed on its own: up to 141 rows by
  *    one-sided Jacobi, larger sectors (up to 4096 rows) by subspace iteration
  *    with Rayleigh-Ritz (every third iteration) until the leading chi Ritz
  *    pairs have residuals below 1e-12 of the largest eigenvalue.

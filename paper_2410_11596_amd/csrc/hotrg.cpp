@@ -28,8 +28,8 @@ namespace {
 
 constexpr int kSweeps = 40;
 constexpr int kEigMax = 4096;   // rows of a Gram sector the eigensolver takes
-constexpr int kJacSmall = 128;  // sectors up to this size are decomposed directly (LDS Jacobi)
-constexpr int kSubL = 128;      // largest subspace of the iterative eigensolver (chi + 32 <= 96)
+constexpr int kJacSmall = 141;  // sectors up to this size are decomposed directly (in LDS: n^2 <= 19968)
+constexpr int kSubL = 128;      // largest subspace of the iterative eigensolver (max(chi + 32, 2 chi) <= 128)
 constexpr int kSubMaxIter = 300;
 constexpr double kRitzTol = 1e-12;  // converged: ||G u - lam u|| <= kRitzTol * lam_1 for the leading chi pairs
 constexpr double kRitzAccept = 1e-9;
@@ -531,7 +531,9 @@ void Hotrg::step(int n) {
           J.side = side;
           J.P = P;
           J.n = nn;
-          J.l = std::min(nn, chi_ + 32);
+          // oversampled to twice the kept count: the Ritz pairs converge at
+          // lambda_{l+1} / lambda_chi, slowly on the flat spectra of early steps
+          J.l = std::min(nn, std::max(chi_ + 32, 2 * chi_));
           J.kc = std::min(J.l, chi_);
           J.G = Gp;
           big_at[side][P] = (int)sj.size();
