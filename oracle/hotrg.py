@@ -30,6 +30,14 @@ is silent:
   H5  After k steps the tensor stands for a torus of 2^k sites:
       ln Z / N = ln n_0 + sum_{j=1..k} ln(n_j) / 2^j + ln(Tr T_k) / 2^k,
       Tr T = sum_{u,l} T[u,l,u,l], n_0 the norm of the initial tensor.
+  H7  The energy of a vertical bond: the bond operator h[(s1 s2),(s1' s2')]
+      (site 1 above site 2) is written as sum_k c_k O_k (x) O'_k by the SVD of
+      h reshuffled to [(s1 s1'), (s2 s2')]; each term puts the impurities
+      a[O] = sum_{s s'} O[s,s'] A[s] (x) A[s'] (ket s, bra s') above a[O']
+      in the first step, which joins them into one impurity carried like the
+      probe.  E = sum_k c_k Z_k / Z.  In the Z2 form each O is split into its
+      symmetric (even impurity) and antisymmetric (odd) part; the mixed
+      products are odd and contribute nothing.
   H6  The probe: one tensor of the network is replaced by an impurity (b or
       |b|).  In every step the impurity takes the upper place and a pure
       tensor the lower one, with the pure step's U and n_j, so that
@@ -141,7 +149,7 @@ class Run:
     """HOTRG on the double layer of A (or on a given network tensor a), plain
     or Z2 form; optional impurities (H6) carried along."""
 
-    def __init__(self, chi, form="dense", A=None, a=None, tau=1e-12, probes=False):
+    def __init__(self, chi, form="dense", A=None, a=None, tau=1e-12, probes=False, bond=None):
         if form not in ("dense", "z2"):
             raise ValueError(form)
         self.form, self.chi, self.tau = form, chi, tau
@@ -164,9 +172,36 @@ class Run:
         else:
             self.pv = self.ph = None
             self.tp = [0] * len(imps)
+        # bond energy (H7): pairs (coefficient, upper, lower) of impurities
+        pairs = []
+        if bond is not None:
+            d = A.shape[0]
+            H = np.asarray(bond, dtype=np.float64).reshape(d, d, d, d)  # [s1, s2, s1', s2']
+            Hr = H.transpose(0, 2, 1, 3).reshape(d * d, d * d)       # [(s1 s1'), (s2 s2')]
+            Uh, sh, Vh = np.linalg.svd(Hr)
+            for k in range(len(sh)):
+                if sh[k] <= 1e-14 * sh[0]:
+                    continue
+                O1 = Uh[:, k].reshape(d, d)
+                O2 = Vh[k].reshape(d, d)
+                if form == "z2":
+                    parts = [((O1 + O1.T) / 2, (O2 + O2.T) / 2, 0), ((O1 - O1.T) / 2, (O2 - O2.T) / 2, 1)]
+                else:
+                    parts = [(O1, O2, 0)]
+                for P1, P2, tp in parts:
+                    if not (np.abs(P1).max() > 0 and np.abs(P2).max() > 0):
+                        continue
+                    i1 = np.einsum("st,sabcd,tefgh->aebfcgdh", P1, A, A).reshape(a.shape)
+                    i2 = np.einsum("st,sabcd,tefgh->aebfcgdh", P2, A, A).reshape(a.shape)
+                    if form == "z2":
+                        i1 = _mask_parity(basis.rotate(i1, U), [p] * 4, tp)
+                        i2 = _mask_parity(basis.rotate(i2, U), [p] * 4, tp)
+                    pairs.append((sh[k], i1, i2))
         n0 = np.linalg.norm(a)
         self.T = a / n0
         self.imps = [x / n0 for x in imps]
+        self.pairs = [(c, x / n0, y / n0) for c, x, y in pairs]
+        self.bond_imps = []  # joined pairs after the first step
         self.log_norms = [np.log(n0)]
         self.records = []
         self.steps = 0
@@ -178,15 +213,21 @@ class Run:
             U, side, kept, spec, errs = isometry(M, self.chi, self.tau, self.ph if z2 else None)
             Tn = contract_step(M, U)
             imps = [contract_step(join_vertical(x, self.T), U) for x in self.imps]
+            if self.steps == 0:
+                bimps = [contract_step(join_vertical(x, y), U) for _, x, y in self.pairs]
+            else:
+                bimps = [contract_step(join_vertical(x, self.T), U) for x in self.bond_imps]
             if z2:
                 newp = np.array([0] * kept[0] + [1] * kept[1], dtype=np.int64)
                 Tn = _mask_parity(Tn, [self.pv, newp, self.pv, newp], 0)
                 imps = [_mask_parity(x, [self.pv, newp, self.pv, newp], tp) for x, tp in zip(imps, self.tp)]
+                bimps = [_mask_parity(x, [self.pv, newp, self.pv, newp], 0) for x in bimps]
                 # after the quarter turn the new bond is vertical
                 self.pv, self.ph = newp, self.pv
             nj = np.linalg.norm(Tn)
             self.T = rotate_quarter(Tn / nj)
             self.imps = [rotate_quarter(x / nj) for x in imps]
+            self.bond_imps = [rotate_quarter(x / nj) for x in bimps]
             self.log_norms.append(np.log(nj))
             self.records.append({"kept": kept if z2 else (sum(kept), 0), "side": side, "spectrum": spec,
                                  "discarded": errs})
@@ -207,6 +248,11 @@ class Run:
         """Z_imp / Z for the carried impurities (H6)."""
         t = self.trace()
         return [self.trace(x) / t for x in self.imps]
+
+    def energy(self):
+        """<h> on a vertical bond (H7); needs at least one step."""
+        t = self.trace()
+        return sum(c * self.trace(x) / t for (c, _, _), x in zip(self.pairs, self.bond_imps))
 
     def sym_error(self):
         """|Z_b| / Z_|b| (H6, Sec. III A)."""
