@@ -82,6 +82,22 @@ int hotrg_log_z(hotrg_ctx* c, double* lnz);
  * (any pointer may be NULL).  Synchronises. */
 int hotrg_sym_error(hotrg_ctx* c, double* err, double* z_b, double* z_abs);
 
+/*
+ * Bond energy: h (host, d^2 x d^2 doubles, row-major, h[(s1 s2),(s1' s2')],
+ * site 1 above site 2 on a vertical bond, ket indices s, bra indices s') is
+ * written as sum_{a,b} |a><b| (x) O_ab with O_ab[s2,s2'] = h[(a s2),(b s2')]
+ * (in the Z2 form regrouped into symmetric and antisymmetric pairs, the
+ * mixed ones vanishing); every term puts the impurities
+ * a[O] = sum O[s,s'] A[s] (x) A[s'] on two vertically adjacent sites, joined
+ * in the first step and carried like the probes.  Must be called before the
+ * first step; d <= 4.  A second call replaces the operator.
+ */
+int hotrg_set_bond(hotrg_ctx* c, const double* h);
+
+/* <h> on a vertical bond after at least one step (hotrg_set_bond first).
+ * Synchronises. */
+int hotrg_energy(hotrg_ctx* c, double* e);
+
 /* Number of steps run. */
 int hotrg_num_records(hotrg_ctx* c, int* n);
 

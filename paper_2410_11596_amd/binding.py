@@ -25,7 +25,8 @@ EXPORTS = [
     "ctm_env_epsilon", "ctm_s_err", "ctm_log_kappa", "ctm_num_records", "ctm_record",
     "ctm_sector_dims", "ctm_timing", "ctm_gemm_stats", "ctm_set_precision",
     "ctm_server_create", "ctm_server_submit", "ctm_server_wait", "ctm_server_load", "ctm_server_destroy",
-    "hotrg_opts_default", "hotrg_init", "hotrg_step", "hotrg_log_z", "hotrg_sym_error", "hotrg_num_records",
+    "hotrg_opts_default", "hotrg_init", "hotrg_step", "hotrg_log_z", "hotrg_sym_error", "hotrg_set_bond",
+    "hotrg_energy", "hotrg_num_records",
     "hotrg_record", "hotrg_last_error", "hotrg_free",
     "hctm_dev_gemm", "hctm_dev_gemm_f32", "hctm_dev_gemm_bf16x3", "hctm_dev_copy", "hctm_dev_chol_inv", "hctm_dev_jacobi", "hctm_dev_jacobi_log_doubles",
 ]
@@ -136,6 +137,8 @@ def lib():
         "hotrg_step": ([vp, ctypes.c_int], ctypes.c_int),
         "hotrg_log_z": ([vp, dp], ctypes.c_int),
         "hotrg_sym_error": ([vp, dp, dp, dp], ctypes.c_int),
+        "hotrg_set_bond": ([vp, dp], ctypes.c_int),
+        "hotrg_energy": ([vp, dp], ctypes.c_int),
         "hotrg_num_records": ([vp, ip], ctypes.c_int),
         "hotrg_record": ([vp, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, ip, dp], ctypes.c_int),
         "hotrg_last_error": ([vp], ctypes.c_char_p),
@@ -416,11 +419,12 @@ def _hcheck(code, ctx=None):
 
 class HOTRG:
     """HOTRG on the double layer of A (d, D, D, D, D) on the GPU, Z2 or
-    plain form; probes=True carries the symmetry probes b and |b|.  Work runs
+    plain form; probes=True carries the symmetry probes b and |b|; bond=h
+    (d^2 x d^2) the impurities of the bond energy.  Work runs
     on torch's current HIP stream; the context allocates its own device
     memory."""
 
-    def __init__(self, A, chi, form="z2", svd_rel_cutoff=1e-12, probes=False, stream=None):
+    def __init__(self, A, chi, form="z2", svd_rel_cutoff=1e-12, probes=False, bond=None, stream=None):
         torch = _torch()
         A = np.ascontiguousarray(A, dtype=np.float64)
         if A.ndim != 5:
@@ -438,6 +442,9 @@ class HOTRG:
         ctx = ctypes.c_void_p()
         _hcheck(lib().hotrg_init(ctypes.byref(ctx), _dptr(A), self.d, self.D, self.chi, ctypes.byref(o)))
         self._ctx = ctx
+        if bond is not None:
+            h = np.ascontiguousarray(bond, dtype=np.float64).reshape(self.d ** 2, self.d ** 2)
+            _hcheck(lib().hotrg_set_bond(self._ctx, _dptr(h)), self._ctx)
 
     def close(self):
         if getattr(self, "_ctx", None):
@@ -463,6 +470,12 @@ class HOTRG:
     def log_z(self):
         v = ctypes.c_double()
         _hcheck(lib().hotrg_log_z(self._ctx, ctypes.byref(v)), self._ctx)
+        return v.value
+
+    def energy(self):
+        """<h> on a vertical bond (the operator given as bond=)."""
+        v = ctypes.c_double()
+        _hcheck(lib().hotrg_energy(self._ctx, ctypes.byref(v)), self._ctx)
         return v.value
 
     def impurity_ratios(self):

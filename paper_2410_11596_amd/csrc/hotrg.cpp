@@ -38,7 +38,8 @@ constexpr double kRitzAccept = 1e-9;
 struct EigJob {
   int side = 0, P = 0, n = 0, l = 0, kc = 0, slot = 0;
   const double* G = nullptr;  // n x n, ld n
-  std::vector<double> lam;    // Ritz values, descending (host)
+  double shift = 0.0;         // the iteration runs on G + shift I (rank-deficient G near a fixed point)
+  std::vector<double> lam;    // Ritz values of G, descending (host)
 };
 
 struct StepRecord {
@@ -54,6 +55,8 @@ class Hotrg {
   void step(int n);
   double log_z();
   void impurity_ratios(double* zb, double* zab);
+  void set_bond(const double* h_host);
+  double energy();
   const std::vector<StepRecord>& records() const { return rec_; }
 
  private:
@@ -64,7 +67,8 @@ class Hotrg {
   void gram(int side);
   void orth(std::vector<EigJob*>& js, bool from_y);
   void eig_subspace(std::vector<EigJob>& jobs, uint64_t salt);
-  void coarse(const BT& upper, BT& out);
+  void coarse(const BT& upper, const BT& lower, BT& out);
+  void impurity(const double* O, int tp, BT& out);
   double trace(const BT& t);
   void sync() { HCTM_HIP(hipStreamSynchronize(st_)); }
 
@@ -99,6 +103,12 @@ class Hotrg {
   double* host_ = nullptr;  // pinned: spectra, infos, scalars
   std::vector<double> log_norms_;
   std::vector<StepRecord> rec_;
+  // bond energy: pairs of impurities (upper, lower), joined in the first step
+  struct BondTerm {
+    BT up, lo;
+  };
+  std::vector<BondTerm> bond_;
+  void* bond_mem_ = nullptr;
 };
 
 Hotrg::Hotrg(const double* A, int d, int D, int chi, int form, double tau, int probes, hipStream_t st)
@@ -129,6 +139,7 @@ Hotrg::Hotrg(const double* A, int d, int D, int chi, int form, double tau, int p
 
 Hotrg::~Hotrg() {
   if (st_) (void)hipStreamSynchronize(st_);
+  if (bond_mem_) (void)hipFree(bond_mem_);
   if (host_) (void)hipHostFree(host_);
   if (mem_) (void)hipFree(mem_);
   if (own_stream_ && st_) (void)hipStreamDestroy(st_);
@@ -365,11 +376,14 @@ void Hotrg::orth(std::vector<EigJob*>& js, bool from_y) {
 }
 
 // Leading eigenpairs of Gram sectors too large for a direct decomposition:
-// subspace iteration Y = G Q, Q = orth(Y), and every third iteration a
-// Rayleigh-Ritz step (B = Q^T G Q, Jacobi on B, U = Q V) whose residuals
-// ||G u - lam u|| over the leading kc pairs decide convergence.  The result
-// of job J is in its slot: Ritz vectors Uf (n x l, by decreasing value) and
-// J.lam on the host.
+// subspace iteration Y = (G + shift I) Q, Q = orth(Y), and every third
+// iteration a Rayleigh-Ritz step (B = Q^T Y, Jacobi on B, U = Q V) whose
+// residuals ||G u - lam u|| over the leading kc pairs decide convergence.
+// The shift (1e-14 of the trace) keeps Y of full rank when G is rank
+// deficient (near a fixed point), which CholeskyQR needs; it moves no
+// eigenvector and is taken off the Ritz values.  The result of job J is in
+// its slot: Ritz vectors Uf (n x l, by decreasing value) and J.lam on the
+// host.
 void Hotrg::eig_subspace(std::vector<EigJob>& jobs, uint64_t salt) {
   if (jobs.empty()) return;
   std::vector<EigJob*> act;
@@ -384,7 +398,8 @@ void Hotrg::eig_subspace(std::vector<EigJob>& jobs, uint64_t salt) {
     std::vector<GemmDesc> g;
     for (EigJob* J : act) {
       Slot& z = slot_[J->slot];
-      GemmDesc d{};  // Y = G Q
+      HCTM_HIP(hipMemcpyAsync(z.Y, z.Q, sizeof(double) * J->n * J->l, hipMemcpyDeviceToDevice, st_));
+      GemmDesc d{};  // Y = (G + shift I) Q
       d.A = J->G;
       d.B = z.Q;
       d.C = z.Y;
@@ -395,6 +410,7 @@ void Hotrg::eig_subspace(std::vector<EigJob>& jobs, uint64_t salt) {
       d.ldb = J->l;
       d.ldc = J->l;
       d.alpha = 1.0;
+      d.beta = J->shift;
       g.push_back(d);
     }
     gemm(g, st_, gscratch_, gscratch_cap_);
@@ -478,6 +494,7 @@ void Hotrg::eig_subspace(std::vector<EigJob>& jobs, uint64_t salt) {
         const bool last = t == kSubMaxIter - 1;
         if (rmax <= kRitzTol * lam1 || (last && rmax <= kRitzAccept * lam1)) {
           J->lam.assign(h, h + J->l);
+          for (double& v : J->lam) v = std::max(0.0, v - J->shift);
         } else if (last) {
           throw Error(4, "HOTRG: the subspace iteration did not converge");
         } else {
@@ -491,13 +508,13 @@ void Hotrg::eig_subspace(std::vector<EigJob>& jobs, uint64_t salt) {
   }
 }
 
-// out[u,x,d,y] = sum U[(l1 l2),x] upper[u,l1,m,r1] T[m,l2,d,r2] U[(r1 r2),y]
-void Hotrg::coarse(const BT& upper, BT& out) {
+// out[u,x,d,y] = sum U[(l1 l2),x] upper[u,l1,m,r1] lower[m,l2,d,r2] U[(r1 r2),y]
+void Hotrg::coarse(const BT& upper, const BT& lower, BT& out) {
   permute(upper, s1_, {0, 2, 3, 1}, 3);  // [u m r1 | l1]
   permute(U_, s2_, {0, 1, 2}, 1);        // [l1 | l2 x]
   contract(s1_, s2_, big1_);             // [u m r1 | l2 x]
   permute(big1_, big2_, {0, 2, 4, 1, 3}, 3);  // [u r1 x | m l2]
-  contract(big2_, T_, big1_);            // [u r1 x | d r2]
+  contract(big2_, lower, big1_);         // [u r1 x | d r2]
   permute(big1_, big2_, {0, 2, 3, 1, 4}, 3);  // [u x d | r1 r2]
   contract(big2_, U_, out);              // [u x d | y]
 }
@@ -561,6 +578,11 @@ void Hotrg::step(int n) {
         jp.push_back(p);
       }
     jacobi(jp, st_);
+    if (!sj.empty()) {
+      HCTM_HIP(hipMemcpyAsync(host_ + 4100, misc_ + 16, sizeof(double) * 4, hipMemcpyDeviceToHost, st_));
+      sync();
+      for (EigJob& J : sj) J.shift = 1e-14 * std::max(0.0, host_[4100 + J.side * 2 + J.P]);
+    }
     eig_subspace(sj, (uint64_t)rec_.size());
     for (int side = 0; side < 2; ++side)
       for (int P = 0; P < 2; ++P)
@@ -665,12 +687,18 @@ void Hotrg::step(int n) {
     }
     // the pure tensor, then the impurities (above a pure one), all divided
     // by the pure tensor's norm and turned a quarter
-    coarse(T_, R_);
+    coarse(T_, T_, R_);
     norm2(R_.p, (size_t)R_.L.size, misc_, part_, st_);
     for (int w = 0; w < nimp_; ++w) {
-      coarse(imp_[w], s3_);
+      coarse(imp_[w], T_, s3_);
       scale_inv(s3_.p, (size_t)s3_.L.size, misc_, st_);
       permute(s3_, imp_[w], {3, 0, 1, 2}, 2);
+    }
+    // bond terms: the pair joined in the first step, then above a pure tensor
+    for (BondTerm& b : bond_) {
+      coarse(b.up, rec_.empty() ? b.lo : T_, s3_);
+      scale_inv(s3_.p, (size_t)s3_.L.size, misc_, st_);
+      permute(s3_, b.up, {3, 0, 1, 2}, 2);
     }
     scale_inv(R_.p, (size_t)R_.L.size, misc_, st_);
     permute(R_, T_, {3, 0, 1, 2}, 2);
@@ -681,6 +709,125 @@ void Hotrg::step(int n) {
     log_norms_.push_back(std::log(nj));
     rec_.push_back(std::move(rec));
   }
+}
+
+// a[O] = sum_{s s'} O[s,s'] A[s] (x) A[s'] (ket s, bra s') in the tensor's
+// basis, packed with total parity tp and divided by the initial norm n_0
+void Hotrg::impurity(const double* O, int tp, BT& out) {
+  const int q = q_;
+  DLArgs g;
+  g.A = Ad_;
+  g.out = plain_;
+  g.tab_idx = tab_idx_;
+  g.tab_c = tab_c_;
+  g.d = d_;
+  g.D = D_;
+  g.npairs = 0;
+  for (int s = 0; s < d_; ++s)
+    for (int t = 0; t < d_; ++t)
+      if (O[s * d_ + t] != 0.0) {
+        if (g.npairs == kMaxPairs) throw Error(1, "HOTRG: too many operator entries");
+        g.ket[g.npairs] = s;
+        g.bra[g.npairs] = t;
+        g.w[g.npairs] = O[s * d_ + t];
+        ++g.npairs;
+      }
+  if (g.npairs == 0) throw Error(1, "HOTRG: empty impurity operator");
+  double_layer_basis(g, st_);
+  const long long str[4] = {(long long)q * q * q, (long long)q * q, (long long)q, 1};
+  out.L = Layout({lq_, lq_, lq_, lq_}, 2, tp);
+  std::vector<CopyJob> jobs;
+  plan_pack(plain_, str, out, true, jobs);
+  copy_jobs(jobs, st_);
+  host_[4400] = std::exp(log_norms_[0]);
+  HCTM_HIP(hipMemcpyAsync(misc_ + 32, host_ + 4400, sizeof(double), hipMemcpyHostToDevice, st_));
+  scale_inv(out.p, (size_t)out.L.size, misc_ + 32, st_);
+  sync();  // plain_ and the pinned scalar are reused by the next impurity
+}
+
+// h[(s1 s2),(s1' s2')] on a vertical bond, site 1 above site 2:
+// h = sum_{a b} E_ab (x) O_ab with E_ab the matrix unit |a><b| and
+// O_ab[s2, s2'] = h[(a s2),(b s2')].  In the Z2 form E_ab + E_ba (a <= b) is
+// paired with the symmetric part of O_ab + O_ba, E_ab - E_ba (a < b) with
+// the antisymmetric part of O_ab - O_ba (mixed parities contribute nothing).
+void Hotrg::set_bond(const double* h) {
+  if (!rec_.empty()) throw Error(1, "HOTRG: the bond operator must be set before the first step");
+  if (d_ > 4) throw Error(1, "HOTRG: the bond energy needs d <= 4");
+  const int d = d_;
+  auto H = [&](int s1, int s2, int t1, int t2) { return h[(s1 * d + s2) * (d * d) + t1 * d + t2]; };
+  struct Term {
+    std::vector<double> up, lo;
+    int tp;
+  };
+  std::vector<Term> terms;
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      if (form_ == 0 && b < a) continue;
+      for (int anti = 0; anti < (form_ == 0 ? 2 : 1); ++anti) {
+        if (anti && a == b) continue;
+        Term t;
+        t.tp = anti;
+        t.up.assign((size_t)d * d, 0.0);
+        t.lo.assign((size_t)d * d, 0.0);
+        bool any = false;
+        if (form_ != 0) {
+          t.up[(size_t)a * d + b] = 1.0;
+          for (int s = 0; s < d; ++s)
+            for (int u = 0; u < d; ++u) {
+              t.lo[(size_t)s * d + u] = H(a, s, b, u);
+              any = any || t.lo[(size_t)s * d + u] != 0.0;
+            }
+        } else {
+          const double sg = anti ? -1.0 : 1.0;
+          t.up[(size_t)a * d + b] += 1.0;
+          t.up[(size_t)b * d + a] += sg;
+          if (a == b) t.up[(size_t)a * d + a] = 1.0;
+          // lower: (O_ab + sg O_ba) / 2 (O_aa for a = b), then its
+          // (anti)symmetric part
+          std::vector<double> o((size_t)d * d);
+          for (int s = 0; s < d; ++s)
+            for (int u = 0; u < d; ++u) o[(size_t)s * d + u] = 0.5 * (H(a, s, b, u) + sg * H(b, s, a, u));
+          for (int s = 0; s < d; ++s)
+            for (int u = 0; u < d; ++u) {
+              t.lo[(size_t)s * d + u] = 0.5 * (o[(size_t)s * d + u] + sg * o[(size_t)u * d + s]);
+              any = any || t.lo[(size_t)s * d + u] != 0.0;
+            }
+        }
+        if (any) terms.push_back(std::move(t));
+      }
+    }
+  if (bond_mem_) {
+    HCTM_HIP(hipStreamSynchronize(st_));
+    HCTM_HIP(hipFree(bond_mem_));
+    bond_mem_ = nullptr;
+  }
+  bond_.clear();
+  if (terms.empty()) return;
+  const long long C4 = (long long)C_ * C_ * C_ * C_;
+  if (hipMalloc(&bond_mem_, sizeof(double) * C4 * 2 * terms.size()) != hipSuccess) {
+    bond_mem_ = nullptr;
+    throw Error(2, "hipMalloc of the bond impurities failed");
+  }
+  double* base = static_cast<double*>(bond_mem_);
+  bond_.resize(terms.size());
+  for (size_t i = 0; i < terms.size(); ++i) {
+    BondTerm& b = bond_[i];
+    b.up.p = base + C4 * (2 * i);
+    b.up.capacity = C4;
+    b.lo.p = base + C4 * (2 * i + 1);
+    b.lo.capacity = C4;
+    impurity(terms[i].up.data(), terms[i].tp, b.up);
+    impurity(terms[i].lo.data(), terms[i].tp, b.lo);
+  }
+}
+
+double Hotrg::energy() {
+  if (bond_.empty()) throw Error(1, "HOTRG: no bond operator (hotrg_set_bond)");
+  if (rec_.empty()) throw Error(1, "HOTRG: the bond energy needs at least one step");
+  const double tr = trace(T_);
+  double e = 0.0;
+  for (BondTerm& b : bond_) e += trace(b.up);
+  return e / tr;
 }
 
 // sum T[u,l,u,l]: the trace of the block matrix [u l | d r]; zero for a
@@ -818,6 +965,22 @@ int hotrg_sym_error(hotrg_ctx* c, double* err, double* z_b, double* z_abs) {
     if (z_b) *z_b = zb;
     if (z_abs) *z_abs = zab;
     if (err) *err = std::fabs(zb) / std::fabs(zab);
+  });
+}
+
+int hotrg_set_bond(hotrg_ctx* c, const double* h) {
+  if (!c) return CTM_E_ARG;
+  return hguarded(c, [&] {
+    if (!h) throw hctm::Error(CTM_E_ARG, "h is NULL");
+    c->h->set_bond(h);
+  });
+}
+
+int hotrg_energy(hotrg_ctx* c, double* e) {
+  if (!c) return CTM_E_ARG;
+  return hguarded(c, [&] {
+    if (!e) throw hctm::Error(CTM_E_ARG, "e is NULL");
+    *e = c->h->energy();
   });
 }
 

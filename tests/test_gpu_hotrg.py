@@ -150,3 +150,30 @@ def test_degenerate_sizes(form):
     g = _gpu(P, 8, form, 5, probes=True)
     assert abs(g.log_z() - np.log(v @ v)) < 1e-13
     assert all(sum(r["kept"]) == 1 for r in g.records())
+
+
+@pytest.mark.parametrize("form", ["z2", "dense"])
+def test_bond_energy_against_oracle(form):
+    h = inputs.heisenberg_bond_matrix()
+    A = inputs.iid_tensor(2, 2, 6)
+    o = hotrg.Run(16, form, A=A, tau=0.0, bond=h).step(2)
+    g = _gpu(A, 16, form, 2, svd_rel_cutoff=0.0, bond=h)
+    assert abs(g.energy() - o.energy()) < 1e-13  # untruncated: the 2 x 2 torus
+    A = inputs.iid_tensor(2, 3, 8)
+    o = hotrg.Run(12, form, A=A, bond=h).step(6)
+    g = _gpu(A, 12, form, 6, bond=h)
+    _compare(g, o)
+    assert abs(g.energy() - o.energy()) < 1e-10
+
+
+def test_ising_correlation_and_plain_z2_energy_difference():
+    zz = np.kron(np.diag([1.0, -1.0]), np.diag([1.0, -1.0]))
+    from test_oracle_pins import ising_nn_corr
+
+    g = _gpu(inputs.ising_peps(0.3), 10, "z2", 20, bond=zz)
+    assert abs(g.energy() - ising_nn_corr(0.3)) < 5e-6
+    h = inputs.heisenberg_bond_matrix()
+    A = inputs.iid_tensor(2, 2, 7)
+    z = _gpu(A, 32, "z2", 10, bond=h)
+    p = _gpu(A, 32, "dense", 10, bond=h)
+    assert abs(z.energy() - p.energy()) < 1e-9
