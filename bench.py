@@ -222,8 +222,8 @@ def c4v_scheme(D, chi, steps, warmup, tol=1e-10, max_iter=200):
 def hotrg_speedup(chis=(32, 48, 64), D=2, steps=4, warmup=6, probe_chi=32):
     """HOTRG (include/hctm_hotrg.h): time per step of the Z2 and the plain
     form once the bonds have reached chi, and their ratio, for several chi
-    (Fig. 4(c) of the paper); the symmetry error of both forms with the probe
-    b at probe_chi."""
+    (Fig. 4(c) of the paper); at probe_chi the symmetry error of both forms
+    with the probe b and their Heisenberg bond energies (Fig. 3)."""
     import torch
 
     from paper_2410_11596_amd import HOTRG, inputs
@@ -246,12 +246,15 @@ def hotrg_speedup(chis=(32, 48, 64), D=2, steps=4, warmup=6, probe_chi=32):
             h.close()
         res[form + "_ms_per_step"] = ms
         res[form + "_kept_last"] = kept
-        p = HOTRG(A, probe_chi, form=form, probes=True)
+        p = HOTRG(A, probe_chi, form=form, probes=True, bond=inputs.heisenberg_bond_matrix())
         p.step(warmup + steps)
         res[form + "_sym_error_chi%d" % probe_chi] = p.sym_error()
         res[form + "_log_z_chi%d" % probe_chi] = p.log_z()
+        res[form + "_energy_chi%d" % probe_chi] = p.energy()
         p.close()
     res["z2_over_dense"] = [d / z for d, z in zip(res["dense_ms_per_step"], res["z2_ms_per_step"])]
+    res["abs_energy_difference_chi%d" % probe_chi] = abs(res["z2_energy_chi%d" % probe_chi] -
+                                                          res["dense_energy_chi%d" % probe_chi])
     return res
 
 
