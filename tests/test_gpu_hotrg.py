@@ -177,3 +177,30 @@ def test_ising_correlation_and_plain_z2_energy_difference():
     z = _gpu(A, 32, "z2", 10, bond=h)
     p = _gpu(A, 32, "dense", 10, bond=h)
     assert abs(z.energy() - p.energy()) < 1e-9
+
+
+def test_api_misuse_is_an_argument_error_and_leaves_the_context_usable():
+    from paper_2410_11596_amd import HctmError, binding
+
+    h = inputs.heisenberg_bond_matrix()
+    A = inputs.iid_tensor(2, 2, 3)
+    g = _gpu(A, 8, "z2", 0)
+    with pytest.raises(HctmError) as e:
+        g.energy()  # no bond operator
+    assert e.value.code == binding.CTM_E_ARG
+    with pytest.raises(HctmError) as e:
+        g.sym_error()  # no probes
+    assert e.value.code == binding.CTM_E_ARG
+    g2 = _gpu(A, 8, "z2", 0, bond=h)
+    with pytest.raises(HctmError):
+        g2.energy()  # no step yet
+    g2.step(2)
+    e2 = g2.energy()
+    with pytest.raises(HctmError) as e:
+        binding._hcheck(binding.lib().hotrg_set_bond(g2._ctx, binding._dptr(np.ascontiguousarray(h))), g2._ctx)
+    assert e.value.code == binding.CTM_E_ARG  # after the first step
+    g2.step(1)  # still usable
+    assert np.isfinite(g2.energy()) and np.isfinite(e2)
+    A5 = inputs.iid_tensor(5, 2, 1)
+    with pytest.raises(HctmError):
+        _gpu(A5, 8, "z2", 0, bond=np.eye(25))  # d > 4
