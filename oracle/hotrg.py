@@ -38,6 +38,10 @@ is silent:
       probe.  E = sum_k c_k Z_k / Z.  In the Z2 form each O is split into its
       symmetric (even impurity) and antisymmetric (odd) part; the mixed
       products are odd and contribute nothing.
+  H8  The one-site RDM: rho[s,s'] = Z[a(E_ss')] / Z with E_ss' = |s><s'|, each
+      impurity carried like the probe; in the Z2 form only the symmetric
+      parts (E_ss' + E_s's)/2 are even, so rho is symmetric by construction.
+      Divided by its trace.
   H6  The probe: one tensor of the network is replaced by an impurity (b or
       |b|).  In every step the impurity takes the upper place and a pure
       tensor the lower one, with the pure step's U and n_j, so that
@@ -149,7 +153,7 @@ class Run:
     """HOTRG on the double layer of A (or on a given network tensor a), plain
     or Z2 form; optional impurities (H6) carried along."""
 
-    def __init__(self, chi, form="dense", A=None, a=None, tau=1e-12, probes=False, bond=None):
+    def __init__(self, chi, form="dense", A=None, a=None, tau=1e-12, probes=False, bond=None, rdm1=False):
         if form not in ("dense", "z2"):
             raise ValueError(form)
         self.form, self.chi, self.tau = form, chi, tau
@@ -197,6 +201,25 @@ class Run:
                         i1 = _mask_parity(basis.rotate(i1, U), [p] * 4, tp)
                         i2 = _mask_parity(basis.rotate(i2, U), [p] * 4, tp)
                     pairs.append((sh[k], i1, i2))
+        # one-site RDM (H8): impurities of E_ss' (plain) or of the symmetric
+        # parts (Z2, s <= s'), with their places in rho
+        self.rdm_places = []
+        if rdm1:
+            d = A.shape[0]
+            for s1 in range(d):
+                for s2 in range(d):
+                    if form == "z2" and s2 < s1:
+                        continue
+                    E = np.zeros((d, d))
+                    E[s1, s2] = 1.0
+                    if form == "z2":
+                        E = 0.5 * (E + E.T)
+                    x = np.einsum("st,sabcd,tefgh->aebfcgdh", E, A, A).reshape(a.shape)
+                    if form == "z2":
+                        x = _mask_parity(basis.rotate(x, U), [p] * 4, 0)
+                    imps.append(x)
+                    self.tp.append(0)
+                    self.rdm_places.append((s1, s2))
         n0 = np.linalg.norm(a)
         self.T = a / n0
         self.imps = [x / n0 for x in imps]
@@ -256,5 +279,16 @@ class Run:
 
     def sym_error(self):
         """|Z_b| / Z_|b| (H6, Sec. III A)."""
-        rb, rab = self.impurity_ratios()
+        rb, rab = self.impurity_ratios()[:2]
         return abs(rb) / abs(rab)
+
+    def rho1(self):
+        """One-site RDM (H8), trace one."""
+        ratios = self.impurity_ratios()[len(self.imps) - len(self.rdm_places):]
+        d = 1 + max(max(pl) for pl in self.rdm_places)
+        rho = np.zeros((d, d))
+        for (s1, s2), r in zip(self.rdm_places, ratios):
+            rho[s1, s2] = r
+            if self.form == "z2":
+                rho[s2, s1] = r
+        return rho / np.trace(rho)

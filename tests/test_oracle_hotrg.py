@@ -159,3 +159,25 @@ def test_bond_energy_forms_agree():
     z = hotrg.Run(12, "z2", A=A, bond=heis()).step(6)
     p = hotrg.Run(12, "dense", A=A, bond=heis()).step(6)
     assert abs(z.energy() - p.energy()) < 1e-10
+
+
+@pytest.mark.parametrize("form", ["dense", "z2"])
+def test_rho1_untruncated_is_the_torus_rdm(form):
+    A = inputs.iid_tensor(3, 2, 9)
+    a = basis.double_layer(A)
+    z = torus_2x2(a, a, a, a)
+    exact = np.array([[torus_2x2(basis.impurity(A, s, t), a, a, a) / z for t in range(3)] for s in range(3)])
+    r = hotrg.Run(form=form, A=A, rdm1=True, **EXACT).step(2)
+    assert np.abs(r.rho1() - exact).max() < 1e-13
+
+
+def test_rho1_symmetric_in_z2_and_forms_agree():
+    A = inputs.iid_tensor(2, 3, 4)
+    z = hotrg.Run(10, "z2", A=A, rdm1=True).step(6)
+    p = hotrg.Run(10, "dense", A=A, rdm1=True).step(6)
+    rz, rp = z.rho1(), p.rho1()
+    assert np.array_equal(rz, rz.T) and abs(np.trace(rz) - 1.0) < 1e-14
+    assert np.abs(rz - rp).max() < 1e-10
+    v = np.array([0.6, -0.8])
+    r = hotrg.Run(8, "z2", A=inputs.product_state(v, 2), rdm1=True).step(4).rho1()
+    assert np.abs(r - np.outer(v, v)).max() < 1e-14
