@@ -98,6 +98,17 @@ int hotrg_set_bond(hotrg_ctx* c, const double* h);
  * Synchronises. */
 int hotrg_energy(hotrg_ctx* c, double* e);
 
+/*
+ * One-site RDM: carries the impurities a[|s><s'|] (in the Z2 form only the
+ * symmetric parts (|s><s'| + |s'><s|)/2, s <= s', whose double layers are
+ * even: the RDM is symmetric by construction).  Must be called before the
+ * first step; d <= 4.
+ */
+int hotrg_track_rdm1(hotrg_ctx* c);
+
+/* rho[s][s'] (host, d*d), trace one, after hotrg_track_rdm1.  Synchronises. */
+int hotrg_rdm1(hotrg_ctx* c, double* rho);
+
 /* Number of steps run. */
 int hotrg_num_records(hotrg_ctx* c, int* n);
 

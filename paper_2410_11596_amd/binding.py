@@ -26,7 +26,7 @@ EXPORTS = [
     "ctm_sector_dims", "ctm_timing", "ctm_gemm_stats", "ctm_set_precision",
     "ctm_server_create", "ctm_server_submit", "ctm_server_wait", "ctm_server_load", "ctm_server_destroy",
     "hotrg_opts_default", "hotrg_init", "hotrg_step", "hotrg_log_z", "hotrg_sym_error", "hotrg_set_bond",
-    "hotrg_energy", "hotrg_num_records",
+    "hotrg_energy", "hotrg_track_rdm1", "hotrg_rdm1", "hotrg_num_records",
     "hotrg_record", "hotrg_last_error", "hotrg_free",
     "hctm_dev_gemm", "hctm_dev_gemm_f32", "hctm_dev_gemm_bf16x3", "hctm_dev_copy", "hctm_dev_chol_inv", "hctm_dev_jacobi", "hctm_dev_jacobi_log_doubles",
 ]
@@ -139,6 +139,8 @@ def lib():
         "hotrg_sym_error": ([vp, dp, dp, dp], ctypes.c_int),
         "hotrg_set_bond": ([vp, dp], ctypes.c_int),
         "hotrg_energy": ([vp, dp], ctypes.c_int),
+        "hotrg_track_rdm1": ([vp], ctypes.c_int),
+        "hotrg_rdm1": ([vp, dp], ctypes.c_int),
         "hotrg_num_records": ([vp, ip], ctypes.c_int),
         "hotrg_record": ([vp, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, ip, dp], ctypes.c_int),
         "hotrg_last_error": ([vp], ctypes.c_char_p),
@@ -420,11 +422,13 @@ def _hcheck(code, ctx=None):
 class HOTRG:
     """HOTRG on the double layer of A (d, D, D, D, D) on the GPU, Z2 or
     plain form; probes=True carries the symmetry probes b and |b|; bond=h
-    (d^2 x d^2) the impurities of the bond energy.  Work runs
+    (d^2 x d^2) the impurities of the bond energy; rdm1=True those of the
+    one-site RDM.  Work runs
     on torch's current HIP stream; the context allocates its own device
     memory."""
 
-    def __init__(self, A, chi, form="z2", svd_rel_cutoff=1e-12, probes=False, bond=None, stream=None):
+    def __init__(self, A, chi, form="z2", svd_rel_cutoff=1e-12, probes=False, bond=None, rdm1=False,
+                 stream=None):
         torch = _torch()
         A = np.ascontiguousarray(A, dtype=np.float64)
         if A.ndim != 5:
@@ -445,6 +449,8 @@ class HOTRG:
         if bond is not None:
             h = np.ascontiguousarray(bond, dtype=np.float64).reshape(self.d ** 2, self.d ** 2)
             _hcheck(lib().hotrg_set_bond(self._ctx, _dptr(h)), self._ctx)
+        if rdm1:
+            _hcheck(lib().hotrg_track_rdm1(self._ctx), self._ctx)
 
     def close(self):
         if getattr(self, "_ctx", None):
@@ -471,6 +477,12 @@ class HOTRG:
         v = ctypes.c_double()
         _hcheck(lib().hotrg_log_z(self._ctx, ctypes.byref(v)), self._ctx)
         return v.value
+
+    def rho1(self):
+        """One-site RDM (needs rdm1=True), trace one."""
+        rho = np.zeros((self.d, self.d))
+        _hcheck(lib().hotrg_rdm1(self._ctx, _dptr(rho)), self._ctx)
+        return rho
 
     def energy(self):
         """<h> on a vertical bond (the operator given as bond=)."""

@@ -57,6 +57,8 @@ class Hotrg {
   void impurity_ratios(double* zb, double* zab);
   void set_bond(const double* h_host);
   double energy();
+  void track_rdm1();
+  void rdm1(double* rho);
   const std::vector<StepRecord>& records() const { return rec_; }
 
  private:
@@ -109,6 +111,10 @@ class Hotrg {
   };
   std::vector<BondTerm> bond_;
   void* bond_mem_ = nullptr;
+  // one-site RDM: impurities of |s><s'| (Z2: symmetric parts, s <= s')
+  std::vector<BT> rdm_;
+  std::vector<std::pair<int, int>> rdm_places_;
+  void* rdm_mem_ = nullptr;
 };
 
 Hotrg::Hotrg(const double* A, int d, int D, int chi, int form, double tau, int probes, hipStream_t st)
@@ -140,6 +146,7 @@ Hotrg::Hotrg(const double* A, int d, int D, int chi, int form, double tau, int p
 Hotrg::~Hotrg() {
   if (st_) (void)hipStreamSynchronize(st_);
   if (bond_mem_) (void)hipFree(bond_mem_);
+  if (rdm_mem_) (void)hipFree(rdm_mem_);
   if (host_) (void)hipHostFree(host_);
   if (mem_) (void)hipFree(mem_);
   if (own_stream_ && st_) (void)hipStreamDestroy(st_);
@@ -694,6 +701,11 @@ void Hotrg::step(int n) {
       scale_inv(s3_.p, (size_t)s3_.L.size, misc_, st_);
       permute(s3_, imp_[w], {3, 0, 1, 2}, 2);
     }
+    for (BT& x : rdm_) {
+      coarse(x, T_, s3_);
+      scale_inv(s3_.p, (size_t)s3_.L.size, misc_, st_);
+      permute(s3_, x, {3, 0, 1, 2}, 2);
+    }
     // bond terms: the pair joined in the first step, then above a pure tensor
     for (BondTerm& b : bond_) {
       coarse(b.up, rec_.empty() ? b.lo : T_, s3_);
@@ -819,6 +831,55 @@ void Hotrg::set_bond(const double* h) {
     impurity(terms[i].up.data(), terms[i].tp, b.up);
     impurity(terms[i].lo.data(), terms[i].tp, b.lo);
   }
+}
+
+void Hotrg::track_rdm1() {
+  if (!rec_.empty()) throw Error(1, "HOTRG: the RDM must be requested before the first step");
+  if (d_ > 4) throw Error(1, "HOTRG: the RDM needs d <= 4");
+  if (!rdm_.empty()) return;
+  const int d = d_;
+  std::vector<std::pair<int, int>> places;
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b)
+      if (form_ != 0 || a <= b) places.emplace_back(a, b);
+  const long long C4 = (long long)C_ * C_ * C_ * C_;
+  if (hipMalloc(&rdm_mem_, sizeof(double) * C4 * places.size()) != hipSuccess) {
+    rdm_mem_ = nullptr;
+    throw Error(2, "hipMalloc of the RDM impurities failed");
+  }
+  rdm_.resize(places.size());
+  std::vector<double> O((size_t)d * d);
+  for (size_t i = 0; i < places.size(); ++i) {
+    std::fill(O.begin(), O.end(), 0.0);
+    const int a = places[i].first, b = places[i].second;
+    if (form_ == 0) {
+      O[(size_t)a * d + b] += 0.5;
+      O[(size_t)b * d + a] += 0.5;
+    } else {
+      O[(size_t)a * d + b] = 1.0;
+    }
+    rdm_[i].p = static_cast<double*>(rdm_mem_) + C4 * i;
+    rdm_[i].capacity = C4;
+    impurity(O.data(), 0, rdm_[i]);
+  }
+  rdm_places_ = places;
+}
+
+// rho[s,s'] = Z[a(|s><s'|)] / Z, mirrored in the Z2 form, trace one
+void Hotrg::rdm1(double* rho) {
+  if (rdm_.empty()) throw Error(1, "HOTRG: the RDM was not requested (hotrg_track_rdm1)");
+  const int d = d_;
+  std::vector<double> r((size_t)d * d, 0.0);
+  for (size_t i = 0; i < rdm_.size(); ++i) {
+    const int a = rdm_places_[i].first, b = rdm_places_[i].second;
+    const double v = trace(rdm_[i]);
+    r[(size_t)a * d + b] = v;
+    if (form_ == 0) r[(size_t)b * d + a] = v;
+  }
+  double tr = 0.0;
+  for (int s = 0; s < d; ++s) tr += r[(size_t)s * d + s];
+  if (!(std::fabs(tr) > 0.0)) throw Error(4, "HOTRG: the RDM has zero trace");
+  for (int e = 0; e < d * d; ++e) rho[e] = r[(size_t)e] / tr;
 }
 
 double Hotrg::energy() {
@@ -981,6 +1042,19 @@ int hotrg_energy(hotrg_ctx* c, double* e) {
   return hguarded(c, [&] {
     if (!e) throw hctm::Error(CTM_E_ARG, "e is NULL");
     *e = c->h->energy();
+  });
+}
+
+int hotrg_track_rdm1(hotrg_ctx* c) {
+  if (!c) return CTM_E_ARG;
+  return hguarded(c, [&] { c->h->track_rdm1(); });
+}
+
+int hotrg_rdm1(hotrg_ctx* c, double* rho) {
+  if (!c) return CTM_E_ARG;
+  return hguarded(c, [&] {
+    if (!rho) throw hctm::Error(CTM_E_ARG, "rho is NULL");
+    c->h->rdm1(rho);
   });
 }
 

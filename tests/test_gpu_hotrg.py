@@ -204,3 +204,21 @@ def test_api_misuse_is_an_argument_error_and_leaves_the_context_usable():
     A5 = inputs.iid_tensor(5, 2, 1)
     with pytest.raises(HctmError):
         _gpu(A5, 8, "z2", 0, bond=np.eye(25))  # d > 4
+
+
+@pytest.mark.parametrize("form", ["z2", "dense"])
+def test_rho1_against_oracle(form):
+    A = inputs.iid_tensor(3, 2, 9)
+    o = hotrg.Run(16, form, A=A, tau=0.0, rdm1=True).step(2)
+    g = _gpu(A, 16, form, 2, svd_rel_cutoff=0.0, rdm1=True)
+    assert np.abs(g.rho1() - o.rho1()).max() < 1e-13  # untruncated: the 2 x 2 torus
+    A = inputs.iid_tensor(2, 3, 4)
+    o = hotrg.Run(10, form, A=A, rdm1=True, probes=True, bond=inputs.heisenberg_bond_matrix()).step(6)
+    g = _gpu(A, 10, form, 6, rdm1=True, probes=True, bond=inputs.heisenberg_bond_matrix())
+    _compare(g, o)
+    r = g.rho1()
+    assert np.abs(r - o.rho1()).max() < 1e-10
+    assert abs(g.energy() - o.energy()) < 1e-10
+    if form == "z2":
+        assert np.array_equal(r, r.T)  # Hermitian by construction
+    assert abs(np.trace(r) - 1.0) < 1e-14
