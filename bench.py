@@ -25,6 +25,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+PHASES = ["corners", "halves", "svd", "renormalise", "convergence"]
 METRIC = "CTMRG steps/s Z2 vs dense (FP64 vs mixed) at D=6 χ=144; p50/p99 solve latency"
 FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (datasheet)
 GEMM_SOURCE = os.path.join(ROOT, "paper_2410_11596_amd", "csrc", "gemm.hip")
@@ -320,37 +321,61 @@ def serving(n_req, rate, max_active=8, tol=1e-10, max_iter=40, seed=11):
     return out
 
 
-def cpu_baseline(D, chi, split, seed=0):
-    """The oracle's Z2 left move on a random saturated environment (timed once)."""
+def _oracle_saturated_env(ctmrg, basis, run, D, chi, split, seed):
+    """A seeded random environment with every bond at chi: split (even, odd)
+    in the Z2 form (blocks of odd total parity zero), one sector in the plain
+    form."""
+    rng = np.random.default_rng(seed + 1)
+    q = D * D
+    if run.form == "z2":
+        pq = run.par_q
+        pb = np.array([0] * split[0] + [1] * split[1])
+    else:
+        pq = np.zeros(q, dtype=np.int64)
+        pb = np.zeros(chi, dtype=np.int64)
+    ts = []
+    for shape, pars in [((chi, chi), [pb, pb]), ((chi, q, chi), [pb, pq, pb])] * 4:
+        x = rng.standard_normal(shape)
+        ts.append(np.where(basis.parity_mask(pars), x, 0.0))
+    return ctmrg.Env(ts, [pb.copy() for _ in range(4)] if run.form == "z2" else None)
+
+
+def cpu_baseline(D, chi, split, seed=0, z2_repeats=3):
+    """The oracle as it stands, on the host cores: one left move of its plain
+    (dense) form -- the authority -- on a seeded random environment with every
+    bond at chi, timed once (about 15-25 s on 16 cores), scaled x4 to one
+    iteration; beside it the median of z2_repeats left moves of its Z2 form on
+    the same kind of environment split (even, odd)."""
     from oracle import basis, ctmrg
 
     from paper_2410_11596_amd import inputs
 
     A = inputs.iid_tensor(2, D, seed)
-    run = ctmrg.Run(chi, "z2", A=A)            # builds a~ and the masks
-    rng = np.random.default_rng(seed + 1)
-    pq = run.par_q
-    pb = np.array([0] * split[0] + [1] * split[1])
-    q = D * D
-    shapes_par = [
-        ((chi, chi), [pb, pb]), ((chi, q, chi), [pb, pq, pb]),
-    ] * 4
-    ts = []
-    for shape, pars in shapes_par:
-        x = rng.standard_normal(shape)
-        ts.append(np.where(basis.parity_mask(pars), x, 0.0))
-    env = ctmrg.Env(ts, [pb.copy() for _ in range(4)])
     threads = len(os.sched_getaffinity(0))
+    rd = ctmrg.Run(chi, "dense", A=A)
+    env = _oracle_saturated_env(ctmrg, basis, rd, D, chi, split, seed)
     t0 = time.perf_counter()
-    ctmrg.left_move(env, run.a, chi, run.tau, pq)
-    t = time.perf_counter() - t0
+    ctmrg.left_move(env, rd.a, chi, rd.tau, None)
+    t_dense = time.perf_counter() - t0
+    rz = ctmrg.Run(chi, "z2", A=A)
+    tz = []
+    for r in range(z2_repeats):
+        env = _oracle_saturated_env(ctmrg, basis, rz, D, chi, split, seed + r)
+        t0 = time.perf_counter()
+        ctmrg.left_move(env, rz.a, chi, rz.tau, rz.par_q)
+        tz.append(time.perf_counter() - t0)
+    t_z2 = float(np.median(tz))
     return {
-        "value": 1.0 / (4.0 * t),
+        "value": 1.0 / (4.0 * t_dense),
         "unit": "CTMRG iterations/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"one left move of the oracle's Z2 form (numpy/OpenBLAS, FP64) on a random saturated "
-                  f"D={D}, chi={chi} environment split {split[0]}+{split[1]}, {t:.1f} s, scaled x4 to one iteration",
+        "sample": f"one left move of the oracle's plain (dense) form (numpy + the host BLAS/LAPACK, FP64, "
+                  f"{threads} threads) on a seeded random D={D}, chi={chi} environment with every bond at chi, "
+                  f"{t_dense:.1f} s, scaled x4 to one iteration",
+        "z2_form": {"value": 1.0 / (4.0 * t_z2), "unit": "CTMRG iterations/s",
+                    "sample": f"median of {z2_repeats} left moves of the oracle's Z2 form on such environments "
+                              f"split {split[0]}+{split[1]}: {', '.join(f'{t:.2f}' for t in tz)} s"},
     }
 
 
@@ -359,7 +384,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--dense-steps", type=int, default=3)
+    ap.add_argument("--dense-steps", type=int, default=None,
+                    help="timed iterations of the plain form (default: --steps, the same window as the Z2 form)")
     ap.add_argument("--D", type=int, default=6)
     ap.add_argument("--chi", type=int, default=144)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -377,6 +403,8 @@ def main():
     ap.add_argument("--copy-check", type=int, default=0, metavar="BYTES",
                     help="before timing, copy BYTES three times (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.dense_steps is None:
+        args.dense_steps = args.steps
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solver is built for a single GPU "
               "and has no multi-GPU path", file=sys.stderr)
@@ -424,8 +452,8 @@ def main():
             "precision": "fp64",
         },
         "sector_split": list(split),
-        "phases_ms_per_step": {k: 1e3 * v / args.steps for k, v in
-                               zip(["corners", "halves", "svd", "renormalise"], phases.tolist())},
+        "phases_ms_per_step": {k: 1e3 * v / args.steps for k, v in zip(PHASES, phases.tolist())},
+        "phases_sum_ms_per_step": 1e3 * float(np.sum(phases)) / args.steps,
     }
     if stats["launches"] > 0 and stats["seconds"] > 0:
         # mean algorithmic flops per launch over the mean launch duration; an
@@ -453,13 +481,24 @@ def main():
     if not args.no_late:
         out["late_iterations"] = late_iterations(A, args.chi, args.warmup + args.steps, args.steps)
     if not args.no_dense:
+        # the plain form over the same window: the same warm-up, the same
+        # number of timed iterations (unless --dense-steps says otherwise)
         td, dstats, dphases, _ = time_form(A, args.chi, "dense", args.dense_steps, args.warmup, profile=False)
         dense_rate = args.dense_steps / td
-        out["dense_value"] = dense_rate
-        out["dense_ms_per_step"] = 1e3 * td / args.dense_steps
-        out["z2_over_dense"] = z2_rate / dense_rate
-        out["dense_phases_ms_per_step"] = {k: 1e3 * v / args.dense_steps for k, v in
-                                           zip(["corners", "halves", "svd", "renormalise"], dphases.tolist())}
+        dph = {k: 1e3 * v / args.dense_steps for k, v in zip(PHASES, dphases.tolist())}
+        out["dense"] = {
+            "iterations_timed": [args.warmup + 1, args.warmup + args.dense_steps],
+            "z2_iterations_timed": [args.warmup + 1, args.warmup + args.steps],
+            "value": dense_rate,
+            "ms_per_step": 1e3 * td / args.dense_steps,
+            "phases_ms_per_step": dph,
+            "phases_sum_ms_per_step": sum(dph.values()),
+            "z2_over_dense": z2_rate / dense_rate,
+            "matched_window": args.dense_steps == args.steps,
+            "phase_ratio_dense_over_z2": {k: (dph[k] / out["phases_ms_per_step"][k])
+                                          if out["phases_ms_per_step"][k] > 0 else None for k in PHASES},
+        }
+        out["z2_over_dense"] = out["dense"]["z2_over_dense"]
     if not args.no_mixed:
         out["mixed"] = mixed_precision(A, args.chi, args.steps, args.warmup)
         out["mixed_bf16x3"] = mixed_precision(A, args.chi, args.steps, args.warmup, precision="bf16x3")

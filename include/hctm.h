@@ -122,11 +122,18 @@ int ctm_workspace_size(int d, int D, int chi, const ctm_opts* o, size_t* bytes);
 int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, const ctm_opts* o);
 
 /*
- * Run n_iter CTMRG iterations; one iteration is a left, right, top and
- * bottom move, each absorbing the columns or rows of double-layer tensors of
- * the cell and truncating every grown bond back to chi with per-sector SVD
- * projectors.  After every iteration the corner spectra are compared with the
- * previous ones (see ctm_converged).
+ * Run n_iter CTMRG iterations (Sec. II A: the boundary grows by absorbing
+ * rows and columns, and every grown bond of dimension chi D^2 is truncated
+ * back to chi by an SVD; Sec. II B, points (1)-(3): in the swap eigenbasis
+ * every product and SVD runs per parity sector and the truncation keeps the
+ * symmetry).  One iteration is a left, right, top and bottom move, each
+ * absorbing the columns or rows of double-layer tensors of the cell and
+ * truncating every grown bond back to chi with per-sector SVD projectors.
+ * After every iteration the corner spectra are compared with the previous
+ * ones (see ctm_converged).  Work is enqueued on the context's stream; the
+ * call reads back small values (kept counts, stopping tests) and returns
+ * when the iterations are done.  Errors: CTM_E_ARG for n_iter < 0;
+ * CTM_E_NUMERIC (context poisoned) if a decomposition breaks down.
  */
 int ctm_step(ctm_ctx* c, int n_iter);
 
@@ -136,20 +143,51 @@ int ctm_step(ctm_ctx* c, int n_iter);
 int ctm_set_precision(ctm_ctx* c, int precision);
 
 /*
+ * Convergence of the environment (the boundary tensors of Sec. II A,
+ * Fig. 1d, approach a fixed point as the iterations grow the system):
  * delta = max over the four corners of every site of || s_new - s_old ||_2,
  * s the singular values of a corner divided by their sum and padded with
- * zeros to chi, between the last two iterations (+inf before the second).
- * converged = (delta < tol).  Synchronises.
+ * zeros to max(chi, D^2), between the last iteration and the one before
+ * (the initial environment before the first; +inf before any).
+ * converged = (delta < tol).  Either output may be NULL.  Synchronises.
  */
 int ctm_converged(ctm_ctx* c, double tol, int* converged, double* delta);
 
+/*
+ * Current spectrum of corner `corner` (0 C1 up-left, 1 C2 up-right, 2 C3
+ * down-right, 3 C4 down-left) of site (x, y): the singular values of both
+ * sectors merged in descending order, divided by their sum, zero padded;
+ * *n = its length max(chi, D^2).  s: host array of cap >= *n doubles, or
+ * NULL to query *n.  These are the vectors ctm_converged compares.
+ */
+int ctm_corner_spectrum(ctm_ctx* c, int x, int y, int corner, double* s, int cap, int* n);
+
+/*
+ * Health of the truncations run so far (Sec. II B, point (3); Sec. III A):
+ * *unconverged = truncations in which a sector's subspace iteration reached
+ * ctm_opts.svd_iters iterations without passing its residual test (the
+ * iterate is used as it stands); *multiplet_splits = truncations whose chi
+ * cut separated two values within a relative 1e-10 of each other (the first
+ * discarded value above the cutoff), where the kept space is not unique.
+ * Either output may be NULL.
+ */
+int ctm_svd_health(ctm_ctx* c, int* unconverged, int* multiplet_splits);
+
 /* One-site reduced density matrix rho[s][s'] of site (x, y) of the cell
- * (host, d*d), trace one. */
+ * (host, d*d, row-major), trace one: the one-site environment (Sec. III A)
+ * closed with A[s] (x) A[s'] (Sec. II A, Fig. 1b).  In the Z2 form only
+ * the symmetric impurity (A[s] (x) A[s'] + A[s'] (x) A[s]) / 2 enters, the
+ * only part that is even under the swap of Sec. II B, so rho is symmetric
+ * (Hermitian) bit for bit.  Errors: CTM_E_ARG for a site outside the cell or
+ * a NULL rho.  Synchronises. */
 int ctm_rdm_1site(ctm_ctx* c, int x, int y, double* rho);
 
 /*
- * Two-site RDM of a nearest-neighbour pair, rho[(s1 s2)][(s1' s2')] (host,
- * d^4), trace one.  dir 0: the pair (x, y)-(x+1, y), 1: the pair
+ * Two-site RDM of a nearest-neighbour pair (Sec. I and Sec. II B point (3):
+ * reduced density matrices are the observables whose Hermiticity the swap
+ * symmetry protects), rho[(s1 s2)][(s1' s2')] (host, d^4, row-major), trace
+ * one.  Errors: CTM_E_ARG for a bad site, dir or a NULL rho.  Synchronises.
+ * dir 0: the pair (x, y)-(x+1, y), 1: the pair
  * (x, y)-(x, y+1), the first site first.  In the Z2 form both RDMs are
  * symmetric by construction: only the even (symmetric) part of an impurity
  * couples to the even environment, and pairs of odd (antisymmetric) parts are
@@ -157,8 +195,11 @@ int ctm_rdm_1site(ctm_ctx* c, int x, int y, double* rho);
  */
 int ctm_rdm_2site(ctm_ctx* c, int x, int y, int dir, double* rho);
 
-/* E = mean over the sites of Tr(rho_h h) + Tr(rho_v h), for a bond operator
- * h (host, d^2 x d^2). */
+/* Energy per site of a nearest-neighbour Hamiltonian (Sec. III: the
+ * Heisenberg model's energy is the benchmark observable): E = mean over the
+ * sites of Tr(rho_h h) + Tr(rho_v h), rho the two-site RDMs above, for a bond
+ * operator h (host, d^2 x d^2 row-major, read only).  Errors: CTM_E_ARG for
+ * NULL pointers.  Synchronises. */
 int ctm_energy(ctm_ctx* c, const double* h, double* e);
 
 /* Release everything; NULL is accepted. */
@@ -186,6 +227,11 @@ int ctm_log_kappa(ctm_ctx* c, double* ln_kappa);
  * truncates Lx*Ly cuts). */
 int ctm_num_records(ctm_ctx* c, int* n);
 
+/* Status bits of truncation m: 1 (2) the even (odd) sector's subspace
+ * iteration reached its cap without passing the residual test, 4 the chi cut
+ * split a near-degenerate multiplet (see ctm_svd_health). */
+int ctm_record_status(ctm_ctx* c, int m, int* status);
+
 /*
  * Record of truncation m (0-based, in the order run): the kept singular
  * values of the decomposed matrix, merged over both sectors in descending
@@ -207,7 +253,8 @@ int ctm_sector_dims(ctm_ctx* c, int x, int y, int side, int* chi_even, int* chi_
 /* GPU seconds of the last ctm_step call per phase of the moves:
  * t[0] enlarged corners, t[1] half-system products and M, t[2] truncated SVD
  * (subspace iteration, Jacobi, selection), t[3] projectors, renormalisation
- * and normalisation.  *n = 4. */
+ * and normalisation, t[4] the corner spectra of the convergence test.
+ * *n = 5. */
 int ctm_timing(ctm_ctx* c, double* t, int cap, int* n);
 
 /* Profile mode only (ctm_opts.profile = 1): algorithmic FP64 GEMM flops

@@ -24,6 +24,7 @@ EXPORTS = [
     "ctm_rdm_1site", "ctm_rdm_2site", "ctm_energy", "ctm_free", "ctm_last_error",
     "ctm_env_epsilon", "ctm_s_err", "ctm_log_kappa", "ctm_num_records", "ctm_record",
     "ctm_sector_dims", "ctm_timing", "ctm_gemm_stats", "ctm_set_precision",
+    "ctm_corner_spectrum", "ctm_svd_health", "ctm_record_status",
     "ctm_server_create", "ctm_server_submit", "ctm_server_wait", "ctm_server_load", "ctm_server_destroy",
     "hotrg_opts_default", "hotrg_init", "hotrg_step", "hotrg_log_z", "hotrg_sym_error", "hotrg_set_bond",
     "hotrg_energy", "hotrg_track_rdm1", "hotrg_rdm1", "hotrg_num_records",
@@ -110,6 +111,9 @@ def lib():
         "ctm_num_records": ([ctx, ip], ctypes.c_int),
         "ctm_record": ([ctx, ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, ip], ctypes.c_int),
         "ctm_sector_dims": ([ctx, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ip], ctypes.c_int),
+        "ctm_corner_spectrum": ([ctx, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ip], ctypes.c_int),
+        "ctm_svd_health": ([ctx, ip, ip], ctypes.c_int),
+        "ctm_record_status": ([ctx, ctypes.c_int, ip], ctypes.c_int),
         "ctm_timing": ([ctx, dp, ctypes.c_int, ip], ctypes.c_int),
         "ctm_gemm_stats": ([ctx, dp, dp, P(ctypes.c_longlong), ctypes.c_int], ctypes.c_int),
         "hctm_dev_gemm": ([vp, vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.c_double, vp, vp,
@@ -338,12 +342,30 @@ class CTMRG:
         info = (ctypes.c_int * 8)()
         _check(lib().ctm_record(self._ctx, m, _dptr(s), cap, ctypes.byref(n), ctypes.byref(ke), ctypes.byref(ko),
                                 info), self._ctx)
+        st = ctypes.c_int()
+        _check(lib().ctm_record_status(self._ctx, m, ctypes.byref(st)), self._ctx)
         return {"spectrum": s[: n.value].copy(), "kept": (ke.value, ko.value), "frame": info[0],
                 "column": info[1], "row": info[2], "iters": (info[3], info[4]), "sweeps": (info[5], info[6]),
-                "implicit": bool(info[7])}
+                "implicit": bool(info[7]), "unconverged": (bool(st.value & 1), bool(st.value & 2)),
+                "multiplet_split": bool(st.value & 4)}
 
     def records(self):
         return [self.record(m) for m in range(self.num_records())]
+
+    def corner_spectrum(self, corner, x=0, y=0):
+        """Merged, sum-normalised, zero-padded spectrum of corner 0..3 (C1..C4)."""
+        n = ctypes.c_int()
+        _check(lib().ctm_corner_spectrum(self._ctx, x, y, corner, None, 0, ctypes.byref(n)), self._ctx)
+        s = np.zeros(n.value)
+        _check(lib().ctm_corner_spectrum(self._ctx, x, y, corner, _dptr(s), n.value, ctypes.byref(n)), self._ctx)
+        return s
+
+    def svd_health(self):
+        """(truncations with a sector stopped at the iteration cap, truncations
+        whose chi cut split a near-degenerate multiplet)."""
+        u, m = ctypes.c_int(), ctypes.c_int()
+        _check(lib().ctm_svd_health(self._ctx, ctypes.byref(u), ctypes.byref(m)), self._ctx)
+        return u.value, m.value
 
     def sector_dims(self, side, x=0, y=0):
         e, o = ctypes.c_int(), ctypes.c_int()

@@ -285,6 +285,38 @@ int ctm_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, int* 
   });
 }
 
+int ctm_record_status(ctm_ctx* c, int m, int* status) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    const auto& r = c->ctm->records();
+    if (!status) throw hctm::Error(CTM_E_ARG, "status is NULL");
+    if (m < 0 || m >= (int)r.size()) throw hctm::Error(CTM_E_ARG, "record index out of range");
+    *status = r[m].status;
+  });
+}
+
+int ctm_svd_health(ctm_ctx* c, int* unconverged, int* multiplet_splits) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    if (unconverged) *unconverged = c->ctm->svd_unconverged();
+    if (multiplet_splits) *multiplet_splits = c->ctm->multiplet_splits();
+  });
+}
+
+int ctm_corner_spectrum(ctm_ctx* c, int x, int y, int corner, double* s, int cap, int* n) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    if (corner < 0 || corner > 3) throw hctm::Error(CTM_E_ARG, "corner must be 0..3");
+    check_site(c, x, y);
+    const int len = c->ctm->spectrum_len();
+    if (n) *n = len;
+    if (s) {
+      if (cap < len) throw hctm::Error(CTM_E_ARG, "cap is smaller than the spectrum length");
+      c->ctm->corner_spectrum(x, y, corner, s);
+    }
+  });
+}
+
 int ctm_sector_dims(ctm_ctx* c, int x, int y, int side, int* chi_even, int* chi_odd) {
   if (!c) return CTM_E_ARG;
   return guarded(c, [&] {

@@ -192,6 +192,9 @@ void Ctm::plan_memory(bool counting) {
   csv_ = ar_.take((size_t)(ns * 8 * cc));
   cperm_ = ti(ns * 8 * cc);
   cmat_ = ar_.take((size_t)(ns * 8 * cc * cc));
+  // column-major scratch that lets corner blocks beyond the LDS Jacobi (up
+  // to 256 x 256) run in the L2-resident kernel
+  cwork_ = cc <= 256 ? ar_.take((size_t)(ns * 8 * cc * cc)) : nullptr;
   eps_.p = ar_.take((size_t)q4);
   eps_.capacity = q4;
   halves_cap_ = cc * cc * q;
@@ -240,7 +243,10 @@ Ctm::Ctm(const double* A_host, int d, int D, int chi, const Options& o, hipStrea
   ar_.cap = need;
   plan_memory(false);
   HCTM_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_k_), 64 * sizeof(int), hipHostMallocDefault));
-  HCTM_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_d_), (4096 + 64) * sizeof(double), hipHostMallocDefault));
+  // pinned staging: the kept values of both sectors (cc_ each, cc_ >= chi >=
+  // any kept count), then kHostMisc slots for scalars read back
+  HCTM_HIP(hipHostMalloc(reinterpret_cast<void**>(&host_d_), (2 * (size_t)cc_ + kHostMisc) * sizeof(double),
+                         hipHostMallocDefault));
   setup(A_host);
 }
 
@@ -400,7 +406,16 @@ void Ctm::setup(const double* A_host) {
     }
   }
   for (BT& t : env_) normalise(t);
+  // spectra of the initial corners, so that the first iteration has a delta
+  corner_spectra();
   sync();
+}
+
+void Ctm::corner_spectrum(int x, int y, int c, double* s) {
+  const double* src = cspec_ + ((long long)site(x, y) * 4 + c) * cc_;
+  HCTM_HIP(hipMemcpyAsync(host_d_, src, sizeof(double) * cc_, hipMemcpyDeviceToHost, st_));
+  sync();
+  std::memcpy(s, host_d_, sizeof(double) * cc_);
 }
 
 // ------------------------------------------------------------ quadrant ----
@@ -589,6 +604,7 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
       S.warm = false;
       S.fin = false;
       S.done = false;
+      S.conv = false;
       if (S.n == 0) {
         S.trusted = 0;
         continue;
@@ -601,7 +617,10 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
       S.direct = S.n <= kDirectMax || S.l >= S.n;
       if (S.direct && S.n > l_cap_) throw Error(1, "truncated_svd: sector too large for a direct decomposition");
       if (S.direct && implicit_) throw Error(1, "truncated_svd: a direct decomposition needs the matrix");
-      if (S.direct) S.l = S.n;
+      if (S.direct) {
+        S.l = S.n;
+        S.conv = true;
+      }
       // all Ritz columns are decomposed (restricting the Rayleigh-Ritz step
       // to the leading ones gives up the oversampling's accuracy); the
       // trailing p/2 values are not trusted for the truncation
@@ -695,12 +714,15 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
             fill(misc_ + 48 + 2 * c, 0.0, 2, st_);
             col_resid(S->Y, S->l, S->Qold, kc, S->n, kc, misc_ + 48 + 2 * c, st_);
           }
-          HCTM_HIP(hipMemcpyAsync(host_d_ + 4096, misc_ + 48, sizeof(double) * 2 * chk.size(),
+          HCTM_HIP(hipMemcpyAsync(hmisc(), misc_ + 48, sizeof(double) * 2 * chk.size(),
                                   hipMemcpyDeviceToHost, st_));
           sync();
           for (size_t c = 0; c < chk.size(); ++c) {
-            const double e = host_d_[4096 + 2 * c], ymax = host_d_[4096 + 2 * c + 1];
-            if (e <= kSubspaceTolPrec[opt_.precision] * ymax) chk[c]->fin = true;
+            const double e = hmisc()[2 * c], ymax = hmisc()[2 * c + 1];
+            if (e <= kSubspaceTolPrec[opt_.precision] * ymax) {
+              chk[c]->fin = true;
+              chk[c]->conv = true;
+            }
           }
         }
         for (SvdSector* S : act) {
@@ -775,11 +797,14 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
     a.isv1 = sec_[1].isv;
     select_states(a, st_);
     HCTM_HIP(hipMemcpyAsync(host_k_, kdev_, 2 * sizeof(int), hipMemcpyDeviceToHost, st_));
+    HCTM_HIP(hipMemcpyAsync(hmisc() + 8, misc_ + 8, 3 * sizeof(double), hipMemcpyDeviceToHost, st_));
     for (int P = 0; P < 2; ++P) {
       HCTM_HIP(hipMemcpyAsync(host_k_ + 2 + 2 * P, sec_[P].info, 2 * sizeof(int), hipMemcpyDeviceToHost, st_));
-      const int nc = std::min(sec_[P].n > 0 ? sec_[P].trusted : 0, std::min(chi, 2048));
+      // the kept values (at most chi <= cc_ per sector) for the record
+      const int nc = std::min(sec_[P].n > 0 ? sec_[P].trusted : 0, chi);
+      if (nc > cc_) throw Error(1, "truncated_svd: kept count beyond the staging buffer");
       if (nc > 0)
-        HCTM_HIP(hipMemcpyAsync(host_d_ + 2048 * P, sec_[P].sv, sizeof(double) * nc, hipMemcpyDeviceToHost, st_));
+        HCTM_HIP(hipMemcpyAsync(hspec(P), sec_[P].sv, sizeof(double) * nc, hipMemcpyDeviceToHost, st_));
     }
     sync();
     bool redo = false;
@@ -797,6 +822,19 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
     if (!redo) break;
     if (attempt == 3) throw Error(4, "truncated SVD: subspace too small after retries");
   }
+  // health of this truncation: a sector whose subspace iteration ran to the
+  // cap without passing the residual test, and a chi cut inside a multiplet
+  // (the first discarded value within kSplitGap of the last kept one while
+  // it is above the cutoff, so that only chi removed it)
+  svd_status_ = 0;
+  for (int P = 0; P < 2; ++P)
+    if (sec_[P].n > 0 && !sec_[P].conv) svd_status_ |= P == 0 ? kRecUnconvEven : kRecUnconvOdd;
+  {
+    const double smax = hmisc()[8], nxt = hmisc()[9], last = hmisc()[10];
+    if (nxt > opt_.tau * smax && last > 0.0 && last / nxt - 1.0 < kSplitGap) svd_status_ |= kRecSplit;
+  }
+  if (svd_status_ & (kRecUnconvEven | kRecUnconvOdd)) ++svd_unconverged_;
+  if (svd_status_ & kRecSplit) ++splits_;
   // vectors of the kept states: U from the orthogonalised columns, V from the
   // accumulated rotations (a consistent pair: B V = U S to rounding)
   std::vector<GemmDesc> g;
@@ -1050,12 +1088,13 @@ void Ctm::move(int r) {
       rec.column = X;
       rec.row = Y;
       rec.implicit = implicit ? 1 : 0;
+      rec.status = svd_status_;
       for (int P = 0; P < 2; ++P) {
         rec.iters[P] = sec_[P].iters;
         rec.sweeps[P] = sec_[P].sweeps;
       }
       for (int P = 0; P < 2; ++P)
-        for (int i = 0; i < sec_[P].k; ++i) rec.spectrum.push_back(host_d_[2048 * P + i]);
+        for (int i = 0; i < sec_[P].k; ++i) rec.spectrum.push_back(hspec(P)[i]);
       std::sort(rec.spectrum.begin(), rec.spectrum.end(), [](double a, double b) { return a > b; });
       const double s0 = rec.spectrum.empty() ? 1.0 : rec.spectrum[0];
       for (double& v : rec.spectrum) v /= s0;
@@ -1242,12 +1281,13 @@ void Ctm::move_c4v() {
   MoveRecord rec;
   rec.k_even = opt_.form == 0 ? kn.e : kn.e + kn.o;
   rec.k_odd = opt_.form == 0 ? kn.o : 0;
+  rec.status = svd_status_;
   for (int P = 0; P < 2; ++P) {
     rec.iters[P] = sec_[P].iters;
     rec.sweeps[P] = sec_[P].sweeps;
   }
   for (int P = 0; P < 2; ++P)
-    for (int i = 0; i < sec_[P].k; ++i) rec.spectrum.push_back(host_d_[2048 * P + i]);
+    for (int i = 0; i < sec_[P].k; ++i) rec.spectrum.push_back(hspec(P)[i]);
   std::sort(rec.spectrum.begin(), rec.spectrum.end(), [](double a, double b) { return a > b; });
   const double s0 = rec.spectrum.empty() ? 1.0 : rec.spectrum[0];
   for (double& v : rec.spectrum) v /= s0;
@@ -1281,6 +1321,7 @@ void Ctm::corner_spectra() {
         p.info = kdev_ + 8;
         p.sv = csv_ + slot;
         p.perm = cperm_ + slot;
+        p.work = cwork_ ? cwork_ + (mat - cmat_) : nullptr;
         jp.push_back(p);
         mat += (long long)cc_ * cc_;
       }
@@ -1310,15 +1351,18 @@ void Ctm::step(int n_iter) {
     } else {
       for (int m = 0; m < 4; ++m) move(order[m]);
     }
+    mark(4);
     corner_spectra();
+    mark(-1);
   }
   HCTM_HIP(hipMemcpyAsync(host_d_, misc_ + 16, sizeof(double), hipMemcpyDeviceToHost, st_));
   sync();
   delta_ = host_d_[0];
   flush_gemm_stats();
-  // phase times: quadrants, halves, svd, projectors + renormalisation; the
-  // time between two marks counts for the phase of the first
-  timing.assign(4, 0.0);
+  // phase times: quadrants, halves, svd, projectors + renormalisation,
+  // corner spectra; the time between two marks counts for the phase of the
+  // first
+  timing.assign(5, 0.0);
   for (size_t i = 0; i + 1 < ev_phase_.size(); ++i) {
     const int ph = ev_phase_[i];
     if (ph < 0) continue;

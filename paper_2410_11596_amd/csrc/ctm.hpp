@@ -33,7 +33,16 @@ struct MoveRecord {
   int iters[2] = {0, 0};   // subspace iterations per sector (0: decomposed directly)
   int sweeps[2] = {0, 0};  // Jacobi sweeps per sector
   int implicit = 0;        // 1: the matrix was applied through the corners
+  int status = 0;          // kRec* bits
 };
+
+// MoveRecord::status bits
+constexpr int kRecUnconvEven = 1;  // even sector: subspace iteration stopped at its cap
+constexpr int kRecUnconvOdd = 2;   // odd sector: the same
+constexpr int kRecSplit = 4;       // the chi cut fell inside a near-degenerate multiplet
+// relative gap s_k / s_{k+1} - 1 below which the last kept and the first
+// discarded value count as one multiplet
+constexpr double kSplitGap = 1e-10;
 
 constexpr int kMaxCell = 4;  // Lx, Ly <= kMaxCell
 
@@ -67,6 +76,7 @@ struct SvdSector {
   bool warm = false;     // started from the cut's previous right vectors
   bool fin = false;      // the next iterate is the final one
   bool done = false;
+  bool conv = false;     // the residual test ended the subspace iteration (or direct)
   const double* Mp = nullptr;  // sector block of M (n x n, ld = n)
   double *Qr = nullptr, *Ql = nullptr, *Y = nullptr, *Tm = nullptr;
   double* Qold = nullptr;  // projection of Y on the previous left basis (check)
@@ -92,6 +102,12 @@ class Ctm {
   void set_precision(int p) { opt_.precision = p; }
   int precision() const { return opt_.precision; }
   double delta() const { return delta_; }
+  int svd_unconverged() const { return svd_unconverged_; }
+  int multiplet_splits() const { return splits_; }
+  // current corner spectrum (merged over the sectors, sum-normalised, zero
+  // padded) of corner c (0..3) of site (x, y): len() values into s
+  void corner_spectrum(int x, int y, int c, double* s);
+  int spectrum_len() const { return cc_; }
   void rdm1(int x, int y, double* rho);
   void rdm2(int x, int y, int dir, double* rho);
   void epsilon_plain(int x, int y, double* eps_host);
@@ -187,7 +203,13 @@ class Ctm {
   double* misc_ = nullptr;  // small device scalars
   int* kdev_ = nullptr;
   int* host_k_ = nullptr;   // pinned
-  double* host_d_ = nullptr;
+  double* host_d_ = nullptr;  // pinned: 2 cc_ kept values, then kHostMisc scalars
+  static constexpr int kHostMisc = 64;
+  double* hspec(int P) { return host_d_ + (size_t)P * cc_; }
+  double* hmisc() { return host_d_ + 2 * (size_t)cc_; }
+  int svd_unconverged_ = 0;  // truncations with a sector stopped at the iteration cap
+  int splits_ = 0;           // truncations whose chi cut split a multiplet
+  int svd_status_ = 0;       // kRec* bits of the last truncation
   double* part_ = nullptr;
   // corner spectra
   double* cspec_ = nullptr;     // sites x 4 corners x chi (current, normalised)
@@ -195,6 +217,7 @@ class Ctm {
   double* csv_ = nullptr;       // scratch singular values
   int* cperm_ = nullptr;
   double* cmat_ = nullptr;      // scratch copies of corner blocks
+  double* cwork_ = nullptr;     // Jacobi scratch for them (cc_ <= 256)
   bool have_old_spec_ = false;
   double delta_ = 1e300;
   // observables

@@ -1303,6 +1303,16 @@ __global__ void select_kernel(SelectArgs a) {
   a.out_k[0] = i0;
   a.out_k[1] = i1;
   a.out_s[0] = smax;
+  // the last kept and the first discarded value (-1: none), for the
+  // multiplet-split test at the chi cut
+  {
+    const double v0 = i0 < a.n0 ? a.sv0[i0] : -1.0;
+    const double v1 = i1 < a.n1 ? a.sv1[i1] : -1.0;
+    a.out_s[1] = fmax(v0, v1);
+    const double l0 = i0 > 0 ? a.sv0[i0 - 1] : -1.0;
+    const double l1 = i1 > 0 ? a.sv1[i1 - 1] : -1.0;
+    a.out_s[2] = (i0 > 0 && i1 > 0) ? fmin(l0, l1) : fmax(l0, l1);
+  }
   for (int i = 0; i < i0; ++i) {
     a.isq0[i] = 1.0 / sqrt(a.sv0[i]);
     a.isv0[i] = 1.0 / a.sv0[i];

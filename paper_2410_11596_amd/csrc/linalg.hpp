@@ -44,7 +44,7 @@ struct SelectArgs {
   int chi;
   double tau;
   int* out_k;    // [k_even, k_odd]
-  double* out_s; // [s_max]
+  double* out_s; // [s_max, first discarded value or -1, last kept value]
   double* isq0;  // 1/sqrt(s) of the kept values, sector 0
   double* isq1;
   double* isv0;  // 1/s of the kept values

@@ -34,6 +34,28 @@ def _gpu_run(A, chi, form, iters, **kw):
     return c
 
 
+def _gpu_launch(A, chi, form, **kw):
+    from paper_2410_11596_amd import CTMRG
+
+    return CTMRG(A, chi, form=form, **kw)
+
+
+# delta is a distance between sum-normalised spectra whose entries carry
+# absolute rounding errors of a few 1e-16 from either SVD
+DELTA_TOL = 1e-12
+
+
+def _compare_corner_spectra(g, o, atol=1e-12):
+    """The four current corner spectra (sum-normalised, zero padded) against
+    the oracle's on their common length; the rest is zero on both sides."""
+    for c in range(4):
+        sg = g.corner_spectrum(c)
+        so = o._spec[c]
+        n = min(len(sg), len(so))
+        assert np.abs(sg[:n] - so[:n]).max() < atol, c
+        assert not np.any(sg[n:]) and not np.any(so[n:])
+
+
 def _compare(g, o, spectra_rtol=1e-6, tol=TOL):
     assert np.abs(g.rdm1() - o.rho1()).max() < tol
     assert np.abs(g.rdm2("h") - o.rho2("h")).max() < tol
@@ -60,10 +82,17 @@ def test_first_moves_d2(form):
 
 @pytest.mark.parametrize("form", ["z2", "dense"])
 def test_config1_d2_chi16_50_iterations(form):
-    """D=2, chi=16, 50 iterations: the Z2 and plain forms side by side."""
+    """D=2, chi=16, 50 iterations: the Z2 and plain forms side by side; delta
+    after every iteration against the oracle's."""
     A = inputs.iid_tensor(2, 2, 0)
-    o = ctmrg.Run(16, form, A=A).step(50)
-    g = _gpu_run(A, 16, form, 50)
+    o = ctmrg.Run(16, form, A=A)
+    g = _gpu_launch(A, 16, form)
+    _compare_corner_spectra(g, o)  # the initial environment
+    for it in range(50):
+        o.step(1)
+        g.step(1)
+        assert abs(g.converged(0.0)[1] - o.deltas[-1]) < DELTA_TOL, it
+    _compare_corner_spectra(g, o)
     _compare(g, o)
     if form == "z2":
         assert [tuple(r["kept"]) for r in g.records()] == [tuple(r["kept"]) for r in o.records]
@@ -103,14 +132,26 @@ def test_ising_peps_up_boundary():
     assert abs(g.log_kappa() - o.log_kappa()) < 1e-10
 
 
+@pytest.mark.parametrize("form_m", [False, True])
 @pytest.mark.parametrize("form", ["z2", "dense"])
-def test_config2_d4_chi64(form):
-    """D=4 (10+6), chi=64: subspace-iteration SVD path against the oracle."""
+def test_config2_d4_chi64(form, form_m):
+    """D=4 (10+6), chi=64: subspace-iteration SVD path against the oracle,
+    with the decomposed matrix applied through the enlarged corners (default)
+    or always formed (form_m); the convergence measure delta after every
+    iteration and the final corner spectra against the oracle's."""
     A = inputs.iid_tensor(2, 4, 0)
-    o = ctmrg.Run(64, form, A=A).step(8)
-    g = _gpu_run(A, 64, form, 8)
+    o = ctmrg.Run(64, form, A=A)
+    g = _gpu_launch(A, 64, form, form_m=form_m)
+    for it in range(8):
+        o.step(1)
+        g.step(1)
+        assert abs(g.converged(0.0)[1] - o.deltas[-1]) < DELTA_TOL, it
     _compare(g, o)
     assert [tuple(r["kept"]) for r in g.records()] == [tuple(r["kept"]) for r in o.records]
+    _compare_corner_spectra(g, o)
+    if form_m:
+        assert not any(r["implicit"] for r in g.records())
+    assert g.svd_health()[0] == 0
 
 
 def test_metric_shape_d6_chi144_one_iteration():
@@ -199,3 +240,94 @@ def test_runs_are_bitwise_reproducible_with_and_without_instrumentation():
     assert [r["iters"] for r in ra] == [r["iters"] for r in rb]
     assert all(np.array_equal(x["spectrum"], y["spectrum"]) for x, y in zip(ra, rb))
     assert b.gemm_stats()["launches"] > 0
+
+
+def test_subspace_iteration_cap_is_reported():
+    """With one subspace iteration allowed, the truncations that take the
+    subspace path cannot pass their residual test: each is flagged in its
+    record and counted by ctm_svd_health, and the solve itself still runs."""
+    A = inputs.iid_tensor(2, 4, 0)
+    g = _gpu_launch(A, 64, "z2", svd_iters=1)
+    g.step(2)
+    recs = g.records()
+    sub = [r for r in recs if r["iters"][0] > 0 or r["iters"][1] > 0]
+    assert sub, "no truncation took the subspace path"
+    assert all(any(r["unconverged"]) for r in sub)
+    assert all(not any(r["unconverged"]) for r in recs if r["iters"] == (0, 0))
+    assert g.svd_health()[0] == sum(1 for r in recs if any(r["unconverged"]))
+    r1 = g.rdm1()
+    assert np.isfinite(r1).all() and abs(np.trace(r1) - 1.0) < 1e-12
+    # the default cap converges on the same input
+    h = _gpu_launch(A, 64, "z2")
+    h.step(2)
+    assert h.svd_health()[0] == 0
+
+
+def test_product_state_has_zero_delta():
+    """A product state's corners have rank one from the start: delta is zero
+    after the first iteration, the corner spectra are (1, 0, ...)."""
+    v = np.array([0.6, -0.8])
+    A = inputs.product_state(v, 3)
+    g = _gpu_launch(A, 8, "z2")
+    g.step(1)
+    conv, dl = g.converged(1e-14)
+    assert conv and dl < 1e-14
+    for c in range(4):
+        s = g.corner_spectrum(c)
+        assert abs(s[0] - 1.0) < 1e-14 and np.abs(s[1:]).max() < 1e-14
+
+
+def _golden_d6():
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "ctmrg_d6_chi144_seed0.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("form_m", [False, True])
+def test_benchmark_regime_d6_chi144_against_oracle(form_m):
+    """The benchmark shape (D = 6, chi = 144, seed 0) through the iterations
+    the benchmark times: warm starts, small oversampling once the cuts
+    converge, the matrix applied through the corners (default) or always
+    formed (form_m), both Jacobi phases and the redo with a larger subspace.
+    Every record's kept sector sizes exactly and kept spectrum, delta after
+    every iteration, the final corner spectra, RDMs and energy (1e-10), ln
+    kappa and sampled entries of the one-site environment against the
+    oracle's values stored by tests/golden/make_ctmrg_d6_chi144.py."""
+    gold = _golden_d6()
+    A = inputs.iid_tensor(2, 6, 0)
+    g = _gpu_launch(A, gold["chi"], "z2", form_m=form_m)
+    for it in range(gold["iterations"]):
+        g.step(1)
+        assert abs(g.converged(0.0)[1] - gold["deltas"][it]) < DELTA_TOL, it
+    recs = g.records()
+    assert len(recs) == len(gold["records"])
+    for m, (rg, ro) in enumerate(zip(recs, gold["records"])):
+        assert list(rg["kept"]) == ro["kept"], m
+        assert np.allclose(rg["spectrum"], ro["spectrum"], rtol=1e-8, atol=1e-13), m
+        assert not rg["multiplet_split"]
+    # the regimes the benchmark's iterations run in were all exercised
+    if form_m:
+        assert not any(r["implicit"] for r in recs)
+    else:
+        assert any(r["implicit"] for r in recs[8:]) and any(not r["implicit"] for r in recs)
+    assert any(0 < max(r["iters"]) <= 3 for r in recs)
+    assert g.svd_health()[0] == 0
+    for c in range(4):
+        sg = g.corner_spectrum(c)
+        so = np.array(gold["corner_spectra"][c])
+        n = min(len(sg), len(so))
+        assert np.abs(sg[:n] - so[:n]).max() < 1e-12
+    assert np.abs(g.rdm1() - np.array(gold["rho1"])).max() < TOL
+    assert np.abs(g.rdm2("h") - np.array(gold["rho2_h"])).max() < TOL
+    assert np.abs(g.rdm2("v") - np.array(gold["rho2_v"])).max() < TOL
+    e = g.energy(ctmrg.heisenberg_bond())
+    assert abs(e - gold["energy"]) < TOL * max(1.0, abs(gold["energy"]))
+    assert abs(g.log_kappa() - gold["log_kappa"]) < TOL
+    eps = g.epsilon().reshape(-1)
+    got = eps[np.array(gold["eps_index"])]
+    assert np.abs(got - np.array(gold["eps_value"])).max() < 1e-7 * gold["eps_max_abs"]
+    assert g.s_err() <= 1e-15
+    g.close()

@@ -299,3 +299,84 @@ def test_bond_dimension_one_is_a_product_state():
         o = ctmrg.Run(3, form, A=A).step(2)
         assert np.abs(o.rho1() - p).max() < 1e-14
         assert np.abs(o.rho2("h") - np.kron(p, p)).max() < 1e-14
+
+
+# ------------------------------------------------------ corner spectra ----
+def _corner_with(svals, shape, seed):
+    """A corner matrix of the given shape with known singular values, hidden
+    behind random orthogonal matrices on both legs."""
+    rng = np.random.default_rng(seed)
+    m, n = shape
+    O1, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    O2, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    S = np.zeros((m, n))
+    for i, v in enumerate(svals):
+        S[i, i] = v
+    return O1 @ S @ O2.T
+
+
+def _env_with_corners(corners):
+    t = []
+    for C in corners:
+        t += [C, np.zeros((1, 1, 1))]
+    return ctmrg.Env(t)
+
+
+def test_corner_spectra_known_values():
+    """The convergence measure of the corners (sum-normalised singular values,
+    zero padded to chi): corners built from known singular values behind
+    random orthogonal gauges, expected vectors written out by hand."""
+    env = _env_with_corners([
+        _corner_with([3.0, 1.0], (2, 2), 1),
+        _corner_with([2.0, 2.0, 1.0], (3, 3), 2),
+        _corner_with([7.0], (1, 1), 3),
+        _corner_with([4.0, 1.0], (2, 3), 4),
+    ])
+    spec = ctmrg.corner_spectra(env, 4)
+    expect = [[0.75, 0.25, 0.0, 0.0], [0.4, 0.4, 0.2, 0.0], [1.0, 0.0, 0.0, 0.0], [0.8, 0.2, 0.0, 0.0]]
+    for s, e in zip(spec, expect):
+        assert s.shape == (4,)
+        assert np.allclose(s, e, rtol=0, atol=1e-14)
+    # more singular values than chi: nothing is cut off (length = their count)
+    spec2 = ctmrg.corner_spectra(env, 2)
+    assert len(spec2[1]) == 3 and np.allclose(spec2[1], [0.4, 0.4, 0.2], atol=1e-14)
+
+
+def test_spectra_delta_known_values():
+    """delta = max over the corners of the L2 distance of the padded vectors:
+    hand-computed distances for two sets of known corner spectra (a max-
+    instead of a sum-normalisation, an L1 distance or a missing zero padding
+    each give a different number)."""
+    old = ctmrg.corner_spectra(_env_with_corners([
+        _corner_with([3.0, 1.0], (2, 2), 5),
+        _corner_with([1.0, 1.0], (2, 2), 6),
+        _corner_with([2.0, 2.0, 1.0], (3, 3), 7),
+        _corner_with([1.0], (1, 1), 8),
+    ]), 4)
+    new = ctmrg.corner_spectra(_env_with_corners([
+        _corner_with([1.0, 1.0], (2, 2), 9),      # (.5 .5 0 0): |(.25 -.25 0 0)| = sqrt(.125)
+        _corner_with([1.0, 1.0], (2, 2), 10),     # unchanged
+        _corner_with([3.0, 1.0, 1.0], (3, 3), 11),  # (.6 .2 .2 0): |(-.2 .2 0 0)| = sqrt(.08)
+        _corner_with([1.0, 1.0, 1.0, 1.0], (4, 4), 12),  # (.25 x4): |(.75 -.25 -.25 -.25)| = sqrt(.75)
+    ]), 4)
+    per_corner = [0.35355339059327373, 0.0, 0.28284271247461906, 0.8660254037844386]
+    for so, sn, want in zip(old, new, per_corner):
+        assert abs(float(np.linalg.norm(so - sn)) - want) < 1e-14
+    assert abs(ctmrg.spectra_delta(old, new) - 0.8660254037844386) < 1e-14
+    # vectors of different lengths (bond still growing) are compared after
+    # zero padding: (1) against (.5 .5) is |(.5 -.5)| = sqrt(.5)
+    a = [np.array([1.0])] * 4
+    b = [np.array([0.5, 0.5])] * 4
+    assert abs(ctmrg.spectra_delta(a, b) - 0.7071067811865476) < 1e-15
+
+
+@pytest.mark.parametrize("form", ["dense", "z2"])
+def test_product_state_corner_spectra_are_one_state(form):
+    """A product state has rank-one corners from the start: every corner
+    spectrum is (1, 0, ...) and delta is zero after every iteration."""
+    v = np.array([0.6, -0.8])
+    A = inputs.product_state(v, 2)
+    o = ctmrg.Run(4, form, A=A).step(3)
+    for s in o._spec:
+        assert abs(s[0] - 1.0) < 1e-14 and np.abs(s[1:]).max() < 1e-14
+    assert max(o.deltas) < 1e-14
