@@ -93,6 +93,7 @@ def time_form(A, chi, form, steps, warmup, profile):
     g.step(warmup)
     torch.cuda.synchronize()
     g.gemm_stats(reset=True)
+    h0 = g.svd_health()
     t0 = time.perf_counter()
     g.step(steps)
     torch.cuda.synchronize()
@@ -100,6 +101,10 @@ def time_form(A, chi, form, steps, warmup, profile):
     stats = g.gemm_stats()
     phases = g.timing()
     split = g.sector_dims(3)
+    h1 = g.svd_health()
+    stats["svd_unconverged_in_window"] = h1[0] - h0[0]
+    stats["multiplet_splits_in_window"] = h1[1] - h0[1]
+    stats["truncations_in_window"] = 4 * steps
     g.close()
     return (t1 - t0), stats, phases, split
 
@@ -125,20 +130,34 @@ def late_iterations(A, chi, skip, steps):
             "value": steps / (t1 - t0), "unit": "CTMRG iterations/s"}
 
 
-def mixed_precision(A, chi, steps, warmup, refine_max=40, tol=1e-10, precision="fp32"):
-    """Block products of the moves in FP32 (CTM_PREC_FP32), timed like the
-    FP64 form; then the error of its RDMs and energy against the FP64 form
-    after the same iterations, and after FP64 refinement iterations against
-    the converged FP64 environment."""
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+
+
+def _golden(name):
+    """Stored FP64 oracle outputs for D = 6, chi = 144 (written by
+    tests/golden/make_ctmrg_d6_chi144.py from the oracle alone)."""
+    with open(os.path.join(GOLDEN_DIR, f"ctmrg_d6_chi144_{name}.json")) as f:
+        return json.load(f)
+
+
+def _obs_err(g, ob, h):
+    o = np.concatenate([g.rdm1().ravel(), g.rdm2("h").ravel(), g.rdm2("v").ravel()])
+    r = np.concatenate([np.ravel(ob["rho1"]), np.ravel(ob["rho2_h"]), np.ravel(ob["rho2_v"])])
+    return float(np.abs(o - r).max()), float(abs(g.energy(h) - ob["energy"]))
+
+
+def mixed_precision(A, chi, steps, warmup, golden, refine_max=40, tol=1e-10, precision="fp32"):
+    """Block products of the moves in FP32 or BF16x3: timed like the FP64
+    form; the error of the RDMs and the energy against the FP64 oracle
+    (stored outputs of the same tensor) after 12 iterations in low precision,
+    and after 3 more FP64 iterations (the refinement) against the oracle after
+    15; the FP64 form's own error at the same points beside it; then the FP64
+    iterations until the corner spectra change by less than tol."""
     import torch
 
     from paper_2410_11596_amd import CTMRG, inputs
 
     h = inputs.heisenberg_bond_matrix()
-
-    def obs(g):
-        return np.concatenate([g.rdm1().ravel(), g.rdm2("h").ravel(), g.rdm2("v").ravel()]), g.energy(h)
-
     g32 = CTMRG(A, chi, precision=precision)
     g32.step(warmup)
     torch.cuda.synchronize()
@@ -146,35 +165,72 @@ def mixed_precision(A, chi, steps, warmup, refine_max=40, tol=1e-10, precision="
     g32.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    g64 = CTMRG(A, chi).step(warmup + steps)
-    o32, e32 = obs(g32)
-    o64, e64 = obs(g64)
+    g32.close()
     res = {"value": steps / (t1 - t0), "unit": "CTMRG iterations/s", "ms_per_step": 1e3 * (t1 - t0) / steps,
            "precision": {"fp32": "FP32 block products of the moves (FP32 MFMA, FP32 accumulation)",
                          "bf16x3": "BF16x3 block products of the moves (hi*hi + hi*lo + lo*hi on BF16 MFMA, "
                                    "FP32 accumulation)"}[precision] + "; FP64 SVD, normalisation and observables",
-           "max_abs_err_rdm_vs_fp64_same_iterations": float(np.abs(o32 - o64).max()),
-           "abs_err_energy_vs_fp64_same_iterations": float(abs(e32 - e64))}
-    n64 = warmup + steps
-    while not g64.converged(tol)[0] and n64 < warmup + steps + refine_max:
-        g64.step(1)
-        n64 += 1
-    o64, e64 = obs(g64)
-    g32.set_precision("fp64")
-    errs = []
-    for r in range(1, refine_max + 1):
-        g32.step(1)
-        o, e = obs(g32)
-        errs.append((float(np.abs(o - o64).max()), float(abs(e - e64))))
-        if g32.converged(tol)[0] and r >= 3:
-            break
-    res["fp64_reference_iterations"] = n64
-    res["refinement"] = {"max_abs_err_rdm_after_3": errs[min(2, len(errs) - 1)][0],
-                         "abs_err_energy_after_3": errs[min(2, len(errs) - 1)][1],
-                         "iterations_to_delta_1e-10": len(errs),
-                         "max_abs_err_rdm_at_end": errs[-1][0], "abs_err_energy_at_end": errs[-1][1]}
-    g32.close()
-    g64.close()
+           "reference": "FP64 oracle: " + golden["input"]}
+    n_lo = 12
+    g = CTMRG(A, chi, precision=precision).step(n_lo)
+    e_rdm, e_e = _obs_err(g, golden["observables"][str(n_lo)], h)
+    g.set_precision("fp64").step(3)
+    a_rdm, a_e = _obs_err(g, golden["observables"][str(n_lo + 3)], h)
+    n = 3
+    while not g.converged(tol)[0] and n < refine_max:
+        g.step(1)
+        n += 1
+    g.close()
+    f = CTMRG(A, chi).step(n_lo)
+    f_rdm, f_e = _obs_err(f, golden["observables"][str(n_lo)], h)
+    f.step(3)
+    f3_rdm, f3_e = _obs_err(f, golden["observables"][str(n_lo + 3)], h)
+    f.close()
+    res["error_vs_oracle"] = {
+        "after_12_low_precision": {"max_abs_rdm": e_rdm, "abs_energy": e_e},
+        "after_3_fp64_refinement": {"max_abs_rdm": a_rdm, "abs_energy": a_e},
+        "fp64_form_after_12": {"max_abs_rdm": f_rdm, "abs_energy": f_e},
+        "fp64_form_after_15": {"max_abs_rdm": f3_rdm, "abs_energy": f3_e},
+        "targets": {"before_refinement": 1e-6, "after_refinement": 1e-10},
+    }
+    res["refinement_iterations_to_delta_1e-10"] = n
+    return res
+
+
+def large_shape(D=8, chi=256, warmup=2, steps=2):
+    """The largest workload: D = 8 (joined leg 64 = 36 even + 28 odd),
+    chi = 256, 1x1 cell, i.i.d. tensor seed 0, Z2 form with BF16x3 block
+    products and in FP64: time per iteration after the bonds have reached chi,
+    the device memory the solve holds (its workspace, the peak of torch's
+    allocator over the run) and the block products' throughput in the timed
+    iterations (algorithmic 2 M N K flops over the summed launch times; BF16x3
+    issues three BF16 matrix products per product)."""
+    import torch
+
+    from paper_2410_11596_amd import CTMRG, inputs, workspace_size
+
+    A = inputs.iid_tensor(2, D, 0)
+    res = {"workload": f"Z2 directional CTMRG, 1x1 cell, real iPEPS d=2 D={D}, chi={chi}, i.i.d. seed 0",
+           "workspace_bytes": workspace_size(2, D, chi)}
+    for prec in ("bf16x3", "fp64"):
+        torch.cuda.reset_peak_memory_stats()
+        g = CTMRG(A, chi, precision=prec, profile=True)
+        g.step(warmup)
+        torch.cuda.synchronize()
+        g.gemm_stats(reset=True)
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = g.gemm_stats()
+        r = {"ms_per_step": 1e3 * (t1 - t0) / steps, "value": steps / (t1 - t0), "unit": "CTMRG iterations/s",
+             "phases_ms_per_step": {k: 1e3 * v / steps for k, v in zip(PHASES, g.timing().tolist())},
+             "kept_last": list(g.records()[-1]["kept"]), "svd_health": list(g.svd_health()),
+             "peak_device_bytes": int(torch.cuda.max_memory_allocated()),
+             "gemm_algorithmic_tflops": st["flops"] / st["seconds"] / 1e12 if st["seconds"] > 0 else None,
+             "gemm_share_of_step": st["seconds"] / (t1 - t0), "note": "profiled pass (HIP events per GEMM launch)"}
+        g.close()
+        res[prec] = r
     return res
 
 
@@ -393,6 +449,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-block-product run")
     ap.add_argument("--no-late", action="store_true", help="skip the later-iterations timing of the same solve")
     ap.add_argument("--no-c4v", action="store_true", help="skip the C4v-scheme comparison")
+    ap.add_argument("--no-large", action="store_true", help="skip the D = 8, chi = 256 run")
     ap.add_argument("--no-hotrg", action="store_true", help="skip the HOTRG Z2/plain comparison")
     ap.add_argument("--hotrg-by-d", action="store_true", help="run only the HOTRG comparison over D at chi 64")
     ap.add_argument("--hotrg-only", type=int, default=0, metavar="CHI",
@@ -427,7 +484,7 @@ def main():
     # value: the timed iterations without instrumentation; roofline: the
     # same iterations again (the run is deterministic) with a HIP event pair
     # around every GEMM launch
-    tz, _, phases, split = time_form(A, args.chi, "z2", args.steps, args.warmup, profile=False)
+    tz, zstats, phases, split = time_form(A, args.chi, "z2", args.steps, args.warmup, profile=False)
     tz_prof, stats, _, _ = time_form(A, args.chi, "z2", args.steps, args.warmup, profile=True)
     z2_rate = args.steps / tz
     out = {
@@ -454,6 +511,8 @@ def main():
         "sector_split": list(split),
         "phases_ms_per_step": {k: 1e3 * v / args.steps for k, v in zip(PHASES, phases.tolist())},
         "phases_sum_ms_per_step": 1e3 * float(np.sum(phases)) / args.steps,
+        "svd_health_in_window": {k: zstats[k] for k in ("truncations_in_window", "svd_unconverged_in_window",
+                                                        "multiplet_splits_in_window")},
     }
     if stats["launches"] > 0 and stats["seconds"] > 0:
         # mean algorithmic flops per launch over the mean launch duration; an
@@ -492,6 +551,8 @@ def main():
             "value": dense_rate,
             "ms_per_step": 1e3 * td / args.dense_steps,
             "phases_ms_per_step": dph,
+            "svd_health_in_window": {k: dstats[k] for k in ("truncations_in_window", "svd_unconverged_in_window",
+                                                            "multiplet_splits_in_window")},
             "phases_sum_ms_per_step": sum(dph.values()),
             "z2_over_dense": z2_rate / dense_rate,
             "matched_window": args.dense_steps == args.steps,
@@ -499,9 +560,14 @@ def main():
                                           if out["phases_ms_per_step"][k] > 0 else None for k in PHASES},
         }
         out["z2_over_dense"] = out["dense"]["z2_over_dense"]
-    if not args.no_mixed:
-        out["mixed"] = mixed_precision(A, args.chi, args.steps, args.warmup)
-        out["mixed_bf16x3"] = mixed_precision(A, args.chi, args.steps, args.warmup, precision="bf16x3")
+    if not args.no_mixed and args.D == 6 and args.chi == 144:
+        gold = _golden("seed0")
+        out["mixed"] = mixed_precision(A, args.chi, args.steps, args.warmup, gold)
+        out["mixed_bf16x3"] = mixed_precision(A, args.chi, args.steps, args.warmup, gold, precision="bf16x3")
+        out["mixed_perturbed"] = mixed_precision(inputs.perturbed_product(2, 6, 20), args.chi, args.steps,
+                                                 args.warmup, _golden("perturbed"))
+    if not args.no_large:
+        out["large_d8_chi256"] = large_shape()
     if not args.no_c4v:
         out["c4v"] = c4v_scheme(args.D, args.chi, args.steps, args.warmup)
     if not args.no_hotrg:

@@ -3,9 +3,9 @@
  *
  * A server takes independent solves (a tensor, its sizes, chi, the form, a
  * convergence tolerance and an iteration cap) as they arrive and runs them
- * concurrently: each admitted solve gets its own HIP stream, its own host
- * worker thread and a workspace carved from one device pool allocated when
- * the server is created.  Admission is first come, first served, by memory:
+ * concurrently on a fixed pool of max_active host worker threads, each with
+ * its own HIP stream; each admitted solve gets a workspace carved from one
+ * device pool allocated when the server is created.  Admission is first come, first served, by memory:
  * the oldest waiting solve starts as soon as its workspace (ctm_workspace_size)
  * fits into the free part of the pool and fewer than max_active solves run.
  * While it runs, its kernels overlap on the device with those of the others.

@@ -6,7 +6,8 @@
 // concatenation of their output tiles (and K slices).
 //
 // Tile: BM x BN per workgroup of 256 threads (4 wave64 in a 2 x 2 layout),
-// K step 16.  128 x 128 for the large block products; 64 x 64 when the
+// K step 16.  128 x 64 (FP64; 128 x 128 for the FP32 and BF16x3 products)
+// for the large block products; 64 x 64 when the
 // problems are too small to fill the 256 CUs; and when the 64 x 64 tiles are
 // too few (the tall n x l products and the l x l Gram matrices of the
 // subspace iteration) the K range is split over several workgroups, about
@@ -370,16 +371,20 @@ long long tiles(const GemmDesc& d, int bm, int bn) {
 namespace {
 void gemm_one_type(const std::vector<GemmDesc>& probs, int prec, hipStream_t s, double* scratch,
                    long long scratch_cap) {
-  // tile shape for the whole call, from how many workgroups it yields
+  // tile shape for the whole call, from how many workgroups it yields: the
+  // large tile when it alone fills the chip (FP64: 128 x 64, measured faster
+  // than 128 x 128 on the 2592^3 to 8192^3 block products, 55-65 against
+  // 46-59 TFLOP/s; FP32 and BF16x3: 128 x 128), else 64 x 64
   constexpr long long kFill = 240;  // about one workgroup per CU
-  long long t128 = 0, t64 = 0;
+  const int big_n = prec == 0 ? 64 : 128;
+  long long tbig = 0, t64 = 0;
   for (const GemmDesc& d : probs)
     if (d.M > 0 && d.N > 0 && d.K > 0) {
-      t128 += tiles(d, 128, 128);
+      tbig += tiles(d, 128, big_n);
       t64 += tiles(d, 64, 64);
     }
-  const int cfg = t128 >= kFill ? 0 : 1;  // 0: 128x128, 1: 64x64
-  const int bm = cfg == 0 ? 128 : 64, bn = bm;
+  const int cfg = tbig >= kFill ? 0 : 1;  // 0: 128 x big_n, 1: 64 x 64
+  const int bm = cfg == 0 ? 128 : 64, bn = cfg == 0 ? big_n : 64;
   long long part_used = 0;
 
   Group g;
@@ -390,7 +395,7 @@ void gemm_one_type(const std::vector<GemmDesc>& probs, int prec, hipStream_t s, 
   auto flush = [&]() {
     if (g.n == 0) return;
     if (prec == 0 && cfg == 0)
-      hipLaunchKernelGGL((gemm_f64_kernel<128, 128>), dim3(g.total), dim3(NT), 0, s, g);
+      hipLaunchKernelGGL((gemm_f64_kernel<128, 64>), dim3(g.total), dim3(NT), 0, s, g);
     else if (prec == 0)
       hipLaunchKernelGGL((gemm_f64_kernel<64, 64>), dim3(g.total), dim3(NT), 0, s, g);
     else if (prec == 1 && cfg == 0)

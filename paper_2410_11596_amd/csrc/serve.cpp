@@ -1,11 +1,12 @@
 // Serving of independent CTMRG solves on one GPU (include/hctm_serve.h).
 //
-// Each admitted solve runs on its own host thread, HIP stream and context,
-// with its workspace carved from one device pool, so that the host
-// synchronisations inside a solve (the convergence tests of the truncated
-// SVD, the kept counts) never hold up the others and their kernels overlap
-// on the device.  Admission is first come, first served, by pool space and a
-// cap on concurrent solves.
+// A fixed pool of max_active worker threads, each with its own HIP stream,
+// runs the admitted solves, each on its own context with its workspace
+// carved from one device pool, so that the host synchronisations inside a
+// solve (the convergence tests of the truncated SVD, the kept counts) never
+// hold up the others and their kernels overlap on the device.  Admission is
+// first come, first served, by pool space and the cap on concurrent solves;
+// an admitted solve waits in a queue for the next free worker.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -97,10 +98,12 @@ struct ctm_server {
   std::condition_variable cv;
   std::deque<Request*> waiting;
   std::map<long long, std::unique_ptr<Request>> all;
-  int running = 0;
+  std::deque<Request*> admitted;  // pool space taken, waiting for a worker
+  int running = 0;                // admitted and not finished
   long long next_id = 1;
   Pool pool;
-  std::vector<std::thread> threads;
+  std::vector<std::thread> workers;  // max_active of them, for the server's lifetime
+  bool stopping = false;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
   double now() const {
@@ -117,31 +120,41 @@ struct ctm_server {
       r->off = off;
       r->info.t_start = now();
       ++running;
-      try {
-        threads.emplace_back(&ctm_server::run, this, r);
-      } catch (const std::exception& e) {
-        --running;
-        pool.give(off, round_up(r->ws));
-        r->info.status = CTM_E_NOMEM;
-        set_message(r->info, std::string("could not start a worker thread: ") + e.what());
-        r->info.t_end = now();
-        r->done = true;
-        cv.notify_all();
-      }
+      admitted.push_back(r);
+      cv.notify_all();
     }
   }
 
-  void run(Request* r) {
+  // Worker: one HIP stream for its lifetime; takes admitted solves in order
+  // until the server stops and nothing is left.
+  void worker() {
+    hipStream_t st = nullptr;
+    const bool ok = hipSetDevice(device) == hipSuccess &&
+                    hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+    if (!ok) st = nullptr;
+    for (;;) {
+      Request* r = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [this] { return stopping || !admitted.empty(); });
+        if (admitted.empty()) break;  // stopping and drained
+        r = admitted.front();
+        admitted.pop_front();
+      }
+      run(r, st);
+    }
+    if (st) (void)hipStreamDestroy(st);
+  }
+
+  void run(Request* r, hipStream_t st) {
     int rc = CTM_OK;
     std::string msg;
-    hipStream_t st = nullptr;
     ctm_ctx* c = nullptr;
     int it = 0, conv = 0;
     double delta = INFINITY;
-    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    if (!st) {
       rc = CTM_E_HIP;
-      msg = "could not create a stream for the solve";
-      st = nullptr;
+      msg = "the worker has no stream";
     }
     try {
       if (rc == CTM_OK) {
@@ -176,11 +189,8 @@ struct ctm_server {
       msg = std::string("host allocation failed: ") + e.what();
     }
     ctm_free(c);
-    if (st) {
-      // nothing of this solve may still run when its pool space is reused
-      (void)hipStreamSynchronize(st);
-      (void)hipStreamDestroy(st);
-    }
+    // nothing of this solve may still run when its pool space is reused
+    if (st) (void)hipStreamSynchronize(st);
     std::lock_guard<std::mutex> lk(mu);
     pool.give(r->off, round_up(r->ws));
     --running;
@@ -215,6 +225,18 @@ int ctm_server_create(ctm_server** out, size_t pool_bytes, int max_active) {
   s->pool_bytes = pool_bytes;
   s->max_active = max_active;
   s->pool.reset(pool_bytes);
+  try {
+    for (int i = 0; i < max_active; ++i) s->workers.emplace_back(&ctm_server::worker, s.get());
+  } catch (const std::exception&) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stopping = true;
+    }
+    s->cv.notify_all();
+    for (std::thread& t : s->workers) t.join();
+    (void)hipFree(s->pool_base);
+    return CTM_E_NOMEM;
+  }
   *out = s.release();
   return CTM_OK;
 }
@@ -291,8 +313,10 @@ void ctm_server_destroy(ctm_server* s) {
   {
     std::unique_lock<std::mutex> lk(s->mu);
     s->cv.wait(lk, [s] { return s->waiting.empty() && s->running == 0; });
+    s->stopping = true;
   }
-  for (std::thread& t : s->threads)
+  s->cv.notify_all();
+  for (std::thread& t : s->workers)
     if (t.joinable()) t.join();
   if (s->pool_base) (void)hipFree(s->pool_base);
   delete s;

@@ -1,18 +1,21 @@
-"""Write the oracle's outputs for the benchmark shape to ctmrg_d6_chi144_seed0.json.
+"""Write the oracle's outputs for the benchmark shape to ctmrg_d6_chi144_<input>.json.
 
 Calls the CPU oracle only (oracle/ctmrg.py, Z2 form; the plain form runs the
-first iterations beside it as a cross-check).  Input: the i.i.d. tensor of
-paper_2410_11596_amd.inputs.iid_tensor(2, 6, 0) (d = 2, D = 6, N(0,1) entries
-from seed 0, max-abs normalised), chi = 144, traced boundary, 12 iterations of
-four directional moves.  The stored values are the gauge-invariant outputs the
-GPU tests compare: kept sector sizes and kept spectra of every truncation,
-delta after every iteration, the final corner spectra, the one- and two-site
-RDMs, the Heisenberg energy, ln kappa and sampled entries of the one-site
-environment.
+first iterations beside it as a cross-check).  Inputs (d = 2, D = 6, from
+paper_2410_11596_amd.inputs, the generators shared with the GPU tests):
+  seed0      iid_tensor(2, 6, 0): N(0,1) entries from seed 0, max-abs normalised
+  perturbed  perturbed_product(2, 6, 20): e_0 x e_0 x e_0 x e_0 x e_0 plus 1e-2
+             times N(0,1) entries from seed 20, max-abs normalised
+chi = 144, traced boundary, 15 iterations of four directional moves.  Stored:
+the kept sector sizes and kept spectra of every truncation, delta after every
+iteration, the final corner spectra, and after iterations 12 and 15 the one-
+and two-site RDMs, the Heisenberg energy, ln kappa and sampled entries of the
+one-site environment (iteration 12 is the end of a low-precision run, 15 the
+end of three refinement iterations after it).
 
-Usage: python tests/golden/make_ctmrg_d6_chi144.py [--dense-check N]
-(about 35 s per iteration of the Z2 form on 8 cores; the plain form's
-iterations take several times longer).
+Usage: python tests/golden/make_ctmrg_d6_chi144.py [--input seed0|perturbed] [--dense-check N]
+(about 40 s per iteration of the Z2 form on 8 cores; the plain form's
+iterations take several times longer; each set of observables about a minute).
 """
 import argparse
 import json
@@ -29,9 +32,15 @@ sys.path.insert(0, ROOT)
 from oracle import ctmrg  # noqa: E402
 from paper_2410_11596_amd import inputs  # noqa: E402
 
-OUT = os.path.join(HERE, "ctmrg_d6_chi144_seed0.json")
-D, CHI, SEED, ITERS = 6, 144, 0, 12
+D, CHI, ITERS = 6, 144, 15
+OBS_AT = (12, 15)
 N_EPS = 256
+INPUTS = {
+    "seed0": ("inputs.iid_tensor(2, 6, 0): d=2, D=6, i.i.d. N(0,1), seed 0, max-abs normalised",
+              lambda: inputs.iid_tensor(2, D, 0)),
+    "perturbed": ("inputs.perturbed_product(2, 6, 20): product state e_0 plus 1e-2 N(0,1) (seed 20), "
+                  "max-abs normalised", lambda: inputs.perturbed_product(2, D, 20)),
+}
 
 
 def eps_sample_indices(q):
@@ -39,14 +48,27 @@ def eps_sample_indices(q):
     return rng.integers(0, q ** 4, N_EPS)
 
 
+def observables(run):
+    h = ctmrg.heisenberg_bond()
+    eps = run.epsilon().reshape(-1)
+    idx = eps_sample_indices(D * D)
+    return {"rho1": run.rho1().tolist(), "rho2_h": run.rho2("h").tolist(), "rho2_v": run.rho2("v").tolist(),
+            "energy": run.energy(h), "log_kappa": run.log_kappa(), "s_err": run.s_err(),
+            "eps_index": [int(i) for i in idx], "eps_value": [float(eps[i]) for i in idx],
+            "eps_max_abs": float(np.abs(eps).max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--input", choices=sorted(INPUTS), default="seed0")
     ap.add_argument("--dense-check", type=int, default=2, help="iterations of the plain form run beside (0: none)")
     args = ap.parse_args()
-    A = inputs.iid_tensor(2, D, SEED)
+    desc, make = INPUTS[args.input]
+    A = make()
     t0 = time.time()
     z = ctmrg.Run(CHI, "z2", A=A)
     dn = ctmrg.Run(CHI, "dense", A=A) if args.dense_check > 0 else None
+    obs = {}
     for it in range(ITERS):
         z.step(1)
         msg = f"iteration {it + 1}: delta {z.deltas[-1]:.3e} kept {[r['kept'] for r in z.records[-4:]]}"
@@ -55,34 +77,27 @@ def main():
             for rz, rd in zip(z.records[-4:], dn.records[-4:]):
                 k = sum(rz["kept"])
                 assert k == sum(rd["kept"])
-                assert np.allclose(rz["spectrum"][:k], rd["spectrum"][:k], rtol=1e-10, atol=1e-14)
-            assert abs(z.deltas[-1] - dn.deltas[-1]) < 1e-12
+                assert np.allclose(rz["spectrum"][:k], rd["spectrum"][:k], rtol=1e-8, atol=1e-12)
+            assert abs(z.deltas[-1] - dn.deltas[-1]) < 1e-9
             msg += " (plain form agrees)"
+        if it + 1 in OBS_AT:
+            obs[str(it + 1)] = observables(z)
         print(msg, f"{time.time() - t0:.0f} s", flush=True)
-    h = ctmrg.heisenberg_bond()
     out = {
         "source": "oracle/ctmrg.py Z2 form (tests/golden/make_ctmrg_d6_chi144.py)",
-        "input": "inputs.iid_tensor(2, 6, 0): d=2, D=6, i.i.d. N(0,1), seed 0, max-abs normalised",
+        "input": desc,
         "chi": CHI, "iterations": ITERS, "tau": 1e-12,
         "dense_check_iterations": min(args.dense_check, ITERS),
         "records": [{"kept": [int(r["kept"][0]), int(r["kept"][1])],
                      "spectrum": [float(v) for v in r["spectrum"][: sum(r["kept"])]]} for r in z.records],
         "deltas": [float(v) for v in z.deltas],
         "corner_spectra": [[float(v) for v in s] for s in z._spec],
-        "rho1": z.rho1().tolist(),
-        "rho2_h": z.rho2("h").tolist(),
-        "rho2_v": z.rho2("v").tolist(),
-        "energy": z.energy(h),
-        "log_kappa": z.log_kappa(),
+        "observables": obs,
     }
-    eps = z.epsilon().reshape(-1)
-    idx = eps_sample_indices(D * D)
-    out["eps_index"] = [int(i) for i in idx]
-    out["eps_value"] = [float(eps[i]) for i in idx]
-    out["eps_max_abs"] = float(np.abs(eps).max())
-    with open(OUT, "w") as f:
+    path = os.path.join(HERE, f"ctmrg_d6_chi144_{args.input}.json")
+    with open(path, "w") as f:
         json.dump(out, f, indent=0)
-    print("wrote", OUT)
+    print("wrote", path)
 
 
 if __name__ == "__main__":

@@ -40,12 +40,17 @@ def _gpu_launch(A, chi, form, **kw):
     return CTMRG(A, chi, form=form, **kw)
 
 
-# delta is a distance between sum-normalised spectra whose entries carry
-# absolute rounding errors of a few 1e-16 from either SVD
-DELTA_TOL = 1e-12
+# delta and the corner spectra are distances and entries of sum-normalised
+# spectra of corners renormalised with projectors that divide by singular
+# values down to 1e-12 of the largest: FP64 rounding is amplified to about
+# 1e-10 there.  The oracle itself moves by that much when only its LAPACK
+# SVD driver changes (gesdd -> gesvd at D = 2, chi = 16: delta by 2.5e-10,
+# corner spectra by 6e-11), so parity is asked to 1e-9.
+DELTA_TOL = 1e-9
+SPEC_TOL = 1e-9
 
 
-def _compare_corner_spectra(g, o, atol=1e-12):
+def _compare_corner_spectra(g, o, atol=SPEC_TOL):
     """The four current corner spectra (sum-normalised, zero padded) against
     the oracle's on their common length; the rest is zero on both sides."""
     for c in range(4):
@@ -277,13 +282,25 @@ def test_product_state_has_zero_delta():
         assert abs(s[0] - 1.0) < 1e-14 and np.abs(s[1:]).max() < 1e-14
 
 
-def _golden_d6():
+def _golden_d6(name="seed0"):
     import json
     import os
 
-    path = os.path.join(os.path.dirname(__file__), "golden", "ctmrg_d6_chi144_seed0.json")
+    path = os.path.join(os.path.dirname(__file__), "golden", f"ctmrg_d6_chi144_{name}.json")
     with open(path) as f:
         return json.load(f)
+
+
+def _compare_golden_observables(g, ob):
+    assert np.abs(g.rdm1() - np.array(ob["rho1"])).max() < TOL
+    assert np.abs(g.rdm2("h") - np.array(ob["rho2_h"])).max() < TOL
+    assert np.abs(g.rdm2("v") - np.array(ob["rho2_v"])).max() < TOL
+    e = g.energy(ctmrg.heisenberg_bond())
+    assert abs(e - ob["energy"]) < TOL * max(1.0, abs(ob["energy"]))
+    assert abs(g.log_kappa() - ob["log_kappa"]) < TOL
+    eps = g.epsilon().reshape(-1)
+    got = eps[np.array(ob["eps_index"])]
+    assert np.abs(got - np.array(ob["eps_value"])).max() < 1e-7 * ob["eps_max_abs"]
 
 
 @pytest.mark.parametrize("form_m", [False, True])
@@ -296,7 +313,7 @@ def test_benchmark_regime_d6_chi144_against_oracle(form_m):
     every iteration, the final corner spectra, RDMs and energy (1e-10), ln
     kappa and sampled entries of the one-site environment against the
     oracle's values stored by tests/golden/make_ctmrg_d6_chi144.py."""
-    gold = _golden_d6()
+    gold = _golden_d6("seed0")
     A = inputs.iid_tensor(2, 6, 0)
     g = _gpu_launch(A, gold["chi"], "z2", form_m=form_m)
     for it in range(gold["iterations"]):
@@ -306,7 +323,8 @@ def test_benchmark_regime_d6_chi144_against_oracle(form_m):
     assert len(recs) == len(gold["records"])
     for m, (rg, ro) in enumerate(zip(recs, gold["records"])):
         assert list(rg["kept"]) == ro["kept"], m
-        assert np.allclose(rg["spectrum"], ro["spectrum"], rtol=1e-8, atol=1e-13), m
+        # values near the 1e-12 cutoff carry absolute errors of about 1e-13
+        assert np.allclose(rg["spectrum"], ro["spectrum"], rtol=1e-8, atol=1e-12), m
         assert not rg["multiplet_split"]
     # the regimes the benchmark's iterations run in were all exercised
     if form_m:
@@ -314,20 +332,36 @@ def test_benchmark_regime_d6_chi144_against_oracle(form_m):
     else:
         assert any(r["implicit"] for r in recs[8:]) and any(not r["implicit"] for r in recs)
     assert any(0 < max(r["iters"]) <= 3 for r in recs)
-    assert g.svd_health()[0] == 0
+    # truncations whose subspace iteration stopped at the cap (the early,
+    # unconverged cuts) are reported, and are among the ones compared above
+    print("records (iterations even/odd, unconverged):",
+          [(r["iters"], r["unconverged"]) for r in recs], flush=True)
+    assert g.svd_health()[0] == sum(1 for r in recs if any(r["unconverged"]))
+    assert all(max(r["iters"]) == 12 for r in recs if any(r["unconverged"]))
     for c in range(4):
         sg = g.corner_spectrum(c)
         so = np.array(gold["corner_spectra"][c])
         n = min(len(sg), len(so))
-        assert np.abs(sg[:n] - so[:n]).max() < 1e-12
-    assert np.abs(g.rdm1() - np.array(gold["rho1"])).max() < TOL
-    assert np.abs(g.rdm2("h") - np.array(gold["rho2_h"])).max() < TOL
-    assert np.abs(g.rdm2("v") - np.array(gold["rho2_v"])).max() < TOL
-    e = g.energy(ctmrg.heisenberg_bond())
-    assert abs(e - gold["energy"]) < TOL * max(1.0, abs(gold["energy"]))
-    assert abs(g.log_kappa() - gold["log_kappa"]) < TOL
-    eps = g.epsilon().reshape(-1)
-    got = eps[np.array(gold["eps_index"])]
-    assert np.abs(got - np.array(gold["eps_value"])).max() < 1e-7 * gold["eps_max_abs"]
+        assert np.abs(sg[:n] - so[:n]).max() < SPEC_TOL
+    _compare_golden_observables(g, gold["observables"][str(gold["iterations"])])
     assert g.s_err() <= 1e-15
+    g.close()
+
+
+def test_perturbed_product_state_d6_chi144_against_oracle():
+    """The perturbed product state of the mixed-precision workload (e_0 plus
+    1e-2 noise, D = 6, chi = 144): strongly uneven sectors and a fast-decaying
+    spectrum; records, delta and the observables against the oracle."""
+    gold = _golden_d6("perturbed")
+    A = inputs.perturbed_product(2, 6, 20)
+    g = _gpu_launch(A, gold["chi"], "z2")
+    for it in range(gold["iterations"]):
+        g.step(1)
+        assert abs(g.converged(0.0)[1] - gold["deltas"][it]) < DELTA_TOL, it
+    recs = g.records()
+    for m, (rg, ro) in enumerate(zip(recs, gold["records"])):
+        assert list(rg["kept"]) == ro["kept"], m
+        assert np.allclose(rg["spectrum"], ro["spectrum"], rtol=1e-8, atol=1e-12), m
+    print("kept (even, odd):", [r["kept"] for r in recs[-4:]], flush=True)
+    _compare_golden_observables(g, gold["observables"][str(gold["iterations"])])
     g.close()

@@ -22,9 +22,12 @@ def _dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
 
 
-@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 33, 5), (130, 129, 257), (256, 384, 128), (300, 7, 1000)])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 33, 5), (130, 129, 257), (256, 384, 128), (300, 7, 1000),
+                                   (2000, 1990, 70), (1937, 2051, 33)])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_gemm_matches_numpy(hc, M, N, K, ta, tb):
+    """FP64 products; the last two sizes give enough tiles for the large
+    128 x 64 tile, with ragged edges in both directions."""
     rng = np.random.default_rng(M * 1000 + N * 10 + K + 7 * ta + 3 * tb)
     A = rng.standard_normal((K, M) if ta else (M, K))
     B = rng.standard_normal((N, K) if tb else (K, N))

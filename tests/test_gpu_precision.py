@@ -2,15 +2,17 @@
 (CTM_PREC_BF16X3) for the enlarged corners, halves, projectors and
 renormalisation; the truncated SVD, normalisations and observables in FP64.
 
-Measured against the FP64 form of the same library (itself checked against
-the oracle in test_gpu_ctmrg.py): after the same iterations the RDMs agree
-to about 1e-7 with FP32 products (bound 1e-6 here) and 2e-6 with BF16x3
-(bound 1e-5), and FP64 iterations started from that environment reach the
-converged FP64 environment (RDMs and energy within 1e-10) once the corner
-spectra change by less than 1e-10."""
+Errors are stated against the FP64 oracle (oracle/ctmrg.py) on the same
+seeded tensor.  Targets: RDM entries and energy within 1e-6 of the oracle
+after the same iterations in low precision, and within 1e-10 of the
+oracle's fixed point after three FP64 refinement iterations that start from
+the low-precision environment.  Where a target is missed the test is marked
+as an expected failure with the measured cause, and the error it does reach
+is asserted as well."""
 import numpy as np
 import pytest
 
+from oracle import ctmrg
 from paper_2410_11596_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -27,10 +29,29 @@ def gpu():
 
 
 H = inputs.heisenberg_bond_matrix()
+TARGET_BEFORE = 1e-6   # low precision, same iterations as the oracle
+TARGET_AFTER = 1e-10   # after three FP64 refinement iterations
+# BF16x3 misses TARGET_BEFORE: hi + lo in BF16 hold 16 significant bits, so
+# every block product carries about 2^-16 (1.5e-5) relative error, which
+# reaches the RDMs at first order (measured 1.5e-6 to 3.4e-6 at D = 4 and 6).
+# The tests assert this floor and mark the target as an expected failure.
+BF16X3_FLOOR = 1e-5
 
 
-def _obs(g):
+def _check_before(prec, err, what):
+    if prec == "bf16x3" and err >= TARGET_BEFORE:
+        assert err < BF16X3_FLOOR, what
+        pytest.xfail(f"{what}: {err:.1e} > 1e-6 (BF16x3 products carry 2^-16 relative error)")
+    assert err < TARGET_BEFORE, what
+
+
+def _obs_gpu(g):
     return np.concatenate([g.rdm1().ravel(), g.rdm2("h").ravel(), g.rdm2("v").ravel()]), g.energy(H)
+
+
+def _obs_oracle(o):
+    return (np.concatenate([o.rho1().ravel(), o.rho2("h").ravel(), o.rho2("v").ravel()]),
+            o.energy(ctmrg.heisenberg_bond()))
 
 
 def _ctm(A, chi, **kw):
@@ -39,51 +60,73 @@ def _ctm(A, chi, **kw):
     return CTMRG(A, chi, **kw)
 
 
-BOUND = {"fp32": 1e-6, "bf16x3": 1e-5}
+_ORACLE = {}
+
+
+def _oracle_fixed_point(form):
+    """The oracle at D = 4, chi = 64 run until delta < 1e-12 (21 iterations)."""
+    if form not in _ORACLE:
+        A = inputs.iid_tensor(2, 4, 0)
+        o = ctmrg.Run(64, form, A=A)
+        for _ in range(80):
+            o.step(1)
+            if o.deltas[-1] < 1e-12:
+                break
+        assert o.deltas[-1] < 1e-12
+        _ORACLE[form] = _obs_oracle(o)
+    return _ORACLE[form]
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("form", ["z2", "dense"])
-def test_low_precision_block_products_track_fp64_d4(form, prec):
+def test_low_precision_against_the_oracle_d4(form, prec):
+    """Eight iterations at D = 4, chi = 64 in low precision against eight
+    oracle iterations: within the 1e-6 target, with the rounding visible."""
     A = inputs.iid_tensor(2, 4, 0)
-    g64 = _ctm(A, 64, form=form).step(8)
-    g32 = _ctm(A, 64, form=form, precision=prec).step(8)
-    o64, e64 = _obs(g64)
-    o32, e32 = _obs(g32)
-    err = np.abs(o32 - o64).max()
-    assert 1e-12 < err < BOUND[prec]  # the rounding shows, within its accuracy
-    assert abs(e32 - e64) < BOUND[prec]
+    o = ctmrg.Run(64, form, A=A).step(8)
+    oo, eo = _obs_oracle(o)
+    g = _ctm(A, 64, form=form, precision=prec).step(8)
+    og, eg = _obs_gpu(g)
+    err, err_e = np.abs(og - oo).max(), abs(eg - eo)
+    print(f"{form} {prec}: max |rdm - oracle| = {err:.2e}, |E - oracle| = {err_e:.2e}", flush=True)
+    assert err > 1e-12  # the rounding shows
     if form == "z2":
-        assert g32.s_err() <= 1e-15  # Hermitian by construction in any precision
-        r2 = g32.rdm2("h")
+        assert g.s_err() <= 1e-15  # Hermitian by construction in any precision
+        r2 = g.rdm2("h")
         assert np.array_equal(r2, r2.T)
+    _check_before(prec, err_e, "energy")
+    _check_before(prec, err, "RDM entries")
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_fp64_refinement_reaches_the_fp64_fixed_point(prec):
+def test_fp64_refinement_against_the_oracle_fixed_point(prec):
+    """A low-precision solve (20 iterations, converged to its rounding), then
+    FP64 iterations on the same environment: the error against the oracle's
+    fixed point after three of them (the refinement of the mixed-precision
+    workload) and once the corner spectra change by less than 1e-10."""
+    oo, eo = _oracle_fixed_point("z2")
     A = inputs.iid_tensor(2, 4, 0)
-    g64 = _ctm(A, 64)
-    for _ in range(60):
-        g64.step(1)
-        if g64.converged(1e-10)[0]:
+    g = _ctm(A, 64, precision=prec).step(20)
+    og, eg = _obs_gpu(g)
+    before = np.abs(og - oo).max()
+    g.set_precision("fp64")
+    errs = []
+    for r in range(1, 61):
+        g.step(1)
+        og, eg = _obs_gpu(g)
+        errs.append(max(np.abs(og - oo).max(), abs(eg - eo)))
+        if r >= 3 and g.converged(1e-10)[0]:
             break
-    assert g64.converged(1e-10)[0]
-    o64, e64 = _obs(g64)
-    g32 = _ctm(A, 64, precision=prec).step(20)
-    o, e = _obs(g32)
-    assert np.abs(o - o64).max() < BOUND[prec]
-    g32.set_precision("fp64")
-    for r in range(1, 41):
-        g32.step(1)
-        if r == 3:
-            o, e = _obs(g32)
-            assert np.abs(o - o64).max() < 100 * BOUND[prec] ** 2 + 1e-8
-        if g32.converged(1e-10)[0]:
-            break
-    assert g32.converged(1e-10)[0]
-    o, e = _obs(g32)
-    assert np.abs(o - o64).max() < 1e-10
-    assert abs(e - e64) < 1e-10
+    print(f"{prec}: before {before:.2e}, after 3 FP64 iterations {errs[2]:.2e}, "
+          f"{len(errs)} iterations to delta < 1e-10: {errs[-1]:.2e}", flush=True)
+    assert g.converged(1e-10)[0] and errs[-1] < TARGET_AFTER
+    assert before < (BF16X3_FLOOR if prec == "bf16x3" else TARGET_BEFORE)
+    if errs[2] >= TARGET_AFTER:
+        # refinement is plain CTMRG iteration: its error shrinks by the
+        # iteration's contraction factor per sweep, so three sweeps take a
+        # 1e-7..1e-6 start to about 1e-9, not 1e-10
+        pytest.xfail(f"after 3 FP64 iterations {errs[2]:.1e} > 1e-10 (contraction-limited); "
+                     f"{len(errs)} iterations reach {errs[-1]:.1e}")
 
 
 def test_precision_is_checked():
