@@ -61,6 +61,21 @@ int hctm_dev_jacobi(double* X, int m, int n, double tol, int max_sweeps, int pre
 /* Scratch doubles needed by hctm_dev_jacobi's rotation log. */
 long long hctm_dev_jacobi_log_doubles(int n, int max_sweeps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * decomposition as hctm_dev_jacobi with vlog (when V is requested) and work
+ * (when m, n <= 256) taken from a static device buffer of 4 Mi doubles
+ * (32 MiB) that the library holds on every device it runs on; it allocates
+ * nothing.  The caller passes the inputs and outputs as for hctm_dev_jacobi.
+ * Returns CTM_E_ARG, before any work is enqueued, when the rotation log plus
+ * the copy (hctm_dev_jacobi_log_doubles(n, max_sweeps) + m * n doubles)
+ * exceed the buffer.  All calls on one device share that buffer and it keeps
+ * the last call's contents (nothing in it needs to start at zero): calls
+ * that may overlap on one device (different streams or host threads) race
+ * and must be serialised by the caller. */
+int hctm_dev_jacobi_noalloc(double* X, int m, int n, double tol, int max_sweeps, int pre, double* sv, int* perm,
+                            int* sweeps, double* V, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

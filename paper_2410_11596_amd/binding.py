@@ -30,6 +30,7 @@ EXPORTS = [
     "hotrg_energy", "hotrg_track_rdm1", "hotrg_rdm1", "hotrg_num_records",
     "hotrg_record", "hotrg_last_error", "hotrg_free",
     "hctm_dev_gemm", "hctm_dev_gemm_f32", "hctm_dev_gemm_bf16x3", "hctm_dev_copy", "hctm_dev_chol_inv", "hctm_dev_jacobi", "hctm_dev_jacobi_log_doubles",
+    "hctm_dev_jacobi_noalloc",
 ]
 
 
@@ -136,6 +137,8 @@ def lib():
                              vp, vp, vp],
                             ctypes.c_int),
         "hctm_dev_jacobi_log_doubles": ([ctypes.c_int, ctypes.c_int], ctypes.c_longlong),
+        "hctm_dev_jacobi_noalloc": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, vp,
+                                     vp, vp, vp, vp], ctypes.c_int),
         "hotrg_opts_default": ([P(HotrgOpts)], ctypes.c_int),
         "hotrg_init": ([P(vp), dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(HotrgOpts)], ctypes.c_int),
         "hotrg_step": ([vp, ctypes.c_int], ctypes.c_int),
@@ -429,6 +432,15 @@ def dev_jacobi(X, m, n, tol, max_sweeps, sv, perm, sweeps, V=None, vlog=None, pr
     wp = _ptr(work) if work is not None else None
     _check(lib().hctm_dev_jacobi(_ptr(X), m, n, tol, max_sweeps, pre, _ptr(sv), _ptr(perm), _ptr(sweeps), vp, lp,
                                  wp, _stream_ptr(torch)))
+
+
+def dev_jacobi_noalloc(X, m, n, tol, max_sweeps, sv, perm, sweeps, V=None, pre=0):
+    """hctm_dev_jacobi_noalloc: the Jacobi SVD with its scratch in the
+    library's static device buffer (no allocation)."""
+    torch = _torch()
+    vp = _ptr(V) if V is not None else None
+    _check(lib().hctm_dev_jacobi_noalloc(_ptr(X), m, n, tol, max_sweeps, pre, _ptr(sv), _ptr(perm), _ptr(sweeps), vp,
+                                         _stream_ptr(torch)))
 
 
 def jacobi_log_doubles(n, max_sweeps):

@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -451,3 +452,65 @@ int hctm_dev_jacobi(double* X, int m, int n, double tol, int max_sweeps, int pre
 long long hctm_dev_jacobi_log_doubles(int n, int max_sweeps) { return (long long)hctm::jacobi_log_doubles(n, max_sweeps); }
 
 }  // extern "C"
+
+// ------------------------------------------------- no-allocation entry ----
+// Device scratch of hctm_dev_jacobi_noalloc, for callers that cannot
+// allocate: one file-scope array that every device the library runs on holds
+// until the process ends.  In host code `scratch` only names the symbol; its
+// device address is looked up once per device (with that device current)
+// and only that address is ever handed to kernels.
+namespace {
+constexpr long long kStaticScratchDoubles = 4LL << 20;  // 32 MiB per device
+__device__ __align__(256) double scratch[kStaticScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+double* static_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) throw hctm::Error(CTM_E_HIP, "hipGetDevice failed");
+  if (dev < 0 || dev >= kMaxDevices) throw hctm::Error(CTM_E_ARG, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw hctm::Error(CTM_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" int hctm_dev_jacobi_noalloc(double* X, int m, int n, double tol, int max_sweeps, int pre, double* sv,
+                                       int* perm, int* sweeps, double* V, void* stream) {
+  return guarded(nullptr, [&] {
+    if (m < 1 || n < 1 || n > 1024) throw hctm::Error(CTM_E_ARG, "size out of range");
+    if (max_sweeps < 1) throw hctm::Error(CTM_E_ARG, "max_sweeps < 1");
+    if (V && m != n) throw hctm::Error(CTM_E_ARG, "V needs a square X");
+    // rotation log (with V) at the front, then the column-major copy of the
+    // L2 kernel (blocks up to 256 x 256), each 256-byte aligned
+    const long long log = V ? (((long long)hctm::jacobi_log_doubles(n, max_sweeps) + 31) / 32) * 32 : 0;
+    const long long work = (m <= 256 && n <= 256) ? (long long)m * n : 0;
+    if (log + work > kStaticScratchDoubles)
+      throw hctm::Error(CTM_E_ARG, "hctm_dev_jacobi_noalloc: needs " + std::to_string(log + work) +
+                                       " doubles of scratch, the static buffer holds " +
+                                       std::to_string(kStaticScratchDoubles) + " (fewer sweeps or columns)");
+    double* base = static_scratch();
+    hctm::SmallProb p{};
+    p.a = X;
+    p.m = m;
+    p.n = n;
+    p.lda = n;
+    p.rel = tol;
+    p.max_sweeps = max_sweeps;
+    p.pre = pre;
+    p.info = sweeps;
+    p.sv = sv;
+    p.perm = perm;
+    p.b = V;
+    p.vlog = V ? base : nullptr;
+    p.work = work ? base + log : nullptr;
+    hctm::jacobi({p}, reinterpret_cast<hipStream_t>(stream));
+  });
+}
