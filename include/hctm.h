@@ -202,6 +202,45 @@ int ctm_rdm_2site(ctm_ctx* c, int x, int y, int dir, double* rho);
  * NULL pointers.  Synchronises. */
 int ctm_energy(ctm_ctx* c, const double* h, double* e);
 
+/* ---- complex tensors (Sec. II C) ---------------------------------------
+ * For a complex A the double layer a = sum_s A[s] (x) conj(A[s]) is not swap
+ * invariant, but in the eigenbasis of the swap its blocks of even total
+ * parity are real and those of odd total parity imaginary (Sec. II C), and so
+ * is every tensor of the contraction.  The library holds each such tensor as
+ * two real block tensors (the real even-total blocks and the imaginary parts
+ * of the odd-total blocks: the real representation with the extra leg of
+ * dimension 2 and the multiplication rule f of Sec. II C) and multiplies them
+ * with four half-size real block products where complex dense arithmetic
+ * needs four full-size ones.  The truncation decomposes the real matrix
+ * D^-1 M D, D = diag(i^parity), whose SVD gives that of M; every kept state is
+ * then even.  Z2 form, 1 x 1 cell, directional moves and FP64 only; the RDMs
+ * are Hermitian by construction.  ctm_step, ctm_converged,
+ * ctm_corner_spectrum, ctm_record*, ctm_sector_dims, ctm_energy (real h),
+ * ctm_timing and ctm_free apply as for a real tensor; ctm_rdm_1site/2site,
+ * ctm_env_epsilon, ctm_s_err and ctm_log_kappa return CTM_E_ARG. */
+
+/* Device bytes of a complex-tensor context (ctm_opts.workspace). */
+int ctm_workspace_size_complex(int d, int D, int chi, const ctm_opts* o, size_t* bytes);
+
+/* Create a context for the complex tensor A = A_re + i A_im (host, d*D^4
+ * doubles each, legs [s,u,l,d,r], copied).  Requires 1 <= d <= 8,
+ * 1 <= D <= 8, 1 <= chi <= 4096, finite entries; ctm_opts as for ctm_init
+ * with form CTM_FORM_Z2, a 1 x 1 cell, c4v = 0 and CTM_PREC_FP64 (else
+ * CTM_E_ARG). */
+int ctm_init_complex(ctm_ctx** out, const double* A_re, const double* A_im, int d, int D, int chi,
+                     const ctm_opts* o);
+
+/* Hermitian one-site RDM of a complex-tensor context, rho = rho_re + i rho_im
+ * (host, d*d each, row-major), trace one: the entries on and above the
+ * diagonal from the environment, the others their conjugates.  (x, y) must
+ * be (0, 0).  Synchronises. */
+int ctm_rdm_1site_complex(ctm_ctx* c, int x, int y, double* rho_re, double* rho_im);
+
+/* Hermitian two-site RDM [(s1 s2)][(s1' s2')] of a complex-tensor context
+ * (host, d^4 each), dir 0 horizontal, 1 vertical; (x, y) must be (0, 0).
+ * Synchronises. */
+int ctm_rdm_2site_complex(ctm_ctx* c, int x, int y, int dir, double* rho_re, double* rho_im);
+
 /* Release everything; NULL is accepted. */
 void ctm_free(ctm_ctx* c);
 

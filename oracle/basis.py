@@ -63,14 +63,15 @@ def leg_parity(D):
 
 
 def double_layer(A):
-    """a[U,L,Dn,R] = sum_s A[s,u,l,d,r] A[s,ub,lb,db,rb], U = u*D + ub (Fig. 1b).
+    """a[U,L,Dn,R] = sum_s A[s,u,l,d,r] conj(A[s,ub,lb,db,rb]), U = u*D + ub
+    (Fig. 1b: the ket layer A and the bra layer A^dagger).
 
-    For real A the bra tensor equals the ket tensor, so the same array is used
-    for both layers.
+    For real A the conjugate is A itself (Sec. II B), for complex A (Sec. II C)
+    the bra layer is conjugated.
     """
     d, D = A.shape[0], A.shape[1]
     q = D * D
-    a = np.einsum("sabcd,sefgh->aebfcgdh", A, A, optimize=True)
+    a = np.einsum("sabcd,sefgh->aebfcgdh", A, np.conj(A), optimize=True)
     return a.reshape(q, q, q, q)
 
 
@@ -78,7 +79,7 @@ def impurity(A, s, sp):
     """Double layer with fixed physical indices: ket s, bra sp (for RDMs)."""
     D = A.shape[1]
     q = D * D
-    x = np.einsum("abcd,efgh->aebfcgdh", A[s], A[sp])
+    x = np.einsum("abcd,efgh->aebfcgdh", A[s], np.conj(A[sp]))
     return x.reshape(q, q, q, q)
 
 

@@ -57,7 +57,7 @@ def contract(rows, cols, site, b, hole=None):
     if hole is not None:
         # open legs were stored as (U, L, D, R)
         return state
-    return float(state)
+    return state[()]  # a scalar (complex for a complex network)
 
 
 def epsilon(a, b, L):
@@ -72,7 +72,7 @@ def rdm1(a, A, b, L):
     c = L // 2
     d = A.shape[0]
     imp = lambda s, sp: basis.impurity(A, s, sp)
-    rho = np.zeros((d, d))
+    rho = np.zeros((d, d), dtype=np.result_type(a, A))
     for s in range(d):
         for sp in range(d):
             t = imp(s, sp)
@@ -86,7 +86,7 @@ def rdm2_h(a, A, b, rows, cols):
     cj = (cols - 1) // 2
     d = A.shape[0]
     imp = lambda s, sp: basis.impurity(A, s, sp)
-    rho = np.zeros((d, d, d, d))
+    rho = np.zeros((d, d, d, d), dtype=np.result_type(a, A))
     for s1 in range(d):
         for s2 in range(d):
             for t1 in range(d):

@@ -197,8 +197,8 @@ def cut_projectors(Q1, Q2, Q3, Q4, chi, tau, pars=None):
     # new bond basis: even sector first, each sector by descending value
     kept = kept[np.lexsort((loc[kept], sec[kept]))]
     knew = len(kept)
-    Pa = np.zeros((nW, knew))
-    Pb = np.zeros((knew, nW))
+    Pa = np.zeros((nW, knew), dtype=m1.dtype)
+    Pb = np.zeros((knew, nW), dtype=m1.dtype)
     kcount = [0, 0]
     col = 0
     for (P, iW, Hu, Hd, Wm, s, Vt) in parts:
@@ -208,8 +208,10 @@ def cut_projectors(Q1, Q2, Q3, Q4, chi, tau, pars=None):
         if kP == 0:
             continue
         isq = 1.0 / np.sqrt(s[idx])
-        Pa[np.ix_(iW, np.arange(col, col + kP))] = (Hu @ Vt[idx].T) * isq[None, :]
-        Pb[np.ix_(np.arange(col, col + kP), iW)] = (Wm[:, idx].T @ Hd) * isq[:, None]
+        # M = W S V^dagger: P_a = H_u V S^-1/2, P_b = S^-1/2 W^dagger H_d
+        # (for real blocks the conjugates are the blocks themselves)
+        Pa[np.ix_(iW, np.arange(col, col + kP))] = (Hu @ np.conj(Vt[idx]).T) * isq[None, :]
+        Pb[np.ix_(np.arange(col, col + kP), iW)] = (np.conj(Wm[:, idx]).T @ Hd) * isq[:, None]
         col += kP
     order = np.argsort(-svals)
     spec = svals[order] / svals[order[0]]
@@ -310,6 +312,8 @@ class Run:
             a = basis.double_layer(A)
         self.a_plain = a
         q = a.shape[0]
+        if form == "z2" and np.iscomplexobj(a):
+            raise ValueError("the masked Z2 form holds real tensors only; complex ones: oracle.complex_z2")
         if form == "z2":
             D = int(round(np.sqrt(q)))
             self.U = basis.hermitian_basis(D)
@@ -378,7 +382,7 @@ class Run:
     def rho1(self):
         rho = rho1_of(self.epsilon(), self.A)
         if self.form == "z2":
-            rho = 0.5 * (rho + rho.T)
+            rho = 0.5 * (rho + np.conj(rho).T)
         return rho
 
     def rho2(self, direction="h"):
@@ -386,13 +390,15 @@ class Run:
         env = self.plain_env().rotated(r)
         rho = rho2_h_of(env, rot_A(self.A, r))
         if self.form == "z2":
-            rho = 0.5 * (rho + rho.T)
+            rho = 0.5 * (rho + np.conj(rho).T)
         return rho
 
     def energy(self, h=None):
+        """Tr(rho_h h) + Tr(rho_v h); its real part (the RDMs of a complex
+        tensor in the plain form are Hermitian only up to the truncation)."""
         if h is None:
             h = heisenberg_bond()
-        return float(np.trace(self.rho2("h") @ h) + np.trace(self.rho2("v") @ h))
+        return float(np.real(np.trace(self.rho2("h") @ h) + np.trace(self.rho2("v") @ h)))
 
     def s_err(self):
         return s_err_of(self.epsilon())
@@ -421,10 +427,10 @@ def _top_bottom(env):
 
 
 def rho1_of(eps, A):
-    """rho1[s,s'] = <eps, A[s] (x) A[s']>, trace one."""
+    """rho1[s,s'] = <eps, A[s] (x) conj(A[s'])>, trace one."""
     D = A.shape[1]
     e8 = eps.reshape((D,) * 8)
-    rho = np.einsum("aebfcgdh,sabcd,tefgh->st", e8, A, A, **EINSUM)
+    rho = np.einsum("aebfcgdh,sabcd,tefgh->st", e8, A, np.conj(A), **EINSUM)
     return rho / np.trace(rho)
 
 
@@ -452,8 +458,9 @@ def rho2_h_of(env, A, env_r=None, A_r=None):
     # bottom environment bonds that continue to the right half.
     tl = np.einsum("cx,xuvy->cuvy", C1, T1s, **EINSUM)
     lft = np.einsum("plmc,cuvy->plmuvy", T4s, tl, **EINSUM)
+    # ket layer A, bra layer conj(A)
     k1 = np.einsum("plmuvy,suleg->pmvyseg", lft, A, **EINSUM)
-    k2 = np.einsum("pmvyseg,tvmfh->pysegtfh", k1, A, **EINSUM)
+    k2 = np.einsum("pmvyseg,tvmfh->pysegtfh", k1, np.conj(A), **EINSUM)
     bl = np.einsum("zefx,xp->zefp", T3s, C4, **EINSUM)
     left = np.einsum("pysegtfh,zefp->ysgthz", k2, bl, **EINSUM)
     # right half: T1 C2 / [site 2] T2 / T3 C3; g, h are the ket and bra
@@ -461,7 +468,7 @@ def rho2_h_of(env, A, env_r=None, A_r=None):
     tr = np.einsum("yuvx,xc->yuvc", R1s, R2, **EINSUM)
     rgt = np.einsum("yuvc,crwp->yuvrwp", tr, U2s, **EINSUM)
     k1 = np.einsum("yuvrwp,suger->yvwpsge", rgt, A_r, **EINSUM)
-    k2 = np.einsum("yvwpsge,tvhfw->ypsgethf", k1, A_r, **EINSUM)
+    k2 = np.einsum("yvwpsge,tvhfw->ypsgethf", k1, np.conj(A_r), **EINSUM)
     br = np.einsum("px,xefz->pefz", R3, U3s, **EINSUM)
     right = np.einsum("ypsgethf,pefz->ysgthz", k2, br, **EINSUM)
     rho = np.einsum("yagbhz,ycgdhz->acbd", left, right, **EINSUM)
@@ -480,11 +487,12 @@ def heisenberg_bond():
 def s_err_of(eps):
     """Hermitian symmetry error ||e - e^dag|| / ||e + e^dag|| (Sec. III A).
 
-    For real tensors e^dag is e with bra and ket swapped on every leg.
+    e^dag is e with bra and ket swapped on every leg, complex conjugated
+    (for real tensors the conjugate is the tensor itself).
     """
     D = int(round(np.sqrt(eps.shape[0])))
     S = basis.swap_matrix(D)
-    ed = basis.apply_on_all_legs(S, eps)
+    ed = np.conj(basis.apply_on_all_legs(S, eps))
     return float(np.linalg.norm(eps - ed) / np.linalg.norm(eps + ed))
 
 

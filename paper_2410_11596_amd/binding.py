@@ -25,6 +25,7 @@ EXPORTS = [
     "ctm_env_epsilon", "ctm_s_err", "ctm_log_kappa", "ctm_num_records", "ctm_record",
     "ctm_sector_dims", "ctm_timing", "ctm_gemm_stats", "ctm_set_precision",
     "ctm_corner_spectrum", "ctm_svd_health", "ctm_record_status",
+    "ctm_workspace_size_complex", "ctm_init_complex", "ctm_rdm_1site_complex", "ctm_rdm_2site_complex",
     "ctm_server_create", "ctm_server_submit", "ctm_server_wait", "ctm_server_load", "ctm_server_destroy",
     "hotrg_opts_default", "hotrg_init", "hotrg_step", "hotrg_log_z", "hotrg_sym_error", "hotrg_set_bond",
     "hotrg_energy", "hotrg_track_rdm1", "hotrg_rdm1", "hotrg_num_records",
@@ -114,6 +115,11 @@ def lib():
         "ctm_sector_dims": ([ctx, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ip], ctypes.c_int),
         "ctm_corner_spectrum": ([ctx, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ip], ctypes.c_int),
         "ctm_svd_health": ([ctx, ip, ip], ctypes.c_int),
+        "ctm_workspace_size_complex": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, P(CtmOpts), P(ctypes.c_size_t)],
+                                       ctypes.c_int),
+        "ctm_init_complex": ([P(vp), dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(CtmOpts)], ctypes.c_int),
+        "ctm_rdm_1site_complex": ([ctx, ctypes.c_int, ctypes.c_int, dp, dp], ctypes.c_int),
+        "ctm_rdm_2site_complex": ([ctx, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp], ctypes.c_int),
         "ctm_record_status": ([ctx, ctypes.c_int, ip], ctypes.c_int),
         "ctm_timing": ([ctx, dp, ctypes.c_int, ip], ctypes.c_int),
         "ctm_gemm_stats": ([ctx, dp, dp, P(ctypes.c_longlong), ctypes.c_int], ctypes.c_int),
@@ -226,6 +232,13 @@ class CTMRG:
     def __init__(self, A, chi, form="z2", boundary=None, svd_rel_cutoff=1e-12, svd_iters=12, seed=0x5EED,
                  stream=None, torch_workspace=True, profile=False, form_m=False, precision="fp64", c4v=False):
         torch = _torch()
+        self.complex = bool(np.iscomplexobj(A))
+        if self.complex:
+            Ac = np.ascontiguousarray(A, dtype=np.complex128)
+            if Ac.ndim != 5:
+                raise ValueError("a complex tensor must have shape (d, D, D, D, D) (1 x 1 cell)")
+            A_re, A_im = np.ascontiguousarray(Ac.real), np.ascontiguousarray(Ac.imag)
+            A = A_re
         A = _cell_array(A)
         self.Ly, self.Lx = A.shape[0], A.shape[1]
         self.d, self.D, self.chi = A.shape[2], A.shape[3], int(chi)
@@ -250,14 +263,19 @@ class CTMRG:
         self._stream = stream
         o.stream = ctypes.c_void_p(stream.cuda_stream)
         self._ws = None
+        size_fn = lib().ctm_workspace_size_complex if self.complex else lib().ctm_workspace_size
         if torch_workspace:
             nbytes = ctypes.c_size_t()
-            _check(lib().ctm_workspace_size(self.d, self.D, self.chi, ctypes.byref(o), ctypes.byref(nbytes)))
+            _check(size_fn(self.d, self.D, self.chi, ctypes.byref(o), ctypes.byref(nbytes)))
             self._ws = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
             o.workspace = ctypes.c_void_p(self._ws.data_ptr())
             o.workspace_bytes = nbytes.value
         ctx = ctypes.c_void_p()
-        _check(lib().ctm_init(ctypes.byref(ctx), _dptr(A), self.d, self.D, self.chi, ctypes.byref(o)))
+        if self.complex:
+            _check(lib().ctm_init_complex(ctypes.byref(ctx), _dptr(A_re), _dptr(A_im), self.d, self.D, self.chi,
+                                          ctypes.byref(o)))
+        else:
+            _check(lib().ctm_init(ctypes.byref(ctx), _dptr(A), self.d, self.D, self.chi, ctypes.byref(o)))
         self._ctx = ctx
 
     def close(self):
@@ -301,14 +319,25 @@ class CTMRG:
         return self
 
     def rdm1(self, x=0, y=0):
+        """One-site RDM (complex128 for a complex tensor)."""
+        if self.complex:
+            re, im = np.zeros((self.d, self.d)), np.zeros((self.d, self.d))
+            _check(lib().ctm_rdm_1site_complex(self._ctx, x, y, _dptr(re), _dptr(im)), self._ctx)
+            return re + 1j * im
         rho = np.zeros((self.d, self.d))
         _check(lib().ctm_rdm_1site(self._ctx, x, y, _dptr(rho)), self._ctx)
         return rho
 
     def rdm2(self, direction="h", x=0, y=0):
+        """Two-site RDM [(s1 s2), (s1' s2')] (complex128 for a complex tensor)."""
         n = self.d * self.d
+        dr = 0 if direction == "h" else 1
+        if self.complex:
+            re, im = np.zeros((n, n)), np.zeros((n, n))
+            _check(lib().ctm_rdm_2site_complex(self._ctx, x, y, dr, _dptr(re), _dptr(im)), self._ctx)
+            return re + 1j * im
         rho = np.zeros((n, n))
-        _check(lib().ctm_rdm_2site(self._ctx, x, y, 0 if direction == "h" else 1, _dptr(rho)), self._ctx)
+        _check(lib().ctm_rdm_2site(self._ctx, x, y, dr, _dptr(rho)), self._ctx)
         return rho
 
     def energy(self, h):

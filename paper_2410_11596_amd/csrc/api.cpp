@@ -169,6 +169,66 @@ int ctm_init(ctm_ctx** out, const double* A, int d, int D, int chi, const ctm_op
   });
 }
 
+int ctm_workspace_size_complex(int d, int D, int chi, const ctm_opts* o, size_t* bytes) {
+  return guarded(nullptr, [&] {
+    if (!bytes) throw hctm::Error(CTM_E_ARG, "bytes is NULL");
+    check_sizes(d, D, chi);
+    hctm::Options opt = to_options(o, D);
+    opt.cplx = 1;
+    *bytes = hctm::Ctm::workspace_bytes(d, D, chi, opt);
+  });
+}
+
+int ctm_init_complex(ctm_ctx** out, const double* A_re, const double* A_im, int d, int D, int chi,
+                     const ctm_opts* o) {
+  if (out) *out = nullptr;
+  return guarded(nullptr, [&] {
+    if (!out || !A_re || !A_im) throw hctm::Error(CTM_E_ARG, "NULL argument");
+    check_sizes(d, D, chi);
+    if (d > 8) throw hctm::Error(CTM_E_ARG, "complex tensors: d must be at most 8");
+    hctm::Options opt = to_options(o, D);
+    if (opt.form != 0 || opt.Lx != 1 || opt.Ly != 1 || opt.c4v || opt.precision != 0)
+      throw hctm::Error(CTM_E_ARG, "complex tensors: Z2 form, 1 x 1 cell, directional moves and FP64 only");
+    opt.cplx = 1;
+    const long long n = (long long)d * D * D * D * D;
+    for (long long i = 0; i < n; ++i)
+      if (!std::isfinite(A_re[i]) || !std::isfinite(A_im[i])) throw hctm::Error(CTM_E_NUMERIC, "A has a non-finite entry");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) throw hctm::Error(CTM_E_HIP, "no HIP device");
+    std::unique_ptr<ctm_ctx> c(new ctm_ctx);
+    c->d = d;
+    c->D = D;
+    c->chi = chi;
+    c->form = 0;
+    void* stream = o ? o->stream : nullptr;
+    void* ws = o ? o->workspace : nullptr;
+    const size_t wsb = o ? o->workspace_bytes : 0;
+    c->ctm.reset(new hctm::Ctm(A_re, A_im, d, D, chi, opt, reinterpret_cast<hipStream_t>(stream), ws, wsb));
+    *out = c.release();
+  });
+}
+
+int ctm_rdm_1site_complex(ctm_ctx* c, int x, int y, double* rho_re, double* rho_im) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    if (!rho_re || !rho_im) throw hctm::Error(CTM_E_ARG, "NULL argument");
+    if (!c->ctm->is_complex()) throw hctm::Error(CTM_E_ARG, "not a complex context (use ctm_rdm_1site)");
+    if (x != 0 || y != 0) throw hctm::Error(CTM_E_ARG, "site outside the cell");
+    c->ctm->rdm1_complex(x, y, rho_re, rho_im);
+  });
+}
+
+int ctm_rdm_2site_complex(ctm_ctx* c, int x, int y, int dir, double* rho_re, double* rho_im) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    if (!rho_re || !rho_im) throw hctm::Error(CTM_E_ARG, "NULL argument");
+    if (!c->ctm->is_complex()) throw hctm::Error(CTM_E_ARG, "not a complex context (use ctm_rdm_2site)");
+    if (dir != 0 && dir != 1) throw hctm::Error(CTM_E_ARG, "dir must be 0 or 1");
+    if (x != 0 || y != 0) throw hctm::Error(CTM_E_ARG, "site outside the cell");
+    c->ctm->rdm2_complex(x, y, dir, rho_re, rho_im);
+  });
+}
+
 int ctm_step(ctm_ctx* c, int n_iter) {
   if (!c) return CTM_E_ARG;
   return guarded(c, [&] {
@@ -182,6 +242,8 @@ int ctm_set_precision(ctm_ctx* c, int precision) {
   return guarded(c, [&] {
     if (precision != CTM_PREC_FP64 && precision != CTM_PREC_FP32 && precision != CTM_PREC_BF16X3)
       throw hctm::Error(CTM_E_ARG, "precision must be CTM_PREC_FP64, CTM_PREC_FP32 or CTM_PREC_BF16X3");
+    if (c->ctm->is_complex() && precision != CTM_PREC_FP64)
+      throw hctm::Error(CTM_E_ARG, "complex tensors run in FP64 only");
     c->ctm->set_precision(precision);
   });
 }
@@ -203,6 +265,7 @@ int ctm_rdm_1site(ctm_ctx* c, int x, int y, double* rho) {
   if (!c) return CTM_E_ARG;
   return guarded(c, [&] {
     if (!rho) throw hctm::Error(CTM_E_ARG, "rho is NULL");
+    if (c->ctm->is_complex()) throw hctm::Error(CTM_E_ARG, "complex context: use ctm_rdm_1site_complex");
     check_site(c, x, y);
     c->ctm->rdm1(x, y, rho);
   });
@@ -213,6 +276,7 @@ int ctm_rdm_2site(ctm_ctx* c, int x, int y, int dir, double* rho) {
   return guarded(c, [&] {
     if (!rho) throw hctm::Error(CTM_E_ARG, "rho is NULL");
     if (dir != 0 && dir != 1) throw hctm::Error(CTM_E_ARG, "dir must be 0 or 1");
+    if (c->ctm->is_complex()) throw hctm::Error(CTM_E_ARG, "complex context: use ctm_rdm_2site_complex");
     check_site(c, x, y);
     c->ctm->rdm2(x, y, dir, rho);
   });
@@ -222,7 +286,7 @@ int ctm_energy(ctm_ctx* c, const double* h, double* e) {
   if (!c) return CTM_E_ARG;
   return guarded(c, [&] {
     if (!h || !e) throw hctm::Error(CTM_E_ARG, "NULL argument");
-    *e = c->ctm->energy(h);
+    *e = c->ctm->is_complex() ? c->ctm->energy_complex(h) : c->ctm->energy(h);
   });
 }
 
@@ -234,6 +298,7 @@ int ctm_env_epsilon(ctm_ctx* c, int x, int y, double* eps) {
   if (!c) return CTM_E_ARG;
   return guarded(c, [&] {
     if (!eps) throw hctm::Error(CTM_E_ARG, "eps is NULL");
+    if (c->ctm->is_complex()) throw hctm::Error(CTM_E_ARG, "not available for a complex context");
     check_site(c, x, y);
     c->ctm->epsilon_plain(x, y, eps);
   });
@@ -243,6 +308,7 @@ int ctm_s_err(ctm_ctx* c, double* s) {
   if (!c) return CTM_E_ARG;
   return guarded(c, [&] {
     if (!s) throw hctm::Error(CTM_E_ARG, "NULL argument");
+    if (c->ctm->is_complex()) throw hctm::Error(CTM_E_ARG, "not available for a complex context");
     *s = c->ctm->s_err();
   });
 }
@@ -251,6 +317,7 @@ int ctm_log_kappa(ctm_ctx* c, double* lk) {
   if (!c) return CTM_E_ARG;
   return guarded(c, [&] {
     if (!lk) throw hctm::Error(CTM_E_ARG, "NULL argument");
+    if (c->ctm->is_complex()) throw hctm::Error(CTM_E_ARG, "not available for a complex context");
     *lk = c->ctm->log_kappa();
   });
 }

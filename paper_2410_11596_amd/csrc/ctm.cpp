@@ -62,6 +62,7 @@ Ctm::Ctm(CountTag, int d, int D, int chi, int Lx, int Ly) : d_(d), D_(D), chi_(c
 
 size_t Ctm::workspace_bytes(int d, int D, int chi, const Options& o) {
   Ctm c(CountTag{}, d, D, chi, o.Lx, o.Ly);
+  c.cplx_ = o.cplx != 0;
   c.plan_memory(true);
   return c.ar_.used + 256;
 }
@@ -101,7 +102,8 @@ void Ctm::plan_memory(bool counting) {
   tabT_idx_ = ti(2 * q);
   tabT_c_ = ar_.take(2 * q);
   const int ns = ns_;
-  A_ = ar_.take((size_t)ns * d_ * D_ * D_ * D_ * D_);
+  // a complex tensor is held as [A_re; A_im], 2 d physical states
+  A_ = ar_.take((size_t)ns * (cplx_ ? 2 : 1) * d_ * D_ * D_ * D_ * D_);
   b_ = ar_.take((size_t)q);
   a_plain_.assign(ns, nullptr);
   for (int s = 0; s < ns; ++s) a_plain_[s] = ar_.take((size_t)q4);
@@ -198,17 +200,32 @@ void Ctm::plan_memory(bool counting) {
   eps_.p = ar_.take((size_t)q4);
   eps_.capacity = q4;
   halves_cap_ = cc * cc * q;
-  halves_max_ = 2 * d_ * d_;
+  halves_max_ = (cplx_ ? 4 : 2) * d_ * d_;
   halves_ = ar_.take((size_t)(halves_max_ * halves_cap_));
   const long long d4 = (long long)d_ * d_ * d_ * d_;
-  dots_ = ar_.take((size_t)(2 * d4 + 16));
+  dots_ = ar_.take((size_t)((cplx_ ? 8 : 2) * d4 + 16));
   dpart_ = ar_.take((size_t)(64 * kMaxDots));
-  rho_ = ar_.take((size_t)(2 * ns * d4 + 16));
+  rho_ = ar_.take((size_t)((cplx_ ? 4 : 2) * ns * d4 + 16));
   hdev_ = ar_.take((size_t)(d4 + 16));
   // split-K partial tiles: a few K slices of the tall n x l products of both
   // sectors, or of the l x l Gram matrices
   gemm_scratch_cap_ = std::max<long long>({1LL << 20, 24LL * lcap * lcap, 16LL * ncap * lcap});
   gemm_scratch_ = ar_.take((size_t)gemm_scratch_cap_);
+  if (cplx_) {
+    // the imaginary parts share the buffers of the real parts; extra: the
+    // plain imaginary double layer, the real matrix R of the truncation, the
+    // transposed left vectors and two impurities
+    env_i_.assign(env_.size(), BT());
+    quad_i_.assign(quad_.size(), BT());
+    a_rot_i_.assign(a_rot_.size(), BT());
+    Pa_i_.assign(Pa_.size(), BT());
+    Pb_i_.assign(Pb_.size(), BT());
+    a_plain_im_ = ar_.take((size_t)q4);
+    R_.p = ar_.take((size_t)(ncap * ncap));
+    R_.capacity = ncap * ncap;
+    WH_ = ar_.take((size_t)(ncap * cc));
+    cimp_ = ar_.take((size_t)(2 * q4));
+  }
 }
 
 // ------------------------------------------------------------- set-up ----
@@ -1348,11 +1365,16 @@ void Ctm::step(int n_iter) {
   for (int it = 0; it < n_iter; ++it) {
     if (opt_.c4v) {
       move_c4v();
+    } else if (cplx_) {
+      for (int m = 0; m < 4; ++m) cmove(order[m]);
     } else {
       for (int m = 0; m < 4; ++m) move(order[m]);
     }
     mark(4);
-    corner_spectra();
+    if (cplx_)
+      ccorner_spectra();
+    else
+      corner_spectra();
     mark(-1);
   }
   HCTM_HIP(hipMemcpyAsync(host_d_, misc_ + 16, sizeof(double), hipMemcpyDeviceToHost, st_));

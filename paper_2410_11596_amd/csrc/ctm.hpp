@@ -57,6 +57,7 @@ struct Options {
   int c4v = 0;        // 1: one corner and one edge for a C4v-symmetric tensor (1 x 1 cell)
   unsigned long long seed = 0x5eed;
   int profile = 0;  // 1: time every GEMM launch with HIP events
+  int cplx = 0;     // 1: complex tensor in the real representation (1 x 1 cell, Z2 form)
 };
 
 struct GemmStats {
@@ -95,6 +96,13 @@ class Ctm {
   Ctm(CountTag, int d, int D, int chi, int Lx, int Ly);
   Ctm(const double* A_host, int d, int D, int chi, const Options& o, hipStream_t stream, void* workspace,
       size_t ws_bytes);
+  // complex tensor A = A_re + i A_im (o.cplx must be 1)
+  Ctm(const double* A_re, const double* A_im, int d, int D, int chi, const Options& o, hipStream_t stream,
+      void* workspace, size_t ws_bytes);
+  bool is_complex() const { return cplx_; }
+  // complex mode: Hermitian RDMs as real and imaginary parts (host arrays)
+  void rdm1_complex(int x, int y, double* re, double* im);
+  void rdm2_complex(int x, int y, int dir, double* re, double* im);
   ~Ctm();
   static size_t workspace_bytes(int d, int D, int chi, const Options& o);
 
@@ -152,6 +160,37 @@ class Ctm {
   void rdm2_dev(int x, int y, int dir, double* dst);
   void sync();
   void top_bottom(BT& top, BT& bot);  // TOP[a U | c], BOT[c' Dn | e] (frame 0)
+
+  // ---- complex tensors in the real representation (ctm_complex.cpp) ----
+  // A structured complex tensor X = X_re + i X_im is held as two block
+  // tensors: X_re with the layout of total parity 0 (its real even-total
+  // blocks) and X_im with total parity 1 (the imaginary parts of its odd-total
+  // blocks), X_im stored right after X_re in one buffer.
+  bool cplx_ = false;
+  std::vector<BT> env_i_, quad_i_, a_rot_i_;
+  BT Hu_i_, Hd_i_, M_i_, eps_i_;
+  std::vector<BT> Pa_i_, Pb_i_;
+  BT R_;                      // real n x n matrix decomposed for the truncation
+  double* WH_ = nullptr;      // (D U)^dagger of the kept states, k x n
+  double* cimp_ = nullptr;    // two impurities, 2 q^4
+  double* a_plain_im_ = nullptr;
+  void setup_complex(const double* A_re, const double* A_im);
+  void cmul(const BT& Ar, const BT& Ai, const BT& Br, const BT& Bi, BT& Cr, BT& Ci, const double* cscale = nullptr,
+            const double* rscale = nullptr);
+  void cpermute(const BT& inr, const BT& ini, BT& outr, BT& outi, std::initializer_list<int> perm, int nr_out);
+  void cnormalise(BT& r, BT& i);
+  void cquadrant(int o);
+  void cmove(int r);
+  void ccorner_spectra();
+  void ccompute_epsilon();
+  void cimpurity(int s, int sp, int frame, BT& s1r, BT& s1i, BT& s2r, BT& s2i);
+  void cleft_half(int f, const BT& ir, const BT& ii, BT& outr, BT& outi);
+  void cright_half(int f, const BT& ir, const BT& ii, BT& outr, BT& outi);
+  void rdm2c_dev(int dir, double* re, double* im);
+ public:
+  double energy_complex(const double* h_host);
+
+ private:
 
   int d_, D_, chi_, q_, cc_;
   int Lx_ = 1, Ly_ = 1, ns_ = 1;

@@ -62,6 +62,12 @@ __global__ void scale_inv_kernel(double* __restrict__ p, long long n, const doub
     p[i] *= f;
 }
 
+__global__ void scale_block_kernel(double* p, int rows, int cols, long long ld, double alpha) {
+  const long long n = (long long)rows * cols;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    p[(e / cols) * ld + e % cols] *= alpha;
+}
+
 __global__ void fill_kernel(double* p, long long n, double v) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = v;
@@ -1280,46 +1286,63 @@ __global__ __launch_bounds__(256) void ritz_resid_kernel(const double* __restric
 // --------------------------------------------------------- truncation ----
 // Merge the two descending spectra (even sector first on ties) and keep
 // k = min(chi, #{s > tau * s_max}) (at least one).  Writes k_even, k_odd,
-// s_max and the inverse square roots of the kept values per sector.
-__global__ void select_kernel(SelectArgs a) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double s0 = a.n0 > 0 ? a.sv0[0] : -1.0;
-  const double s1 = a.n1 > 0 ? a.sv1[0] : -1.0;
-  const double smax = fmax(s0, s1);
-  int i0 = 0, i1 = 0, k = 0;
-  while (k < a.chi) {
-    const double v0 = i0 < a.n0 ? a.sv0[i0] : -1.0;
-    const double v1 = i1 < a.n1 ? a.sv1[i1] : -1.0;
-    const bool take0 = v0 >= v1;
-    const double v = take0 ? v0 : v1;
-    if (v < 0.0) break;
-    if (!(v > a.tau * smax) && k > 0) break;
-    if (take0)
-      ++i0;
-    else
-      ++i1;
-    ++k;
+// s_max, the first discarded and the last kept value, and the inverse square
+// roots and inverses of the kept values per sector.  The leading chi + 1
+// values of each sector are staged in LDS by all threads, one thread merges,
+// all threads write the inverses.
+__global__ __launch_bounds__(256) void select_kernel(SelectArgs a, int staged) {
+  extern __shared__ double sh[];
+  __shared__ int kk[2];
+  const int c0 = min(a.n0, a.chi + 1), c1 = min(a.n1, a.chi + 1);
+  const double* s0 = a.sv0;
+  const double* s1 = a.sv1;
+  if (staged) {  // (else the values are read where they are)
+    for (int i = threadIdx.x; i < c0; i += blockDim.x) sh[i] = a.sv0[i];
+    for (int i = threadIdx.x; i < c1; i += blockDim.x) sh[c0 + i] = a.sv1[i];
+    s0 = sh;
+    s1 = sh + c0;
   }
-  a.out_k[0] = i0;
-  a.out_k[1] = i1;
-  a.out_s[0] = smax;
-  // the last kept and the first discarded value (-1: none), for the
-  // multiplet-split test at the chi cut
-  {
-    const double v0 = i0 < a.n0 ? a.sv0[i0] : -1.0;
-    const double v1 = i1 < a.n1 ? a.sv1[i1] : -1.0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double v00 = c0 > 0 ? s0[0] : -1.0;
+    const double v10 = c1 > 0 ? s1[0] : -1.0;
+    const double smax = fmax(v00, v10);
+    int i0 = 0, i1 = 0, k = 0;
+    while (k < a.chi) {
+      const double v0 = i0 < c0 ? s0[i0] : -1.0;
+      const double v1 = i1 < c1 ? s1[i1] : -1.0;
+      const bool take0 = v0 >= v1;
+      const double v = take0 ? v0 : v1;
+      if (v < 0.0) break;
+      if (!(v > a.tau * smax) && k > 0) break;
+      if (take0)
+        ++i0;
+      else
+        ++i1;
+      ++k;
+    }
+    a.out_k[0] = i0;
+    a.out_k[1] = i1;
+    a.out_s[0] = smax;
+    // the first discarded and the last kept value (-1: none), for the
+    // multiplet-split test at the chi cut
+    const double v0 = i0 < c0 ? s0[i0] : -1.0;
+    const double v1 = i1 < c1 ? s1[i1] : -1.0;
     a.out_s[1] = fmax(v0, v1);
-    const double l0 = i0 > 0 ? a.sv0[i0 - 1] : -1.0;
-    const double l1 = i1 > 0 ? a.sv1[i1 - 1] : -1.0;
+    const double l0 = i0 > 0 ? s0[i0 - 1] : -1.0;
+    const double l1 = i1 > 0 ? s1[i1 - 1] : -1.0;
     a.out_s[2] = (i0 > 0 && i1 > 0) ? fmin(l0, l1) : fmax(l0, l1);
+    kk[0] = i0;
+    kk[1] = i1;
   }
-  for (int i = 0; i < i0; ++i) {
-    a.isq0[i] = 1.0 / sqrt(a.sv0[i]);
-    a.isv0[i] = 1.0 / a.sv0[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < kk[0]; i += blockDim.x) {
+    a.isq0[i] = 1.0 / sqrt(s0[i]);
+    a.isv0[i] = 1.0 / s0[i];
   }
-  for (int i = 0; i < i1; ++i) {
-    a.isq1[i] = 1.0 / sqrt(a.sv1[i]);
-    a.isv1[i] = 1.0 / a.sv1[i];
+  for (int i = threadIdx.x; i < kk[1]; i += blockDim.x) {
+    a.isq1[i] = 1.0 / sqrt(s1[i]);
+    a.isv1[i] = 1.0 / s1[i];
   }
 }
 
@@ -1379,6 +1402,14 @@ static unsigned grid_for(long long n, int per = 256, unsigned cap = 4096) {
 void fill(double* p, double v, size_t n, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for((long long)n)), dim3(256), 0, s, p, (long long)n, v);
+  HCTM_HIP(hipGetLastError());
+}
+
+void scale_block(double* p, int rows, int cols, long long ld, double alpha, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  if (ld < cols) throw Error(1, "scale_block: leading dimension below the column count");
+  hipLaunchKernelGGL(scale_block_kernel, dim3(grid_for((long long)rows * cols)), dim3(256), 0, s, p, rows, cols, ld,
+                     alpha);
   HCTM_HIP(hipGetLastError());
 }
 
@@ -1536,7 +1567,11 @@ void corner_spectra_delta(const SpecArgs& a, hipStream_t s) {
 }
 
 void select_states(const SelectArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, a);
+  if (a.chi < 1 || a.chi > 8192 || a.n0 < 0 || a.n1 < 0) throw Error(1, "select_states: sizes out of range");
+  size_t lds = sizeof(double) * (size_t)(std::min(a.n0, a.chi + 1) + std::min(a.n1, a.chi + 1));
+  const int staged = lds <= 48 * 1024 ? 1 : 0;
+  if (!staged) lds = 0;
+  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(256), lds, s, a, staged);
   HCTM_HIP(hipGetLastError());
 }
 

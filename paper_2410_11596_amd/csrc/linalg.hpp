@@ -67,6 +67,8 @@ struct SpecArgs {
 void corner_spectra_delta(const SpecArgs& a, hipStream_t s);
 
 void fill(double* p, double v, size_t n, hipStream_t s);
+// p[r * ld + c] *= alpha for r < rows, c < cols
+void scale_block(double* p, int rows, int cols, long long ld, double alpha, hipStream_t s);
 void random_fill(double* p, size_t n, uint64_t seed, hipStream_t s);
 void norm2(const double* p, size_t n, double* out, double* part, hipStream_t s);
 void sumsq(const double* p, size_t n, double* out, double* part, hipStream_t s);

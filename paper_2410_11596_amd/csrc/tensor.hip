@@ -205,6 +205,42 @@ __global__ void assemble_rho_kernel(const double* __restrict__ dots, int d, int 
   for (int i = 0; i < n * n; ++i) rho[i] /= tr;
 }
 
+// Hermitian RDMs of a complex tensor from real dot products (see
+// assemble_rho_complex in tensor.hpp): the entries on and above the diagonal
+// are formed, those below are their conjugates, the diagonal is real; then
+// everything is divided by the trace.
+__global__ void assemble_rho_complex_kernel(const double* __restrict__ dots, int d, int two_site,
+                                            double* __restrict__ re, double* __restrict__ im) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int n = two_site ? d * d : d;
+  for (int I = 0; I < n; ++I)
+    for (int J = I; J < n; ++J) {
+      double vr, vi;
+      if (!two_site) {
+        const double* t = dots + 4 * pair_le(I, J, d);
+        vr = t[0] - t[1];
+        vi = t[2] - t[3];
+      } else {
+        const int s1 = I / d, s2 = I % d, t1 = J / d, t2 = J % d;
+        const double* t = dots + 8 * ((s1 * d + t1) * d * d + (s2 * d + t2));
+        const double l1r1 = t[0] - t[1], l2r2 = t[2] - t[3], l1r2 = t[4] - t[5], l2r1 = t[6] - t[7];
+        vr = l1r1 - l2r2;
+        vi = l1r2 + l2r1;
+      }
+      if (I == J) vi = 0.0;
+      re[I * n + J] = vr;
+      im[I * n + J] = vi;
+      re[J * n + I] = vr;
+      im[J * n + I] = -vi;
+    }
+  double tr = 0.0;
+  for (int i = 0; i < n; ++i) tr += re[i * n + i];
+  for (int i = 0; i < n * n; ++i) {
+    re[i] /= tr;
+    im[i] /= tr;
+  }
+}
+
 __global__ void trace_products_kernel(const double* __restrict__ rho, int nrho, const double* __restrict__ h, int n,
                                       double* __restrict__ e) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -331,6 +367,7 @@ void double_layer_basis(const DLArgs& g, hipStream_t s) {
   long long blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   const size_t lds = sizeof(double) * g.d * g.D * g.D * g.D * g.D;
+  if (lds > 160 * 1024) throw Error(1, "double layer: d D^4 doubles exceed the LDS of a workgroup");
   hipLaunchKernelGGL(double_layer_basis_kernel, dim3((unsigned)blocks), dim3(256), lds, s, g);
   HCTM_HIP(hipGetLastError());
 }
@@ -350,6 +387,11 @@ void init_env(const double* a, int q, int rot, const double* b, const int* tab_i
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(init_env_kernel, dim3((unsigned)blocks), dim3(256), sizeof(double) * q, s, a, q, rot, b, tab_idx,
                      tab_c, C, T);
+  HCTM_HIP(hipGetLastError());
+}
+
+void assemble_rho_complex(const double* dots, int d, int two_site, double* re, double* im, hipStream_t s) {
+  hipLaunchKernelGGL(assemble_rho_complex_kernel, dim3(1), dim3(64), 0, s, dots, d, two_site, re, im);
   HCTM_HIP(hipGetLastError());
 }
 

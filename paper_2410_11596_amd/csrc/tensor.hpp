@@ -88,6 +88,18 @@ void dots(const std::vector<DotJob>& jobs, double* scratch, hipStream_t s);
 // mode 2: rho2 dense, dots[(s1 d + s1') d^2 + (s2 d + s2')]
 // mode 3: rho2 Z2, dots of sym-sym and anti-anti pairs (see tensor.hip)
 void assemble_rho(const double* dots, int d, int mode, double* rho, hipStream_t s);
+// Complex (Hermitian) RDM from real dot products of structured tensors.
+// One site (two_site = 0): per pair s <= s' (pair_le order) four dots
+//   [eps_re . S1_re, eps_im . S1_im, eps_re . S2_re, eps_im . S2_im] of the
+// structured parts of the impurity S1 + i S2, rho[s][s'] = <eps, S1> +
+// i <eps, S2> = (t0 - t1) + i (t2 - t3).
+// Two sites: per (s1 s1', s2 s2') eight dots of the halves L1, L2 (left) and
+// R1, R2 (right), [L1.R1 re, L1.R1 im, L2.R2 re, L2.R2 im, L1.R2 re,
+// L1.R2 im, L2.R1 re, L2.R1 im] (re, im: the dot of the parts), with
+// <X, Y> = re - im; rho = <L1,R1> - <L2,R2> + i (<L1,R2> + <L2,R1>).
+// The lower triangle is the conjugate of the upper, the result is divided
+// by its trace; re and im are n x n (n = d or d^2), device memory.
+void assemble_rho_complex(const double* dots, int d, int two_site, double* re, double* im, hipStream_t s);
 // e = sum_k Tr(rho_k h), k over nrho matrices of size n x n
 void trace_products(const double* rho, int nrho, const double* h, int n, double* e, hipStream_t s);
 // num = ||x - S x||^2, den = ||x + S x||^2 with S the bra-ket swap on every

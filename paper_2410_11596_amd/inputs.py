@@ -16,6 +16,17 @@ def iid_tensor(d, D, seed):
     return A / np.abs(A).max()
 
 
+def complex_iid_tensor(d, D, seed):
+    """Complex tensor whose real and imaginary parts are i.i.d. N(0,1) (both
+    drawn from one seeded generator, real part first), divided by its largest
+    |entry|."""
+    rng = np.random.default_rng(seed)
+    re = rng.standard_normal((d, D, D, D, D))
+    im = rng.standard_normal((d, D, D, D, D))
+    A = re + 1j * im
+    return A / np.abs(A).max()
+
+
 def c4v_iid_tensor(d, D, seed):
     """iid_tensor(d, D, seed) averaged over the eight symmetries of the square
     (the rotations of the virtual legs [u, l, d, r], each with and without the
