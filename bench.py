@@ -339,41 +339,86 @@ def hotrg_by_d(Ds=(2, 4, 6), chi=64, steps=4, warmup=6):
     return res
 
 
-def serving(n_req, rate, max_active=8, tol=1e-10, max_iter=40, seed=11):
-    """A stream of n_req solves with Poisson arrivals (rate per second), D
-    uniform in {2, 3, 4, 5} and chi in {16, 32, 64, 100} with chi >= D^2,
-    i.i.d. tensors, Z2 form, converged to tol (at most max_iter iterations):
-    latency = result ready - submitted, through the server with up to
-    max_active concurrent solves and one at a time (max_active = 1)."""
-    from paper_2410_11596_amd import Server, inputs, workspace_size
+SERVE_CHI = (16, 32, 64, 100, 144, 196)
+
+
+def serving_requests(n_req, seed=11, complex_share=0.1):
+    """The mixed-solve stream: D uniform in {2, ..., 7}, chi uniform in
+    {16, 32, 64, 100, 144, 196} redrawn until chi >= D^2, i.i.d. N(0,1)
+    tensors (seed 1000 + i), and with probability complex_share a complex
+    tensor (real and imaginary parts N(0,1)) when D <= 5."""
+    from paper_2410_11596_amd import inputs
 
     rng = np.random.default_rng(seed)
     reqs = []
     while len(reqs) < n_req:
-        D = int(rng.integers(2, 6))
-        chi = int(rng.choice([16, 32, 64, 100]))
-        if chi >= D * D:
-            reqs.append((D, chi, inputs.iid_tensor(2, D, 1000 + len(reqs))))
+        D = int(rng.integers(2, 8))
+        chi = int(rng.choice(SERVE_CHI))
+        if chi < D * D:
+            continue
+        cplx = D <= 5 and rng.random() < complex_share
+        i = len(reqs)
+        A = inputs.complex_iid_tensor(2, D, 1000 + i) if cplx else inputs.iid_tensor(2, D, 1000 + i)
+        reqs.append((D, chi, cplx, A))
+    return reqs
+
+
+def serving(n_req, rate, max_active=8, tol=1e-10, max_iter=60, seed=11, baseline_n=None):
+    """A stream of n_req solves (serving_requests) with Poisson arrivals at
+    `rate` per second, each run to delta < tol (at most max_iter iterations):
+    latency = result ready - submitted.  Served: the Z2 form through the
+    server, up to max_active solves at a time, admitted by workspace.
+    Baseline: the first baseline_n requests of the same stream, one at a time,
+    in the plain (dense) FP64 form (the complex ones, which have no plain GPU
+    form, in their Z2 form), arriving at the same times."""
+    from paper_2410_11596_amd import Server, workspace_size
+    from paper_2410_11596_amd.binding import lib, CtmOpts, _check
+    import ctypes
+
+    reqs = serving_requests(n_req, seed)
+    rng = np.random.default_rng(seed + 1)
     gaps = rng.exponential(1.0 / rate, n_req)
-    pool = max_active * max(workspace_size(2, D, chi) for D, chi, _ in reqs) + (1 << 24)
-    out = {"requests": n_req, "arrival_rate_per_s": rate,
-           "mix": "D uniform in {2,3,4,5}, chi in {16,32,64,100} with chi >= D^2, i.i.d. N(0,1) tensors, Z2, "
-                  f"tol {tol:g}, at most {max_iter} iterations"}
-    for label, act in (("concurrent", max_active), ("one_at_a_time", 1)):
+
+    def ws(D, chi, cplx, form):
+        if not cplx:
+            return workspace_size(2, D, chi, form=form)
+        o = CtmOpts()
+        _check(lib().ctm_opts_default(ctypes.byref(o)))
+        n = ctypes.c_size_t()
+        _check(lib().ctm_workspace_size_complex(2, D, chi, ctypes.byref(o), ctypes.byref(n)))
+        return n.value
+
+    big = max(ws(D, chi, c, "z2") for D, chi, c, _ in reqs)
+    out = {"requests": n_req, "arrival_rate_per_s": rate, "tol": tol, "max_iter": max_iter,
+           "mix": "D uniform in {2..7}, chi uniform in {16,32,64,100,144,196} with chi >= D^2, i.i.d. N(0,1) "
+                  "tensors, 10% complex (real and imaginary parts N(0,1)) at D <= 5",
+           "complex_requests": int(sum(c for _, _, c, _ in reqs))}
+    nb = n_req if baseline_n is None else min(baseline_n, n_req)
+    runs = [("concurrent_z2", max_active, "z2", n_req)]
+    if nb > 0:
+        runs.append(("one_at_a_time_dense", 1, "dense", nb))
+    for label, act, form, nrun in runs:
+        pool = act * big + (1 << 24)
         srv = Server(pool, max_active=act)
         t0 = time.perf_counter()
         ids = []
-        for (D, chi, A), gap in zip(reqs, gaps):
+        for (D, chi, cplx, A), gap in zip(reqs[:nrun], gaps[:nrun]):
             time.sleep(gap)
-            ids.append(srv.submit(A, chi, tol=tol, max_iter=max_iter))
+            ids.append(srv.submit(A, chi, form="z2" if cplx else form, tol=tol, max_iter=max_iter))
         res = [srv.wait(i) for i in ids]
         t1 = time.perf_counter()
         srv.close()
         lat = np.array([r["t_end"] - r["t_submit"] for r in res])
-        out[label] = {"max_active": act, "p50_latency_s": float(np.percentile(lat, 50)),
-                      "p99_latency_s": float(np.percentile(lat, 99)), "solves_per_s": n_req / (t1 - t0),
+        out[label] = {"requests": nrun, "max_active": act, "p50_latency_s": float(np.percentile(lat, 50)),
+                      "p99_latency_s": float(np.percentile(lat, 99)), "solves_per_s": nrun / (t1 - t0),
                       "wall_s": t1 - t0, "failed": int(sum(r["status"] != 0 for r in res)),
-                      "iterations": int(sum(r["iterations"] for r in res))}
+                      "converged": int(sum(r["converged"] for r in res)),
+                      "iterations": int(sum(r["iterations"] for r in res)),
+                      "pool_bytes": int(pool)}
+        if label == "concurrent_z2" and nb > 0 and nb < n_req:
+            lat_b = lat[:nb]
+            out[label]["first_%d" % nb] = {"p50_latency_s": float(np.percentile(lat_b, 50)),
+                                           "p99_latency_s": float(np.percentile(lat_b, 99))}
     return out
 
 
@@ -456,7 +501,11 @@ def main():
                     help="run only the HOTRG comparison at this chi and print its JSON")
     ap.add_argument("--serve", type=int, default=24, metavar="N",
                     help="solves in the serving run (0: skip)")
-    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate of the serving run (1/s)")
+    ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrival rate of the serving run (1/s)")
+    ap.add_argument("--serve-baseline", type=int, default=None, metavar="N",
+                    help="requests of the one-at-a-time plain-form baseline (default: all of the serving run)")
+    ap.add_argument("--serve-max-iter", type=int, default=60, help="iteration cap of a served solve")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving comparison and print its JSON")
     ap.add_argument("--copy-check", type=int, default=0, metavar="BYTES",
                     help="before timing, copy BYTES three times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -466,6 +515,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solver is built for a single GPU "
               "and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.serve_only:
+        print(json.dumps(serving(args.serve, args.serve_rate, max_iter=args.serve_max_iter,
+                                 baseline_n=args.serve_baseline)), flush=True)
+        return
     if args.hotrg_only:
         print(json.dumps(hotrg_speedup(chis=(args.hotrg_only,), probe_chi=min(args.hotrg_only, 32))))
         return
@@ -574,7 +627,8 @@ def main():
         out["hotrg"] = hotrg_speedup()
         out["hotrg"]["by_D"] = hotrg_by_d()
     if args.serve > 0:
-        out["serving"] = serving(args.serve, args.serve_rate)
+        out["serving"] = serving(args.serve, args.serve_rate, max_iter=args.serve_max_iter,
+                                 baseline_n=args.serve_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.D, args.chi, (84, 60))
     print(json.dumps(out), flush=True)

@@ -52,6 +52,12 @@ int ctm_server_create(ctm_server** out, size_t pool_bytes, int max_active);
 int ctm_server_submit(ctm_server* s, const double* A, int d, int D, int chi, int form, double tol, int max_iter,
                       long long* id);
 
+/* Queue a solve of the complex tensor A_re + i A_im (host, d*D^4 doubles
+ * each, copied; see ctm_init_complex: Z2 form, d <= 8); waited for like any
+ * other solve, its imaginary RDM parts through ctm_server_wait_complex. */
+int ctm_server_submit_complex(ctm_server* s, const double* A_re, const double* A_im, int d, int D, int chi,
+                              double tol, int max_iter, long long* id);
+
 /* Block until solve id has ended, then copy its results: rho1 (d*d), rho2_h
  * and rho2_v (d^4 each, the pairs (0,0)-(1,0) and (0,0)-(0,1)); any of them
  * may be NULL.  A solve can be waited for once; its results are released
@@ -59,6 +65,11 @@ int ctm_server_submit(ctm_server* s, const double* A, int d, int D, int chi, int
  * own outcome is info->status). */
 int ctm_server_wait(ctm_server* s, long long id, double* rho1, double* rho2_h, double* rho2_v,
                     ctm_solve_info* info);
+
+/* The same with the imaginary parts (zero for a real tensor); any pointer may
+ * be NULL. */
+int ctm_server_wait_complex(ctm_server* s, long long id, double* rho1_re, double* rho1_im, double* rho2_h_re,
+                            double* rho2_h_im, double* rho2_v_re, double* rho2_v_im, ctm_solve_info* info);
 
 /* Number of solves waiting for admission and running now. */
 int ctm_server_load(ctm_server* s, int* waiting, int* running);

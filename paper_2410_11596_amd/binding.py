@@ -27,6 +27,7 @@ EXPORTS = [
     "ctm_corner_spectrum", "ctm_svd_health", "ctm_record_status",
     "ctm_workspace_size_complex", "ctm_init_complex", "ctm_rdm_1site_complex", "ctm_rdm_2site_complex",
     "ctm_server_create", "ctm_server_submit", "ctm_server_wait", "ctm_server_load", "ctm_server_destroy",
+    "ctm_server_submit_complex", "ctm_server_wait_complex",
     "hotrg_opts_default", "hotrg_init", "hotrg_step", "hotrg_log_z", "hotrg_sym_error", "hotrg_set_bond",
     "hotrg_energy", "hotrg_track_rdm1", "hotrg_rdm1", "hotrg_num_records",
     "hotrg_record", "hotrg_last_error", "hotrg_free",
@@ -135,6 +136,10 @@ def lib():
                                ctypes.c_double, ctypes.c_int, P(ctypes.c_longlong)], ctypes.c_int),
         "ctm_server_wait": ([ctypes.c_void_p, ctypes.c_longlong, dp, dp, dp, P(SolveInfo)], ctypes.c_int),
         "ctm_server_load": ([ctypes.c_void_p, ip, ip], ctypes.c_int),
+        "ctm_server_submit_complex": ([ctypes.c_void_p, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_double, ctypes.c_int, P(ctypes.c_longlong)], ctypes.c_int),
+        "ctm_server_wait_complex": ([ctypes.c_void_p, ctypes.c_longlong, dp, dp, dp, dp, dp, dp, P(SolveInfo)],
+                                    ctypes.c_int),
         "ctm_server_destroy": ([ctypes.c_void_p], None),
         "hctm_dev_copy": ([vp, vp, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_longlong), P(ctypes.c_longlong), vp],
                           ctypes.c_int),
@@ -591,22 +596,38 @@ class Server:
         self._d = {}
 
     def submit(self, A, chi, form="z2", tol=1e-10, max_iter=100):
+        """Queue a solve; a complex A runs the complex path (Z2 form)."""
+        i = ctypes.c_longlong()
+        if np.iscomplexobj(A):
+            Ac = np.ascontiguousarray(A, dtype=np.complex128)
+            re, im = np.ascontiguousarray(Ac.real), np.ascontiguousarray(Ac.imag)
+            d, D = re.shape[0], re.shape[1]
+            if form != "z2":
+                raise ValueError("complex tensors are solved in the Z2 form")
+            _check(lib().ctm_server_submit_complex(self._s, _dptr(re), _dptr(im), d, D, int(chi), float(tol),
+                                                   int(max_iter), ctypes.byref(i)))
+            self._d[i.value] = (d, True)
+            return i.value
         A = np.ascontiguousarray(A, dtype=np.float64)
         d, D = A.shape[0], A.shape[1]
-        i = ctypes.c_longlong()
         code = CTM_FORM_Z2 if form == "z2" else CTM_FORM_DENSE
         _check(lib().ctm_server_submit(self._s, _dptr(A), d, D, int(chi), code, float(tol), int(max_iter),
                                        ctypes.byref(i)))
-        self._d[i.value] = d
+        self._d[i.value] = (d, False)
         return i.value
 
     def wait(self, sid):
-        d = self._d.pop(sid)
-        r1 = np.zeros((d * d,))
-        rh = np.zeros((d ** 4,))
-        rv = np.zeros((d ** 4,))
+        """Results of solve sid (complex128 RDMs for a complex tensor)."""
+        d, cplx = self._d.pop(sid)
+        r1, rh, rv = np.zeros((d * d,)), np.zeros((d ** 4,)), np.zeros((d ** 4,))
         info = SolveInfo()
-        _check(lib().ctm_server_wait(self._s, sid, _dptr(r1), _dptr(rh), _dptr(rv), ctypes.byref(info)))
+        if cplx:
+            i1, ih, iv = np.zeros((d * d,)), np.zeros((d ** 4,)), np.zeros((d ** 4,))
+            _check(lib().ctm_server_wait_complex(self._s, sid, _dptr(r1), _dptr(i1), _dptr(rh), _dptr(ih), _dptr(rv),
+                                                 _dptr(iv), ctypes.byref(info)))
+            r1, rh, rv = r1 + 1j * i1, rh + 1j * ih, rv + 1j * iv
+        else:
+            _check(lib().ctm_server_wait(self._s, sid, _dptr(r1), _dptr(rh), _dptr(rv), ctypes.byref(info)))
         return {"status": info.status, "message": info.message.decode(errors="replace"),
                 "iterations": info.iterations, "converged": bool(info.converged), "delta": info.delta,
                 "t_submit": info.t_submit, "t_start": info.t_start, "t_end": info.t_end,

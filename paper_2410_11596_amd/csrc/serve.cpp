@@ -34,6 +34,7 @@ size_t round_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 struct Request {
   long long id = 0;
   std::vector<double> A;
+  std::vector<double> Aim;  // imaginary part of a complex tensor (empty: real)
   int d = 0, D = 0, chi = 0, form = 0, max_iter = 0;
   double tol = 0.0;
   size_t ws = 0;   // workspace bytes (ctm_workspace_size)
@@ -42,6 +43,7 @@ struct Request {
   bool claimed = false;  // a caller waits for it
   ctm_solve_info info{};
   std::vector<double> rho1, rho2h, rho2v;
+  std::vector<double> rho1i, rho2hi, rho2vi;  // imaginary parts (complex tensors)
 };
 
 // First-fit allocator over the pool: free ranges by offset, merged on return.
@@ -164,7 +166,8 @@ struct ctm_server {
         o.stream = st;
         o.workspace = pool_base + r->off;
         o.workspace_bytes = r->ws;
-        rc = ctm_init(&c, r->A.data(), r->d, r->D, r->chi, &o);
+        rc = r->Aim.empty() ? ctm_init(&c, r->A.data(), r->d, r->D, r->chi, &o)
+                            : ctm_init_complex(&c, r->A.data(), r->Aim.data(), r->d, r->D, r->chi, &o);
         if (rc != CTM_OK) msg = ctm_last_error(nullptr);
       }
       while (rc == CTM_OK && it < r->max_iter) {
@@ -179,9 +182,18 @@ struct ctm_server {
         r->rho1.resize(d2);
         r->rho2h.resize(d2 * d2);
         r->rho2v.resize(d2 * d2);
-        rc = ctm_rdm_1site(c, 0, 0, r->rho1.data());
-        if (rc == CTM_OK) rc = ctm_rdm_2site(c, 0, 0, 0, r->rho2h.data());
-        if (rc == CTM_OK) rc = ctm_rdm_2site(c, 0, 0, 1, r->rho2v.data());
+        r->rho1i.assign(d2, 0.0);
+        r->rho2hi.assign(d2 * d2, 0.0);
+        r->rho2vi.assign(d2 * d2, 0.0);
+        if (r->Aim.empty()) {
+          rc = ctm_rdm_1site(c, 0, 0, r->rho1.data());
+          if (rc == CTM_OK) rc = ctm_rdm_2site(c, 0, 0, 0, r->rho2h.data());
+          if (rc == CTM_OK) rc = ctm_rdm_2site(c, 0, 0, 1, r->rho2v.data());
+        } else {
+          rc = ctm_rdm_1site_complex(c, 0, 0, r->rho1.data(), r->rho1i.data());
+          if (rc == CTM_OK) rc = ctm_rdm_2site_complex(c, 0, 0, 0, r->rho2h.data(), r->rho2hi.data());
+          if (rc == CTM_OK) rc = ctm_rdm_2site_complex(c, 0, 0, 1, r->rho2v.data(), r->rho2vi.data());
+        }
       }
       if (rc != CTM_OK && c) msg = ctm_last_error(c);
     } catch (const std::exception& e) {
@@ -241,16 +253,19 @@ int ctm_server_create(ctm_server** out, size_t pool_bytes, int max_active) {
   return CTM_OK;
 }
 
-int ctm_server_submit(ctm_server* s, const double* A, int d, int D, int chi, int form, double tol, int max_iter,
-                      long long* id) {
+static int submit(ctm_server* s, const double* A, const double* Aim, int d, int D, int chi, int form, double tol,
+                  int max_iter, long long* id) {
   if (!s || !A || !id) return CTM_E_ARG;
   if (form != CTM_FORM_Z2 && form != CTM_FORM_DENSE) return CTM_E_ARG;
+  if (Aim && form != CTM_FORM_Z2) return CTM_E_ARG;
+  if (Aim && d > 8) return CTM_E_ARG;
   if (!(tol > 0.0) || max_iter < 1) return CTM_E_ARG;
   ctm_opts o;
   ctm_opts_default(&o);
   o.form = form;
   size_t ws = 0;
-  const int rc = ctm_workspace_size(d, D, chi, &o, &ws);  // checks d, D, chi
+  // checks d, D, chi
+  const int rc = Aim ? ctm_workspace_size_complex(d, D, chi, &o, &ws) : ctm_workspace_size(d, D, chi, &o, &ws);
   if (rc != CTM_OK) return rc;
   if (round_up(ws) > s->pool_bytes) return CTM_E_NOMEM;
   try {
@@ -259,6 +274,11 @@ int ctm_server_submit(ctm_server* s, const double* A, int d, int D, int chi, int
     r->A.assign(A, A + n);
     for (double x : r->A)
       if (!std::isfinite(x)) return CTM_E_NUMERIC;
+    if (Aim) {
+      r->Aim.assign(Aim, Aim + n);
+      for (double x : r->Aim)
+        if (!std::isfinite(x)) return CTM_E_NUMERIC;
+    }
     r->d = d;
     r->D = D;
     r->chi = chi;
@@ -280,8 +300,19 @@ int ctm_server_submit(ctm_server* s, const double* A, int d, int D, int chi, int
   return CTM_OK;
 }
 
-int ctm_server_wait(ctm_server* s, long long id, double* rho1, double* rho2_h, double* rho2_v,
-                    ctm_solve_info* info) {
+int ctm_server_submit(ctm_server* s, const double* A, int d, int D, int chi, int form, double tol, int max_iter,
+                      long long* id) {
+  return submit(s, A, nullptr, d, D, chi, form, tol, max_iter, id);
+}
+
+int ctm_server_submit_complex(ctm_server* s, const double* A_re, const double* A_im, int d, int D, int chi,
+                              double tol, int max_iter, long long* id) {
+  if (!A_im) return CTM_E_ARG;
+  return submit(s, A_re, A_im, d, D, chi, CTM_FORM_Z2, tol, max_iter, id);
+}
+
+static int wait_for(ctm_server* s, long long id, double* rho1, double* rho2_h, double* rho2_v, double* rho1_im,
+                    double* rho2_h_im, double* rho2_v_im, ctm_solve_info* info) {
   if (!s) return CTM_E_ARG;
   std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->all.find(id);
@@ -294,10 +325,23 @@ int ctm_server_wait(ctm_server* s, long long id, double* rho1, double* rho2_h, d
     if (rho1) std::memcpy(rho1, r->rho1.data(), sizeof(double) * r->rho1.size());
     if (rho2_h) std::memcpy(rho2_h, r->rho2h.data(), sizeof(double) * r->rho2h.size());
     if (rho2_v) std::memcpy(rho2_v, r->rho2v.data(), sizeof(double) * r->rho2v.size());
+    if (rho1_im) std::memcpy(rho1_im, r->rho1i.data(), sizeof(double) * r->rho1i.size());
+    if (rho2_h_im) std::memcpy(rho2_h_im, r->rho2hi.data(), sizeof(double) * r->rho2hi.size());
+    if (rho2_v_im) std::memcpy(rho2_v_im, r->rho2vi.data(), sizeof(double) * r->rho2vi.size());
   }
   if (info) *info = r->info;
   s->all.erase(it);
   return CTM_OK;
+}
+
+int ctm_server_wait(ctm_server* s, long long id, double* rho1, double* rho2_h, double* rho2_v,
+                    ctm_solve_info* info) {
+  return wait_for(s, id, rho1, rho2_h, rho2_v, nullptr, nullptr, nullptr, info);
+}
+
+int ctm_server_wait_complex(ctm_server* s, long long id, double* rho1_re, double* rho1_im, double* rho2_h_re,
+                            double* rho2_h_im, double* rho2_v_re, double* rho2_v_im, ctm_solve_info* info) {
+  return wait_for(s, id, rho1_re, rho2_h_re, rho2_v_re, rho1_im, rho2_h_im, rho2_v_im, info);
 }
 
 int ctm_server_load(ctm_server* s, int* waiting, int* running) {

@@ -75,3 +75,25 @@ def test_too_large_request_is_refused():
     with pytest.raises(HctmError):
         srv.submit(inputs.iid_tensor(2, 4, 0), 64)
     srv.close()
+
+
+def test_served_results_against_the_oracle():
+    """A small served mix (real Z2 and plain forms, a complex tensor) run
+    concurrently: each result equals the oracle after the same number of
+    iterations (1e-10)."""
+    from oracle import complex_z2, ctmrg
+    from paper_2410_11596_amd import Server
+
+    reqs = [(inputs.iid_tensor(2, 2, 21), 12, "z2"), (inputs.iid_tensor(2, 3, 22), 16, "dense"),
+            (inputs.complex_iid_tensor(2, 2, 23), 12, "z2"), (inputs.iid_tensor(2, 3, 24), 20, "z2")]
+    srv = Server(1 << 30, max_active=4)
+    ids = [srv.submit(A, chi, form=form, tol=TOL, max_iter=30) for A, chi, form in reqs]
+    res = [srv.wait(i) for i in ids]
+    srv.close()
+    for (A, chi, form), r in zip(reqs, res):
+        assert r["status"] == 0, r["message"]
+        it = r["iterations"]
+        o = complex_z2.Run(chi, A).step(it) if np.iscomplexobj(A) else ctmrg.Run(chi, form, A=A).step(it)
+        assert np.abs(r["rho1"] - o.rho1()).max() < 1e-10
+        assert np.abs(r["rho2_h"] - o.rho2("h")).max() < 1e-10
+        assert np.abs(r["rho2_v"] - o.rho2("v")).max() < 1e-10
