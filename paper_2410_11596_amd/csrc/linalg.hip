@@ -844,10 +844,63 @@ __device__ __forceinline__ void rr_pair(int r, int pp, int n2, int& i, int& j) {
 constexpr int kJacLanes = 8;
 constexpr int kJacRows = 20;  // rows per lane, m <= 160
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Every pair of the columns c0 .. c0 + nn - 1 of Xs at once: the Gram matrix
+// X^T X on the matrix cores (v_mfma_f64_16x16x4f64; lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[l / 16 + 4 v][l % 16]),
+// each off-diagonal entry against the pair test of the sweeps (with the cached
+// squared norms).  True if no pair would rotate, i.e. the next sweep would
+// rotate nothing.  Called by all threads of the workgroup.
+__device__ bool gram_orthogonal(const double* Xs, const double* nrm, int* fail, int m, int c0, int nn, double tol,
+                                double small2, int pairabs) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  if (threadIdx.x == 0) *fail = 0;
+  __syncthreads();
+  const int nt = (nn + 15) / 16, ntiles = nt * (nt + 1) / 2;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int t = wave; t < ntiles; t += nwave) {  // wave-uniform
+    int ti = 0, rem = t;
+    while (rem >= nt - ti) {
+      rem -= nt - ti;
+      ++ti;
+    }
+    const int tj = ti + rem;
+    const int ci = 16 * ti + li, cj = 16 * tj + li;
+    const bool oki = ci < nn, okj = cj < nn;
+    const double* xi = Xs + (long long)(c0 + (oki ? ci : 0)) * m;
+    const double* xj = Xs + (long long)(c0 + (okj ? cj : 0)) * m;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int r0 = 0; r0 < m; r0 += 4) {
+      const int r = r0 + lk;
+      const double a = (oki && r < m) ? xi[r] : 0.0;
+      const double b = (okj && r < m) ? xj[r] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    bool bad = false;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * ti + lk + 4 * v, j = 16 * tj + li;
+      if (i < j && j < nn) {
+        const double g = acc[v];
+        const double a2 = nrm[c0 + i], b2 = nrm[c0 + j];
+        if (fmin(a2, b2) > small2 && fabs(g) > (pairabs ? tol * fmax(a2, b2) : tol * sqrt(a2) * sqrt(b2))) bad = true;
+      }
+    }
+    if (bad) *fail = 1;
+  }
+  __syncthreads();
+  const bool ok = *fail == 0;
+  __syncthreads();
+  return ok;
+}
+
 // Sweeps of round-robin rotations over the columns c0 .. c0 + nn - 1 of Xs
-// (column-major, m rows) until a sweep rotates nothing; rotations logged as
-// (sweep, round, pair) from lg.  Returns the sweeps done (the converged one
-// included), negated when max_sweeps ran out first.
+// (column-major, m rows) until no pair would rotate; rotations logged as
+// (sweep, round, pair) from lg.  After a sweep that rotated, the pair test
+// is run on all pairs at once on the Gram matrix (gram_orthogonal), so that
+// the sweep that would only confirm convergence is not run.  Returns the
+// sweeps done (logged), negated when max_sweeps ran out first.
 __device__ int jacobi_sweeps(double* Xs, double* nrm, int* any_rot, int m, int c0, int nn, double tol,
                              double small2, int pairabs, int max_sweeps, double2* lg) {
   const int tid = threadIdx.x;
@@ -915,6 +968,7 @@ __device__ int jacobi_sweeps(double* Xs, double* nrm, int* any_rot, int m, int c
     const int rot = *any_rot;
     __syncthreads();
     if (!rot) return sweep + 1;  // the converged sweep is logged too (identity rotations)
+    if (gram_orthogonal(Xs, nrm, any_rot, m, c0, nn, tol, small2, pairabs)) return sweep + 1;
   }
   return -max_sweeps;
 }
@@ -1000,7 +1054,8 @@ __global__ __launch_bounds__(NT) void jacobi_lds_kernel(SmallBatch b) {
 // into P.work (global memory; at most 512 KB, so it stays in L2), one wave
 // works on one column pair with four rows per lane, the pairs a wave owns in
 // a round are loaded together; column norms cached in LDS; same rotation
-// order, tests, log layout and phases as the LDS kernel.
+// order, tests, log layout, phases and Gram-matrix convergence check as the
+// LDS kernel.
 constexpr int kJacL2Max = 256;
 constexpr int kJacL2Threads = 1024;
 constexpr int kJacL2Rows = kJacL2Max / 64;  // rows per lane
@@ -1084,6 +1139,7 @@ __device__ int jacobi_l2_sweeps(double* Xc, double* nrm, int* any_rot, int m, in
     const int rot = *any_rot;
     __syncthreads();
     if (!rot) return sweep + 1;
+    if (gram_orthogonal(Xc, nrm, any_rot, m, c0, nn, tol, small2, pairabs)) return sweep + 1;
   }
   return -max_sweeps;
 }
