@@ -568,11 +568,15 @@ def main():
                                                         "multiplet_splits_in_window")},
     }
     if stats["launches"] > 0 and stats["seconds"] > 0:
-        # mean algorithmic flops per launch over the mean launch duration; an
-        # event pair costs a fixed few microseconds even around no work, which
-        # is measured on the same stream and taken off every launch
+        # mean algorithmic flops per launch over the mean launch duration of
+        # the GEMM kernel (a HIP event right before and right after each of
+        # its launches, on the library's stream); an event pair costs a fixed
+        # few microseconds even around no work, which is measured on the same
+        # stream and taken off every launch.  The split-K reductions that
+        # follow some launches are timed apart and reported beside.
         ev = event_pair_overhead()
         kernel_s = stats["seconds"] - stats["launches"] * ev
+        red_s = stats["reduce_seconds"] - stats["reduce_launches"] * ev
         achieved = stats["flops"] / kernel_s / 1e12
         out["roofline"] = {
             "bound": "mfma",
@@ -587,6 +591,10 @@ def main():
             "avg_launch_us": 1e6 * kernel_s / stats["launches"],
             "event_pair_overhead_us": 1e6 * ev,
             "achieved_uncorrected": stats["flops"] / stats["seconds"] / 1e12,
+            "with_splitk_reduce": {"achieved": stats["flops"] / (kernel_s + red_s) / 1e12,
+                                   "frac": stats["flops"] / (kernel_s + red_s) / 1e12 / FP64_PEAK_TFLOPS,
+                                   "reduce_launches": stats["reduce_launches"],
+                                   "avg_reduce_us": 1e6 * red_s / max(1, stats["reduce_launches"])},
             "gemm_share_of_step": kernel_s / tz_prof,
             "profiled_pass_ms_per_step": 1e3 * tz_prof / args.steps,
         }

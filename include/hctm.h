@@ -297,9 +297,15 @@ int ctm_sector_dims(ctm_ctx* c, int x, int y, int side, int* chi_even, int* chi_
 int ctm_timing(ctm_ctx* c, double* t, int cap, int* n);
 
 /* Profile mode only (ctm_opts.profile = 1): algorithmic FP64 GEMM flops
- * (2*M*N*K per block product), summed GEMM launch durations in seconds and
- * the number of launches since the last reset; reset != 0 clears them. */
+ * (2*M*N*K per block product), the summed durations in seconds of the GEMM
+ * kernel launches (a HIP event right before and right after each) and their
+ * number since the last reset; reset != 0 clears them (and the reduction
+ * figures below). */
 int ctm_gemm_stats(ctm_ctx* c, double* flops, double* seconds, long long* launches, int reset);
+
+/* Profile mode only: the summed durations and the number of the split-K
+ * reductions that follow GEMM launches whose K was split over workgroups. */
+int ctm_gemm_reduce_stats(ctm_ctx* c, double* seconds, long long* launches);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,7 @@ EXPORTS = [
     "ctm_opts_default", "ctm_workspace_size", "ctm_init", "ctm_step", "ctm_converged",
     "ctm_rdm_1site", "ctm_rdm_2site", "ctm_energy", "ctm_free", "ctm_last_error",
     "ctm_env_epsilon", "ctm_s_err", "ctm_log_kappa", "ctm_num_records", "ctm_record",
-    "ctm_sector_dims", "ctm_timing", "ctm_gemm_stats", "ctm_set_precision",
+    "ctm_sector_dims", "ctm_timing", "ctm_gemm_stats", "ctm_gemm_reduce_stats", "ctm_set_precision",
     "ctm_corner_spectrum", "ctm_svd_health", "ctm_record_status",
     "ctm_workspace_size_complex", "ctm_init_complex", "ctm_rdm_1site_complex", "ctm_rdm_2site_complex",
     "ctm_server_create", "ctm_server_submit", "ctm_server_wait", "ctm_server_load", "ctm_server_destroy",
@@ -124,6 +124,7 @@ def lib():
         "ctm_record_status": ([ctx, ctypes.c_int, ip], ctypes.c_int),
         "ctm_timing": ([ctx, dp, ctypes.c_int, ip], ctypes.c_int),
         "ctm_gemm_stats": ([ctx, dp, dp, P(ctypes.c_longlong), ctypes.c_int], ctypes.c_int),
+        "ctm_gemm_reduce_stats": ([ctx, dp, P(ctypes.c_longlong)], ctypes.c_int),
         "hctm_dev_gemm": ([vp, vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.c_double, vp, vp,
                                                                ctypes.c_longlong, vp], ctypes.c_int),
         "hctm_dev_gemm_f32": ([vp, vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.c_double, vp, vp,
@@ -410,10 +411,15 @@ class CTMRG:
         return e.value, o.value
 
     def gemm_stats(self, reset=False):
+        """Profile mode: GEMM kernel flops, seconds and launches, and the
+        split-K reductions' seconds and launches (read before a reset)."""
         f, t, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_longlong()
+        rt, rn = ctypes.c_double(), ctypes.c_longlong()
+        _check(lib().ctm_gemm_reduce_stats(self._ctx, ctypes.byref(rt), ctypes.byref(rn)), self._ctx)
         _check(lib().ctm_gemm_stats(self._ctx, ctypes.byref(f), ctypes.byref(t), ctypes.byref(n), 1 if reset else 0),
                self._ctx)
-        return {"flops": f.value, "seconds": t.value, "launches": n.value}
+        return {"flops": f.value, "seconds": t.value, "launches": n.value, "reduce_seconds": rt.value,
+                "reduce_launches": rn.value}
 
     def timing(self):
         t = np.zeros(16)

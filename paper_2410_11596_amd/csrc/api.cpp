@@ -406,6 +406,15 @@ int ctm_timing(ctm_ctx* c, double* t, int cap, int* n) {
   });
 }
 
+int ctm_gemm_reduce_stats(ctm_ctx* c, double* seconds, long long* launches) {
+  if (!c) return CTM_E_ARG;
+  return guarded(c, [&] {
+    const hctm::GemmStats& g = c->ctm->gemm_stats;
+    if (seconds) *seconds = g.reduce_seconds;
+    if (launches) *launches = g.reduce_launches;
+  });
+}
+
 int ctm_gemm_stats(ctm_ctx* c, double* flops, double* seconds, long long* launches, int reset) {
   if (!c) return CTM_E_ARG;
   return guarded(c, [&] {

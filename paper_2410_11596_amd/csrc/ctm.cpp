@@ -292,21 +292,24 @@ void Ctm::launch_gemms(std::vector<GemmDesc>& g) {
     g.clear();
     return;
   }
-  double f = 0.0;
-  for (const GemmDesc& d : g)
-    if (d.M > 0 && d.N > 0 && d.K > 0) f += 2.0 * d.M * d.N * d.K;
-  while (gev_.size() < gev_used_ + 2) {
-    hipEvent_t e;
-    HCTM_HIP(hipEventCreate(&e));
-    gev_.push_back(e);
-  }
-  HCTM_HIP(hipEventRecord(gev_[gev_used_], st_));
-  gemm(g, st_, gemm_scratch_, gemm_scratch_cap_);
-  HCTM_HIP(hipEventRecord(gev_[gev_used_ + 1], st_));
-  gflops_.push_back(f);
-  gev_used_ += 2;
+  obs_.c = this;
+  gemm(g, st_, gemm_scratch_, gemm_scratch_cap_, &obs_);
   g.clear();
   if (gev_used_ >= 4096) flush_gemm_stats();
+}
+
+// profile mode: an event right before and right after every kernel launch
+// of gemm(), so that the GEMM kernel and the split-K reduction are timed
+// apart
+void Ctm::Observer::mark(int kind, int phase, double flops) {
+  if (c->gev_.size() < c->gev_used_ + 1) {
+    hipEvent_t e;
+    HCTM_HIP(hipEventCreate(&e));
+    c->gev_.push_back(e);
+  }
+  HCTM_HIP(hipEventRecord(c->gev_[c->gev_used_], c->st_));
+  ++c->gev_used_;
+  if (phase == 1) c->gflops_.push_back(kind == 0 ? flops : -1.0);
 }
 
 void Ctm::flush_gemm_stats() {
@@ -315,9 +318,14 @@ void Ctm::flush_gemm_stats() {
   for (size_t i = 0; i < gev_used_ / 2; ++i) {
     float ms = 0.f;
     HCTM_HIP(hipEventElapsedTime(&ms, gev_[2 * i], gev_[2 * i + 1]));
-    gemm_stats.seconds += ms * 1e-3;
-    gemm_stats.flops += gflops_[i];
-    gemm_stats.launches += 1;
+    if (gflops_[i] >= 0.0) {
+      gemm_stats.seconds += ms * 1e-3;
+      gemm_stats.flops += gflops_[i];
+      gemm_stats.launches += 1;
+    } else {
+      gemm_stats.reduce_seconds += ms * 1e-3;
+      gemm_stats.reduce_launches += 1;
+    }
   }
   gev_used_ = 0;
   gflops_.clear();

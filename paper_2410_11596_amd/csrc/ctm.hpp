@@ -62,8 +62,10 @@ struct Options {
 
 struct GemmStats {
   double flops = 0.0;    // algorithmic 2*M*N*K summed over problems
-  double seconds = 0.0;  // summed launch durations
+  double seconds = 0.0;  // summed durations of the GEMM kernel launches
   long long launches = 0;
+  double reduce_seconds = 0.0;  // split-K reductions that follow some of them
+  long long reduce_launches = 0;
 };
 
 // per-sector state of the truncated SVD
@@ -276,9 +278,14 @@ class Ctm {
   double* rho_ = nullptr;      // device RDM outputs (2 ns d^4)
   double* hdev_ = nullptr;     // bond operator (d^4)
   MoveRecord pending_;
-  // profile mode: pending GEMM event pairs and their flops
+  // profile mode: pending event pairs around every GEMM kernel (kind 0) and
+  // split-K reduction (kind 1) launch, and the GEMM kernels' flops
+  struct Observer : GemmObserver {
+    Ctm* c = nullptr;
+    void mark(int kind, int phase, double flops) override;
+  } obs_;
   std::vector<hipEvent_t> gev_;
-  std::vector<double> gflops_;
+  std::vector<double> gflops_;  // flops per pair; < 0: a reduction pair
   size_t gev_used_ = 0;
   void flush_gemm_stats();
 };

@@ -370,7 +370,7 @@ long long tiles(const GemmDesc& d, int bm, int bn) {
 
 namespace {
 void gemm_one_type(const std::vector<GemmDesc>& probs, int prec, hipStream_t s, double* scratch,
-                   long long scratch_cap) {
+                   long long scratch_cap, GemmObserver* obs) {
   // tile shape for the whole call, from how many workgroups it yields: the
   // large tile when it alone fills the chip (FP64: 128 x 64, measured faster
   // than 128 x 128 on the 2592^3 to 8192^3 block products, 55-65 against
@@ -394,6 +394,9 @@ void gemm_one_type(const std::vector<GemmDesc>& probs, int prec, hipStream_t s, 
   long long split_mn = 0;
   auto flush = [&]() {
     if (g.n == 0) return;
+    double f = 0.0;
+    for (int i = 0; i < g.n; ++i) f += 2.0 * g.p[i].M * g.p[i].N * (double)g.p[i].K;
+    if (obs) obs->mark(0, 0, f);
     if (prec == 0 && cfg == 0)
       hipLaunchKernelGGL((gemm_f64_kernel<128, 64>), dim3(g.total), dim3(NT), 0, s, g);
     else if (prec == 0)
@@ -407,11 +410,14 @@ void gemm_one_type(const std::vector<GemmDesc>& probs, int prec, hipStream_t s, 
     else
       hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 64>), dim3(g.total), dim3(NT), 0, s, g);
     HCTM_HIP(hipGetLastError());
+    if (obs) obs->mark(0, 1, f);
     if (any_split) {
       // one thread per output element of the largest split problem
       const unsigned gx = (unsigned)std::min<long long>(2048, (split_mn + 255) / 256);
+      if (obs) obs->mark(1, 0, 0.0);
       hipLaunchKernelGGL(splitk_reduce_kernel, dim3(gx, g.n), dim3(256), 0, s, g);
       HCTM_HIP(hipGetLastError());
+      if (obs) obs->mark(1, 1, 0.0);
     }
     g.n = 0;
     g.total = 0;
@@ -474,13 +480,14 @@ void gemm_one_type(const std::vector<GemmDesc>& probs, int prec, hipStream_t s, 
 }
 }  // namespace
 
-void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch, long long scratch_cap) {
+void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch, long long scratch_cap,
+          GemmObserver* obs) {
   // problems of different arithmetic go to separate launches (all problems
   // of one call are independent)
   std::vector<GemmDesc> by[3];
   for (const GemmDesc& d : probs) by[(d.prec >= 0 && d.prec <= 2) ? d.prec : 0].push_back(d);
   for (int p = 0; p < 3; ++p)
-    if (!by[p].empty()) gemm_one_type(by[p], p, s, scratch, scratch_cap);
+    if (!by[p].empty()) gemm_one_type(by[p], p, s, scratch, scratch_cap, obs);
 }
 
 }  // namespace hctm

@@ -40,8 +40,16 @@ struct GemmDesc {
                          // 2: BF16x3 (operands split into BF16 hi + lo, hi*hi + hi*lo + lo*hi
                          //    on BF16 MFMA with FP32 accumulation)
 };
+// Optional observer of the kernels gemm() launches, called on the host right
+// before (phase 0) and after (phase 1) each launch: kind 0 a GEMM kernel
+// (flops = algorithmic 2 M N K of its problems), kind 1 a split-K reduction.
+struct GemmObserver {
+  virtual void mark(int kind, int phase, double flops) = 0;
+  virtual ~GemmObserver() = default;
+};
 // scratch (optional): device doubles for split-K partial tiles.
-void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch = nullptr, long long scratch_cap = 0);
+void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch = nullptr, long long scratch_cap = 0,
+          GemmObserver* obs = nullptr);
 
 // -------------------------------------------------------------- permute ----
 // Strided copy of one dense block: out[sum_j x_j ostr_j] = in[sum_j x_j istr_j]
