@@ -94,18 +94,38 @@ def time_form(A, chi, form, steps, warmup, profile):
     torch.cuda.synchronize()
     g.gemm_stats(reset=True)
     h0 = g.svd_health()
+    nrec0 = g.num_records()
+    # one iteration per call, an event on the library's stream between them:
+    # the window's total and each iteration's own time
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    g.step(steps)
+    ev[0].record()
+    phases = np.zeros(len(PHASES))
+    for i in range(steps):
+        g.step(1)
+        ev[i + 1].record()
+        phases += g.timing()  # GPU seconds per phase of this iteration
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
     stats = g.gemm_stats()
-    phases = g.timing()
     split = g.sector_dims(3)
     h1 = g.svd_health()
+    recs = [g.record(m) for m in range(nrec0, g.num_records())]
+    g.close()
     stats["svd_unconverged_in_window"] = h1[0] - h0[0]
     stats["multiplet_splits_in_window"] = h1[1] - h0[1]
-    stats["truncations_in_window"] = 4 * steps
-    g.close()
+    stats["truncations_in_window"] = len(recs)
+    # per truncation, the larger of the two sectors' counts
+    stats["svd_in_window"] = {
+        "truncations": len(recs),
+        "with_subspace_iteration": int(sum(max(r["iters"]) > 0 for r in recs)),
+        "subspace_iterations_mean": float(np.mean([max(r["iters"]) for r in recs])) if recs else 0.0,
+        "jacobi_sweeps_mean": float(np.mean([max(r["sweeps"]) for r in recs])) if recs else 0.0,
+        "matrix_applied_through_corners": int(sum(r["implicit"] for r in recs)),
+    }
+    stats["iteration_ms"] = {"p10": float(np.percentile(per, 10)), "p50": float(np.percentile(per, 50)),
+                             "p90": float(np.percentile(per, 90))}
     return (t1 - t0), stats, phases, split
 
 
@@ -566,6 +586,8 @@ def main():
         "phases_sum_ms_per_step": 1e3 * float(np.sum(phases)) / args.steps,
         "svd_health_in_window": {k: zstats[k] for k in ("truncations_in_window", "svd_unconverged_in_window",
                                                         "multiplet_splits_in_window")},
+        "svd_in_window": zstats["svd_in_window"],
+        "iteration_ms": zstats["iteration_ms"],
     }
     if stats["launches"] > 0 and stats["seconds"] > 0:
         # mean algorithmic flops per launch over the mean launch duration of
@@ -614,6 +636,8 @@ def main():
             "phases_ms_per_step": dph,
             "svd_health_in_window": {k: dstats[k] for k in ("truncations_in_window", "svd_unconverged_in_window",
                                                             "multiplet_splits_in_window")},
+            "svd_in_window": dstats["svd_in_window"],
+            "iteration_ms": dstats["iteration_ms"],
             "phases_sum_ms_per_step": sum(dph.values()),
             "z2_over_dense": z2_rate / dense_rate,
             "matched_window": args.dense_steps == args.steps,

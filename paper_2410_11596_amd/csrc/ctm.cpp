@@ -656,34 +656,71 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
     }
     // subspace iteration (both sectors batched)
     if (!sub.empty()) {
+      // Start block Q_r.  Warm (the cut's previous right vectors V, k_w of
+      // them, orthonormal): [V | R] with the random columns R made
+      // orthogonal to V by one block Gram-Schmidt step, R -= V (V^T R); the
+      // block only seeds the first product M Q_r, whose orthonormalisation
+      // follows.  Cold: random columns orthonormalised by three CholeskyQR
+      // passes.
       std::vector<CopyJob> jobs;
+      std::vector<SvdSector*> cold;
+      std::vector<GemmDesc> proj, rem;
       for (SvdSector* S : sub) {
         const int P = S == &sec_[1] ? 1 : 0;
         const uint64_t seed = opt_.seed * 0x9E3779B97F4A7C15ull + (salt << 4) + P + ((uint64_t)attempt << 2);
-        random_fill(S->Y, (size_t)S->n * S->l, seed, st_);
         const WarmV& w = warm_[key * 2 + P];
-        if (attempt == 0 && w.V && w.n == S->n && w.k > 0) {
-          // previous right vectors in the leading columns
-          S->warm = true;
-          CopyJob j{};
-          j.in = w.V;
-          j.out = S->Y;
-          j.r = 2;
-          j.dims[0] = S->n;
-          j.dims[1] = std::min(w.k, S->l);
-          j.istr[0] = w.k;
-          j.istr[1] = 1;
-          j.ostr[0] = S->l;
-          j.ostr[1] = 1;
-          jobs.push_back(j);
+        S->warm = attempt == 0 && w.V && w.n == S->n && w.k > 0;
+        random_fill(S->warm ? S->Qr : S->Y, (size_t)S->n * S->l, seed, st_);
+        if (!S->warm) {
+          S->passes = 3;
+          cold.push_back(S);
+          continue;
         }
-        // a warm block is its own well-conditioned basis plus random columns:
-        // two passes orthonormalise it to rounding
-        S->passes = S->warm ? 2 : 3;
+        const int kw = std::min(w.k, S->l), pr = S->l - kw;
+        CopyJob j{};
+        j.in = w.V;
+        j.out = S->Qr;
+        j.r = 2;
+        j.dims[0] = S->n;
+        j.dims[1] = kw;
+        j.istr[0] = w.k;
+        j.istr[1] = 1;
+        j.ostr[0] = S->l;
+        j.ostr[1] = 1;
+        jobs.push_back(j);
+        if (pr == 0) continue;
+        GemmDesc d{};  // G = V^T R (kw x pr)
+        d.A = S->Qr;
+        d.B = S->Qr + kw;
+        d.C = S->G;
+        d.M = kw;
+        d.N = pr;
+        d.K = S->n;
+        d.lda = S->l;
+        d.ldb = S->l;
+        d.ldc = pr;
+        d.ta = 1;
+        d.alpha = 1.0;
+        proj.push_back(d);
+        GemmDesc e{};  // R -= V G
+        e.A = S->Qr;
+        e.B = S->G;
+        e.C = S->Qr + kw;
+        e.M = S->n;
+        e.N = pr;
+        e.K = kw;
+        e.lda = S->l;
+        e.ldb = pr;
+        e.ldc = S->l;
+        e.alpha = -1.0;
+        e.beta = 1.0;
+        rem.push_back(e);
       }
       launch_copies(jobs);
-      for (SvdSector* S : sub) S->rel0 = 1e-10;
-      orth(sub, false);  // Qr
+      launch_gemms(proj);
+      launch_gemms(rem);
+      for (SvdSector* S : cold) S->rel0 = 1e-10;
+      if (!cold.empty()) orth(cold, false);  // Qr
       // Iterate; from the second iteration on, before a sector's new left
       // basis is formed, the residual of the leading columns of Y = M Q_r
       // outside the previous left basis (relative to the largest column)
