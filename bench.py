@@ -385,16 +385,20 @@ def serving_requests(n_req, seed=11, complex_share=0.1):
 
 def serving(n_req, rate, max_active=8, tol=1e-10, max_iter=60, seed=11, baseline_n=None):
     """A stream of n_req solves (serving_requests) with Poisson arrivals at
-    `rate` per second, each run to delta < tol (at most max_iter iterations):
-    latency = result ready - submitted.  Served: the Z2 form through the
-    server, up to max_active solves at a time, admitted by workspace.
-    Baseline: the first baseline_n requests of the same stream, one at a time,
-    in the plain (dense) FP64 form (the complex ones, which have no plain GPU
-    form, in their Z2 form), arriving at the same times."""
-    from paper_2410_11596_amd import Server, workspace_size
-    from paper_2410_11596_amd.binding import lib, CtmOpts, _check
+    `rate` per second, each run to delta < tol (at most max_iter iterations)
+    and its RDMs read: latency = result ready - arrival.  Served: the Z2 form
+    through the server, up to max_active solves at a time, admitted by
+    workspace.  Baseline: the first baseline_n requests of the same stream,
+    one at a time, in the plain (dense) FP64 form (the complex ones, which
+    have no plain GPU form, in their Z2 form), queued behind each other."""
     import ctypes
 
+    import torch
+
+    from paper_2410_11596_amd import Server, workspace_size
+    from paper_2410_11596_amd.binding import lib, CtmOpts, _check
+
+    torch.cuda.init()  # before the server's streams: the baseline runs through torch's device
     reqs = serving_requests(n_req, seed)
     rng = np.random.default_rng(seed + 1)
     gaps = rng.exponential(1.0 / rate, n_req)
@@ -414,31 +418,74 @@ def serving(n_req, rate, max_active=8, tol=1e-10, max_iter=60, seed=11, baseline
                   "tensors, 10% complex (real and imaginary parts N(0,1)) at D <= 5",
            "complex_requests": int(sum(c for _, _, c, _ in reqs))}
     nb = n_req if baseline_n is None else min(baseline_n, n_req)
-    runs = [("concurrent_z2", max_active, "z2", n_req)]
+    arrive = np.cumsum(gaps)
+    # served: the Z2 form through the server, up to max_active at a time
+    pool = max_active * big + (1 << 24)
+    srv = Server(pool, max_active=max_active)
+    t0 = time.perf_counter()
+    ids = []
+    for (D, chi, cplx, A), at in zip(reqs, arrive):
+        time.sleep(max(0.0, t0 + at - time.perf_counter()))
+        ids.append(srv.submit(A, chi, form="z2", tol=tol, max_iter=max_iter))
+        if len(ids) % 32 == 0:
+            print(f"serving concurrent_z2: {len(ids)}/{n_req} submitted", file=sys.stderr, flush=True)
+    res = []
+    for i in ids:
+        res.append(srv.wait(i))
+        if len(res) % 32 == 0:
+            print(f"serving concurrent_z2: {len(res)}/{n_req} done", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    srv.close()
+    lat = np.array([r["t_end"] - r["t_submit"] for r in res])
+    out["concurrent_z2"] = {"requests": n_req, "max_active": max_active,
+                            "p50_latency_s": float(np.percentile(lat, 50)),
+                            "p99_latency_s": float(np.percentile(lat, 99)), "solves_per_s": n_req / (t1 - t0),
+                            "wall_s": t1 - t0, "failed": int(sum(r["status"] != 0 for r in res)),
+                            "converged": int(sum(r["converged"] for r in res)),
+                            "iterations": int(sum(r["iterations"] for r in res)), "pool_bytes": int(pool)}
+    if 0 < nb < n_req:
+        out["concurrent_z2"]["first_%d" % nb] = {"p50_latency_s": float(np.percentile(lat[:nb], 50)),
+                                                 "p99_latency_s": float(np.percentile(lat[:nb], 99))}
+    print(json.dumps({"concurrent_z2": out["concurrent_z2"]}), file=sys.stderr, flush=True)
     if nb > 0:
-        runs.append(("one_at_a_time_dense", 1, "dense", nb))
-    for label, act, form, nrun in runs:
-        pool = act * big + (1 << 24)
-        srv = Server(pool, max_active=act)
-        t0 = time.perf_counter()
-        ids = []
-        for (D, chi, cplx, A), gap in zip(reqs[:nrun], gaps[:nrun]):
-            time.sleep(gap)
-            ids.append(srv.submit(A, chi, form="z2" if cplx else form, tol=tol, max_iter=max_iter))
-        res = [srv.wait(i) for i in ids]
-        t1 = time.perf_counter()
-        srv.close()
-        lat = np.array([r["t_end"] - r["t_submit"] for r in res])
-        out[label] = {"requests": nrun, "max_active": act, "p50_latency_s": float(np.percentile(lat, 50)),
-                      "p99_latency_s": float(np.percentile(lat, 99)), "solves_per_s": nrun / (t1 - t0),
-                      "wall_s": t1 - t0, "failed": int(sum(r["status"] != 0 for r in res)),
-                      "converged": int(sum(r["converged"] for r in res)),
-                      "iterations": int(sum(r["iterations"] for r in res)),
-                      "pool_bytes": int(pool)}
-        if label == "concurrent_z2" and nb > 0 and nb < n_req:
-            lat_b = lat[:nb]
-            out[label]["first_%d" % nb] = {"p50_latency_s": float(np.percentile(lat_b, 50)),
-                                           "p99_latency_s": float(np.percentile(lat_b, 99))}
+        # baseline: one solve at a time in the plain FP64 form (complex
+        # requests, which have no plain form, in their Z2 form), the same
+        # arrivals: solve i starts when it has arrived and solve i-1 is done
+        from paper_2410_11596_amd import CTMRG
+
+        end = 0.0
+        lat_b, iters, conv_n = [], 0, 0
+        for i, ((D, chi, cplx, A), at) in enumerate(zip(reqs[:nb], arrive[:nb])):
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            g = CTMRG(A, chi, form="z2" if cplx else "dense")
+            it, conv = 0, False
+            while it < max_iter and not conv:
+                g.step(1)
+                it += 1
+                conv = g.converged(tol)[0]
+                if it % 10 == 0:
+                    print(f"baseline solve {i + 1}/{nb} (D={D}, chi={chi}): {it} iterations", file=sys.stderr,
+                          flush=True)
+            g.rdm1()
+            g.rdm2("h")
+            g.rdm2("v")
+            g.close()
+            torch.cuda.synchronize()
+            dur = time.perf_counter() - s0
+            end = max(at, end) + dur
+            lat_b.append(end - at)
+            iters += it
+            conv_n += int(conv)
+            print(f"baseline solve {i + 1}/{nb} done in {dur:.2f} s", file=sys.stderr, flush=True)
+        lat_b = np.array(lat_b)
+        out["one_at_a_time_dense"] = {"requests": nb, "max_active": 1,
+                                      "p50_latency_s": float(np.percentile(lat_b, 50)),
+                                      "p99_latency_s": float(np.percentile(lat_b, 99)),
+                                      "solves_per_s": nb / end, "wall_s": end, "converged": conv_n,
+                                      "iterations": iters,
+                                      "queue": "one server: solve i starts at max(arrival i, end of solve i-1); "
+                                               "solves run back to back, arrivals on the same clock"}
     return out
 
 

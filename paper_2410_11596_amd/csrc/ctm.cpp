@@ -604,6 +604,17 @@ void Ctm::apply_M(std::vector<SvdSector*>& ss, bool trans) {
   }
 }
 
+// H_u = Q1 Q2, H_d = Q3 Q4 and M = H_d H_u from the enlarged corners of the
+// current cut (impl_q_).
+void Ctm::form_M() {
+  std::vector<GemmDesc> g;
+  plan_contract(*impl_q_[0], *impl_q_[1], Hu_, 1.0, 0.0, g);
+  plan_contract(*impl_q_[2], *impl_q_[3], Hd_, 1.0, 0.0, g);
+  launch_gemms(g);
+  plan_contract(Hd_, Hu_, M_, 1.0, 0.0, g);
+  launch_gemms(g);
+}
+
 // Truncated SVD of both sector blocks of M (batched): randomized subspace
 // iteration, Rayleigh-Ritz and one-sided Jacobi, or Jacobi on the block itself
 // when it is small.  key selects the cut: its previous kept count guesses the
@@ -618,6 +629,7 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
   implicit_ = M == nullptr;
   for (int attempt = 0; attempt < 4; ++attempt) {
     std::vector<SvdSector*> sub, all;
+    bool restart = false;
     for (int P = 0; P < 2; ++P) {
       SvdSector& S = sec_[P];
       // M acts on the east cut: H_d H_u = Q3 Q4 Q1 Q2
@@ -641,7 +653,17 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
       S.l = std::min<int>(std::min(S.n, kg + p), l_cap_);
       S.direct = S.n <= kDirectMax || S.l >= S.n;
       if (S.direct && S.n > l_cap_) throw Error(1, "truncated_svd: sector too large for a direct decomposition");
-      if (S.direct && implicit_) throw Error(1, "truncated_svd: a direct decomposition needs the matrix");
+      if (S.direct && implicit_) {
+        // a retry's subspace (kept count + 64) reaches the sector size: the
+        // block is decomposed directly, which needs M itself; form it from
+        // the enlarged corners and restart this attempt on it
+        form_M();
+        implicit_ = false;
+        M = &M_;
+        --attempt;
+        restart = true;
+        break;
+      }
       if (S.direct) {
         S.l = S.n;
         S.conv = true;
@@ -654,6 +676,7 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
       all.push_back(&S);
       if (!S.direct) sub.push_back(&S);
     }
+    if (restart) continue;
     // subspace iteration (both sectors batched)
     if (!sub.empty()) {
       // Start block Q_r.  Warm (the cut's previous right vectors V, k_w of
@@ -1016,20 +1039,17 @@ void Ctm::move(int r) {
         const int l = std::min(std::min(n, kg + oversample(kg, key)), l_cap_);
         if (n <= kDirectMax || l >= n) implicit = false;
       }
+      impl_q_[0] = &Q1;
+      impl_q_[1] = &Q2;
+      impl_q_[2] = &Q3;
+      impl_q_[3] = &Q4;
       if (implicit) {
-        impl_q_[0] = &Q1;
-        impl_q_[1] = &Q2;
-        impl_q_[2] = &Q3;
-        impl_q_[3] = &Q4;
         mark(2);
         truncated_svd(nullptr, chi_, key, (uint64_t)records_.size());
+        // a retry with a larger subspace may have needed the matrix itself
+        implicit = implicit_;
       } else {
-        std::vector<GemmDesc> g;
-        plan_contract(Q1, Q2, Hu_, 1.0, 0.0, g);
-        plan_contract(Q3, Q4, Hd_, 1.0, 0.0, g);
-        launch_gemms(g);
-        plan_contract(Hd_, Hu_, M_, 1.0, 0.0, g);
-        launch_gemms(g);
+        form_M();
         mark(2);
         truncated_svd(&M_, chi_, key, (uint64_t)records_.size());
       }

@@ -151,6 +151,7 @@ class Ctm {
   void move_c4v();
   void mark(int phase);
   void truncated_svd(const BT* M, int chi, int key, uint64_t salt);  // M null: apply via impl_q_
+  void form_M();  // H_u, H_d and M of the cut impl_q_
   void apply_M(std::vector<SvdSector*>& ss, bool trans);
   int oversample(int kg, int key) const;
   void orth(std::vector<SvdSector*>& ss, bool ql);

@@ -268,6 +268,34 @@ def test_subspace_iteration_cap_is_reported():
     assert h.svd_health()[0] == 0
 
 
+@pytest.mark.parametrize("form", ["dense", "z2"])
+def test_retry_that_needs_the_formed_matrix(form):
+    """D = 2, chi = 100 (a request of the serving stream, seed 1033): while
+    the bonds grow, a kept count passes the trusted part of a subspace that
+    was applied through the corners, and the retry with the larger block
+    reaches the sector size, so that block is decomposed directly on M formed
+    from the enlarged corners.  The solve completes and matches the oracle.
+
+    This input keeps singular values down to the 1e-12 cutoff from the first
+    iteration on and is ill-conditioned at that level: a 1e-15 relative
+    perturbation of the tensor moves the oracle's own delta by up to 2e-8,
+    its corner spectra by up to 6e-8 and its rho1 by up to 2.8e-10 (measured
+    over three iterations).  So delta is compared to 1e-6 and the RDMs to
+    1e-9; the kept sector sizes exactly."""
+    iters = 6
+    A = inputs.iid_tensor(2, 2, 1033)
+    o = ctmrg.Run(100, form, A=A).step(iters)
+    g = _gpu_launch(A, 100, form)
+    for it in range(iters):
+        g.step(1)
+        assert abs(g.converged(0.0)[1] - o.deltas[it]) < 1e-6, it
+    assert [tuple(r["kept"]) for r in g.records()] == [tuple(r["kept"]) for r in o.records]
+    assert np.abs(g.rdm1() - o.rho1()).max() < 1e-9
+    assert np.abs(g.rdm2("h") - o.rho2("h")).max() < 1e-9
+    assert np.abs(g.rdm2("v") - o.rho2("v")).max() < 1e-9
+    assert any(max(r["iters"]) > 0 for r in g.records())  # the subspace path ran
+
+
 def test_product_state_has_zero_delta():
     """A product state's corners have rank one from the start: delta is zero
     after the first iteration, the corner spectra are (1, 0, ...)."""
