@@ -41,6 +41,7 @@ namespace hctm {
 
 namespace {
 constexpr int kDirectMax = 160;  // sectors up to this size are decomposed directly
+constexpr int kWideBlock = 128;  // subspace width reached while a cut converges slowly
 constexpr int kJacobiSweeps = 40;
 // relative residual of the leading columns that ends the subspace iteration
 constexpr double kSubspaceTol = 1e-12;
@@ -149,6 +150,7 @@ void Ctm::plan_memory(bool counting) {
   }
   kg_.assign(4 * kMaxCell * kMaxCell, std::array<int, 2>{0, 0});
   iters_prev_.assign(4 * kMaxCell * kMaxCell, 0);
+  chi_cut_.assign(4 * kMaxCell * kMaxCell, 0);
   // right vectors of the last truncation of every cut (warm starts)
   warm_cap_ = ncap * cc;
   warm_.assign(2 * 4 * kMaxCell * kMaxCell, WarmV());
@@ -463,12 +465,18 @@ void Ctm::quadrant(int s, int j) {
 }
 
 // ---------------------------------------------------------------- SVD ----
-// Oversampling of the subspace for a kept-state guess kg at a cut: half the
-// guess (at least 32) while the cut's subspace iteration still needs many
-// iterations, 16 once it converges within three.
+// Oversampling of the subspace for a kept-state guess kg at a cut: 16 once
+// the cut's subspace iteration converges within three iterations; before
+// that half the guess (at least 32), and where chi ended the last truncation
+// at this cut (the spectrum continues above the cutoff) widened to a block of
+// up to 128 columns (at most 64 more than the guess): the tall products M Q
+// cost the same for any block width up to 128, and the wider block converges
+// faster where the spectrum is flat at the cut.
 int Ctm::oversample(int kg, int key) const {
   const int it = iters_prev_[key];
-  return (it > 0 && it <= 3) ? 16 : std::max(32, kg / 2);
+  if (it > 0 && it <= 3) return 16;
+  const int p = std::max(32, kg / 2);
+  return (chi_cut_[key] && kg + p < kWideBlock) ? std::max(p, std::min(64, kWideBlock - kg)) : p;
 }
 
 // CholeskyQR of S->Y into Ql (ql) or Qr with S->passes passes per sector
@@ -917,6 +925,9 @@ void Ctm::truncated_svd(const BT* M, int chi, int key, uint64_t salt) {
   {
     const double smax = hmisc()[8], nxt = hmisc()[9], last = hmisc()[10];
     if (nxt > opt_.tau * smax && last > 0.0 && last / nxt - 1.0 < kSplitGap) svd_status_ |= kRecSplit;
+    // chi, not the cutoff, ended the kept states: the spectrum goes on above
+    // the cutoff, so a wider subspace block holds signal, not rounding noise
+    chi_cut_[key] = nxt > opt_.tau * smax;
   }
   if (svd_status_ & (kRecUnconvEven | kRecUnconvOdd)) ++svd_unconverged_;
   if (svd_status_ & kRecSplit) ++splits_;

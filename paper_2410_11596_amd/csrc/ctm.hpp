@@ -232,6 +232,7 @@ class Ctm {
   SvdSector sec_[2];
   std::vector<std::array<int, 2>> kg_;  // kept-state guess per (frame, column, row)
   std::vector<int> iters_prev_;           // subspace iterations of the last truncation per cut
+  std::vector<char> chi_cut_;             // the last truncation per cut was ended by chi, not the cutoff
   bool low_prec_ = false;  // block products launched now use opt_.precision (set per move phase)
   bool implicit_ = false;                 // M applied through the corners impl_q_
   const BT* impl_q_[4] = {nullptr, nullptr, nullptr, nullptr};
