@@ -856,7 +856,11 @@ __device__ __forceinline__ void rr_pair(int r, int pp, int n2, int& i, int& j) {
 // 27-31 % faster than 256 threads with 8 lanes per pair on 76-141 columns)
 constexpr int kJacNT = 1024;
 constexpr int kJacLanes = 16;
-constexpr int kJacRows = (160 + kJacLanes - 1) / kJacLanes;  // rows per lane, m <= 160
+constexpr int kJacMaxRows = 160;                 // rows of a matrix the LDS kernel takes
+constexpr int kJacRowsMax = kJacMaxRows / kJacLanes;  // rows per lane at that size
+// Rows per lane of the kernel instance for m rows (the row loops are unrolled
+// to this length, so small matrices take a short instance).
+inline int jacobi_rows_per_lane(int m) { return m <= 64 ? 4 : (m <= 128 ? 8 : kJacRowsMax); }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -915,6 +919,7 @@ __device__ bool gram_orthogonal(const double* Xs, const double* nrm, int* fail, 
 // is run on all pairs at once on the Gram matrix (gram_orthogonal), so that
 // the sweep that would only confirm convergence is not run.  Returns the
 // sweeps done (logged), negated when max_sweeps ran out first.
+template <int ROWS>
 __device__ int jacobi_sweeps(double* Xs, double* nrm, int* any_rot, int m, int c0, int nn, double tol,
                              double small2, int pairabs, int max_sweeps, double2* lg) {
   const int tid = threadIdx.x;
@@ -934,10 +939,10 @@ __device__ int jacobi_sweeps(double* Xs, double* nrm, int* any_rot, int m, int c
           j += c0;
           double* xi = Xs + i * m;
           double* xj = Xs + j * m;
-          double u[kJacRows], v[kJacRows];
+          double u[ROWS], v[ROWS];
           double g = 0.0;
 #pragma unroll
-          for (int q = 0; q < kJacRows; ++q) {
+          for (int q = 0; q < ROWS; ++q) {
             const int k = sub + kJacLanes * q;
             u[q] = k < m ? xi[k] : 0.0;
             v[q] = k < m ? xj[k] : 0.0;
@@ -954,7 +959,7 @@ __device__ int jacobi_sweeps(double* Xs, double* nrm, int* any_rot, int m, int c
             sn = c * t;
             double a2 = 0.0, b2 = 0.0;
 #pragma unroll
-            for (int q = 0; q < kJacRows; ++q) {
+            for (int q = 0; q < ROWS; ++q) {
               const int k = sub + kJacLanes * q;
               const double x = c * u[q] - sn * v[q], y = sn * u[q] + c * v[q];
               if (k < m) {
@@ -1000,6 +1005,7 @@ __host__ __device__ inline long long jacobi_pre_log_offset(int n, int max_sweeps
 // over all columns start from nearly orthogonal columns and converge in few
 // sweeps.  The result is the same one-sided Jacobi SVD (the full sweeps run
 // until a sweep rotates nothing).
+template <int ROWS>
 __global__ __launch_bounds__(kJacNT) void jacobi_lds_kernel(SmallBatch b) {
   __shared__ double Xs[kJacLds];
   __shared__ int any_rot;
@@ -1034,7 +1040,8 @@ __global__ __launch_bounds__(kJacNT) void jacobi_lds_kernel(SmallBatch b) {
   for (int ph = pre ? 0 : 1; ph < 2; ++ph) {
     const int c0 = ph == 0 ? n - pre : 0, nn = ph == 0 ? pre : n;
     double2* lg = (rlog && ph == 0) ? rlog + jacobi_pre_log_offset(n, P.max_sweeps) : rlog;
-    const int sw = jacobi_sweeps(Xs, nrm, &any_rot, m, c0, nn, tol, small2, P.flags & kJacPairAbs, P.max_sweeps, lg);
+    const int sw =
+        jacobi_sweeps<ROWS>(Xs, nrm, &any_rot, m, c0, nn, tol, small2, P.flags & kJacPairAbs, P.max_sweeps, lg);
     if (tid == 0 && P.info) {
       if (ph == 0)
         P.info[1] = sw < 0 ? -sw : sw;
@@ -1563,7 +1570,7 @@ void jacobi(const std::vector<SmallProb>& probs, hipStream_t s) {
   for (const SmallProb& p : probs) {
     if (p.n > 1024) throw Error(1, "jacobi: too many columns");
     const bool logok = !p.b || p.vlog;
-    if ((long long)p.m * p.n <= kJacLds && p.n <= 160 && logok)
+    if ((long long)p.m * p.n <= kJacLds && p.n <= 160 && p.m <= kJacMaxRows && logok)
       lds.push_back(p);
     else if (p.work && p.m <= kJacL2Max && p.n <= kJacL2Max && logok)
       l2.push_back(p);
@@ -1588,8 +1595,15 @@ void jacobi(const std::vector<SmallProb>& probs, hipStream_t s) {
           nmax = std::max(nmax, q.n);
         }
       }
-      if (kind == 0)
-        hipLaunchKernelGGL(jacobi_lds_kernel, dim3(b.n), dim3(kJacNT), 0, s, b);
+      int mmax = 0;
+      for (int j = 0; j < b.n; ++j) mmax = std::max(mmax, b.p[j].m);
+      const int rows = jacobi_rows_per_lane(mmax);
+      if (kind == 0 && rows == 4)
+        hipLaunchKernelGGL(jacobi_lds_kernel<4>, dim3(b.n), dim3(kJacNT), 0, s, b);
+      else if (kind == 0 && rows == 8)
+        hipLaunchKernelGGL(jacobi_lds_kernel<8>, dim3(b.n), dim3(kJacNT), 0, s, b);
+      else if (kind == 0)
+        hipLaunchKernelGGL(jacobi_lds_kernel<kJacRowsMax>, dim3(b.n), dim3(kJacNT), 0, s, b);
       else
         hipLaunchKernelGGL(jacobi_l2_kernel, dim3(b.n), dim3(kJacL2Threads), 0, s, b);
       HCTM_HIP(hipGetLastError());

@@ -174,11 +174,15 @@ def test_cholesky_inverse(hc, n):
 @pytest.mark.parametrize("m,n,pre,l2", [(1, 1, 0, 0), (8, 5, 0, 0), (8, 5, 2, 0), (40, 40, 0, 0), (40, 40, 16, 0),
                                         (120, 97, 0, 0), (120, 97, 33, 0), (126, 126, 42, 0), (150, 150, 0, 0),
                                         (201, 180, 0, 0), (150, 150, 0, 1), (160, 160, 16, 1), (216, 216, 72, 1),
-                                        (201, 180, 0, 1), (256, 256, 0, 1), (33, 7, 3, 1)])
+                                        (201, 180, 0, 1), (256, 256, 0, 1), (33, 7, 3, 1),
+                                        (64, 64, 0, 0), (100, 100, 16, 0), (128, 90, 0, 0), (129, 100, 0, 0),
+                                        (200, 60, 0, 0), (200, 60, 0, 1), (300, 40, 0, 0)])
 def test_jacobi_svd(hc, m, n, pre, l2):
-    """Jacobi SVD in LDS (n <= 160), in L2 with a scratch copy (l2 = 1, n <=
-    256) or in global memory (no scratch); with and without the first phase
-    over the trailing columns."""
+    """Jacobi SVD in LDS (n <= 160, m <= 160; instances of 4, 8 and 10 rows
+    per lane), in L2 with a scratch copy (l2 = 1, n, m <= 256) or in global
+    memory (no scratch); with and without the first phase over the trailing
+    columns; tall blocks with more rows than the LDS kernel takes (200 x 60,
+    300 x 40) go to the other kernels."""
     rng = np.random.default_rng(m + n)
     # graded singular values, as in the CTMRG spectra
     U, _ = np.linalg.qr(rng.standard_normal((m, m)))
