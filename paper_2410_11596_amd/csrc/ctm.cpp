@@ -42,6 +42,7 @@ namespace hctm {
 namespace {
 constexpr int kDirectMax = 160;  // sectors up to this size are decomposed directly
 constexpr int kWideBlock = 128;  // subspace width reached while a cut converges slowly
+constexpr int kCornerSweeps = 24;  // Jacobi sweeps of a corner spectrum with its rotations logged
 constexpr int kJacobiSweeps = 40;
 // relative residual of the leading columns that ends the subspace iteration
 constexpr double kSubspaceTol = 1e-12;
@@ -199,6 +200,20 @@ void Ctm::plan_memory(bool counting) {
   // column-major scratch that lets corner blocks beyond the LDS Jacobi (up
   // to 256 x 256) run in the L2-resident kernel
   cwork_ = cc <= 256 ? ar_.take((size_t)(ns * 8 * cc * cc)) : nullptr;
+  // warm start of those decompositions: per block the right vectors of the
+  // last one (two buffers, swapped at each update), the rotations of the new
+  // one and their log
+  if (cc <= 256) {
+    const long long nb = (long long)ns * 8;
+    cvec_[0] = ar_.take((size_t)(nb * cc * cc));
+    cvec_[1] = ar_.take((size_t)(nb * cc * cc));
+    cvj_ = ar_.take((size_t)(nb * cc * cc));
+    clog_n_ = (long long)jacobi_log_doubles(cc, kCornerSweeps);
+    clog_ = ar_.take((size_t)(nb * clog_n_));
+    cinfo_ = ti((int)(2 * nb));  // each block's sweep counts: the replay of its log reads them
+    cdims_.assign((size_t)nb, std::array<int, 2>{0, 0});
+    ccur_.assign((size_t)nb, 0);
+  }
   eps_.p = ar_.take((size_t)q4);
   eps_.capacity = q4;
   halves_cap_ = cc * cc * q;
@@ -1392,6 +1407,14 @@ void Ctm::move_c4v() {
 void Ctm::corner_spectra() {
   std::vector<SmallProb> jp;
   std::vector<SpecArgs> sa(ns_);
+  // Warm start (blocks up to 256 x 256): the block C is decomposed as
+  // X = C V with V the right vectors of its last decomposition (orthogonal,
+  // so X has C's singular values), whose columns are then nearly orthogonal
+  // and the one-sided Jacobi needs a few sweeps instead of about eight; the
+  // rotations R of this decomposition are logged and give the next V = V R.
+  // A block whose shape changed starts from V = identity (X = C).
+  std::vector<GemmDesc> warm_x, warm_v;
+  std::vector<int> fresh, updated;
   double* mat = cmat_;
   for (int st = 0; st < ns_; ++st) {
     SpecArgs& a = sa[st];
@@ -1399,28 +1422,76 @@ void Ctm::corner_spectra() {
       BT& C = env(st, 2 * c);
       for (int P = 0; P < 2; ++P) {
         const int m = (int)C.L.rows[P], n = (int)C.L.cols[P];
-        const long long slot = (long long)(st * 8 + 2 * c + P) * cc_;
+        const int b = st * 8 + 2 * c + P;
+        const long long slot = (long long)b * cc_;
         a.sv[2 * c + P] = csv_ + slot;
         a.nsv[2 * c + P] = (m > 0 && n > 0) ? n : 0;
+        const bool keep = cvj_ != nullptr && m > 0 && n > 0;
+        const bool warm = keep && cdims_[b][0] == m && cdims_[b][1] == n;
+        if (cvj_) cdims_[b] = {m, n};
         if (m == 0 || n == 0) continue;
-        HCTM_HIP(hipMemcpyAsync(mat, C.p + C.L.off[P], sizeof(double) * m * n, hipMemcpyDeviceToDevice, st_));
+        const long long boff = (long long)b * cc_ * cc_;
+        if (warm) {
+          GemmDesc d{};
+          d.A = C.p + C.L.off[P];
+          d.B = cvec_[ccur_[b]] + boff;
+          d.C = mat;
+          d.M = m;
+          d.N = n;
+          d.K = n;
+          d.lda = n;
+          d.ldb = n;
+          d.ldc = n;
+          d.alpha = 1.0;
+          warm_x.push_back(d);
+          GemmDesc e{};
+          e.A = cvec_[ccur_[b]] + boff;
+          e.B = cvj_ + boff;
+          e.C = cvec_[1 - ccur_[b]] + boff;
+          e.M = n;
+          e.N = n;
+          e.K = n;
+          e.lda = n;
+          e.ldb = n;
+          e.ldc = n;
+          e.alpha = 1.0;
+          warm_v.push_back(e);
+          updated.push_back(b);
+        } else {
+          HCTM_HIP(hipMemcpyAsync(mat, C.p + C.L.off[P], sizeof(double) * m * n, hipMemcpyDeviceToDevice, st_));
+          if (keep) fresh.push_back(b);
+        }
         SmallProb p{};
         p.a = mat;
         p.m = m;
         p.n = n;
         p.lda = n;
         p.rel = 1.1e-16 * std::max(m, 8);
-        p.max_sweeps = 40;
+        p.max_sweeps = keep ? kCornerSweeps : 40;
         p.info = kdev_ + 8;
         p.sv = csv_ + slot;
         p.perm = cperm_ + slot;
         p.work = cwork_ ? cwork_ + (mat - cmat_) : nullptr;
+        if (keep) {
+          p.b = cvj_ + boff;
+          p.vlog = clog_ + (long long)b * clog_n_;
+          p.info = cinfo_ + 2 * b;
+        }
         jp.push_back(p);
         mat += (long long)cc_ * cc_;
       }
     }
   }
+  launch_gemms(warm_x);
   jacobi(jp, st_);
+  launch_gemms(warm_v);
+  for (int b : updated) ccur_[b] = 1 - ccur_[b];
+  for (int b : fresh) {  // V = R
+    const int n = cdims_[b][1];
+    const long long boff = (long long)b * cc_ * cc_;
+    HCTM_HIP(hipMemcpyAsync(cvec_[ccur_[b]] + boff, cvj_ + boff, sizeof(double) * n * n, hipMemcpyDeviceToDevice,
+                            st_));
+  }
   std::swap(cspec_, cspec_old_);
   for (int st = 0; st < ns_; ++st) {
     SpecArgs& a = sa[st];

@@ -261,6 +261,13 @@ class Ctm {
   int* cperm_ = nullptr;
   double* cmat_ = nullptr;      // scratch copies of corner blocks
   double* cwork_ = nullptr;     // Jacobi scratch for them (cc_ <= 256)
+  double* cvec_[2] = {nullptr, nullptr};  // right vectors of each corner block's last decomposition
+  double* cvj_ = nullptr;       // rotations of the current one
+  double* clog_ = nullptr;      // their logs
+  long long clog_n_ = 0;        // doubles per log
+  int* cinfo_ = nullptr;        // each block's Jacobi sweep counts
+  std::vector<std::array<int, 2>> cdims_;  // block shape at the last decomposition
+  std::vector<char> ccur_;      // which of cvec_ holds a block's vectors
   bool have_old_spec_ = false;
   double delta_ = 1e300;
   // observables
