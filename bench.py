@@ -254,6 +254,36 @@ def large_shape(D=8, chi=256, warmup=2, steps=2):
     return res
 
 
+def complex_case(D=5, chi=100, warmup=5, steps=10):
+    """Complex iPEPS tensors (Sec. II C) in the real representation of their
+    Hermitian structure: Z2 FP64 time per iteration of a complex i.i.d.
+    tensor (real and imaginary parts N(0,1), seed 0) against the real path on
+    a real i.i.d. tensor of the same shape (seed 0), after `warmup`
+    iterations, with the iterations' subspace iterations and kept sizes."""
+    import torch
+
+    from paper_2410_11596_amd import CTMRG, inputs
+
+    res = {"workload": f"Z2 directional CTMRG, 1x1 cell, d=2 D={D}, chi={chi}, FP64: complex i.i.d. tensor "
+                       f"(real and imaginary parts N(0,1), seed 0) against a real i.i.d. tensor (seed 0)"}
+    for label, A in (("complex", inputs.complex_iid_tensor(2, D, 0)), ("real", inputs.iid_tensor(2, D, 0))):
+        g = CTMRG(A, chi)
+        g.step(warmup)
+        torch.cuda.synchronize()
+        n0 = g.num_records()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        recs = [g.record(m) for m in range(n0, g.num_records())]
+        res[label] = {"ms_per_step": 1e3 * (t1 - t0) / steps, "value": steps / (t1 - t0), "unit": "CTMRG iterations/s",
+                      "kept_last": list(recs[-1]["kept"]),
+                      "subspace_iterations_mean": float(np.mean([max(r["iters"]) for r in recs]))}
+        g.close()
+    res["complex_over_real_time"] = res["complex"]["ms_per_step"] / res["real"]["ms_per_step"]
+    return res
+
+
 def c4v_scheme(D, chi, steps, warmup, tol=1e-10, max_iter=200):
     """The C4v scheme (one corner, one edge, one truncation per iteration)
     against the directional moves, both Z2 FP64, on a C4v-symmetric tensor of
@@ -561,6 +591,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-block-product run")
     ap.add_argument("--no-late", action="store_true", help="skip the later-iterations timing of the same solve")
     ap.add_argument("--no-c4v", action="store_true", help="skip the C4v-scheme comparison")
+    ap.add_argument("--no-complex", action="store_true", help="skip the complex-tensor timing")
     ap.add_argument("--no-large", action="store_true", help="skip the D = 8, chi = 256 run")
     ap.add_argument("--no-hotrg", action="store_true", help="skip the HOTRG Z2/plain comparison")
     ap.add_argument("--hotrg-by-d", action="store_true", help="run only the HOTRG comparison over D at chi 64")
@@ -702,6 +733,8 @@ def main():
         out["large_d8_chi256"] = large_shape()
     if not args.no_c4v:
         out["c4v"] = c4v_scheme(args.D, args.chi, args.steps, args.warmup)
+    if not args.no_complex:
+        out["complex"] = complex_case()
     if not args.no_hotrg:
         out["hotrg"] = hotrg_speedup()
         out["hotrg"]["by_D"] = hotrg_by_d()
