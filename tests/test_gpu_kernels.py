@@ -140,8 +140,12 @@ def test_gemm_leading_dims_and_zero_k(hc):
 
 
 @pytest.mark.parametrize("shape,perm", [((3, 40, 5, 33), (0, 3, 2, 1)), ((64, 64), (1, 0)), ((7, 1, 9, 2, 5), (4, 2, 0, 1, 3)),
-                                         ((50, 3, 70), (0, 1, 2))])
+                                         ((50, 3, 70), (0, 1, 2)), ((5, 18, 18, 72), (0, 3, 2, 1)),
+                                         ((4, 3, 10, 37), (0, 3, 2, 1)), ((6, 9, 7, 18), (0, 2, 1, 3)),
+                                         ((2, 31, 33, 40), (0, 3, 2, 1))])
 def test_copy_is_exact_permutation(hc, shape, perm):
+    """Exact permutations; (w, l, u, t) -> (w, t, u, l) with a short l joins
+    l and u into one destination-fast index of the LDS tile."""
     rng = np.random.default_rng(len(shape))
     X = rng.standard_normal(shape)
     Y = np.ascontiguousarray(X.transpose(perm))
