@@ -175,6 +175,27 @@ def test_cholesky_inverse(hc, n):
     assert np.abs(Q.T @ Q - np.eye(n)).max() < 1e-11 * np.linalg.cond(X) ** 2
 
 
+@pytest.mark.parametrize("n,dead", [(20, 3), (100, 57), (128, 127), (128, 64), (96, 0)])
+def test_cholesky_inverse_dead_pivot(hc, n, dead):
+    """A zero row and column of G (a dead pivot inside or at the edge of an
+    eight-column block): it is counted in info, its row and column of R^-1 are
+    zero, and the other columns of X R^-1 are orthonormal."""
+    rng = np.random.default_rng(n + dead)
+    X = rng.standard_normal((n + 30, n))
+    X[:, dead] = 0.0
+    G = X.T @ X
+    dG, dR = _dev(G), torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    info = torch.zeros(4, dtype=torch.int32, device="cuda")
+    hc.dev_chol_inv(dG, dR, n, 0.0, info)
+    torch.cuda.synchronize()
+    Ri = dR.cpu().numpy()
+    assert int(info[0].item()) == 1
+    assert np.all(Ri[dead, :] == 0.0) and np.all(Ri[:, dead] == 0.0)
+    keep = [j for j in range(n) if j != dead]
+    Q = X @ Ri[:, keep]
+    assert np.abs(Q.T @ Q - np.eye(n - 1)).max() < 1e-11 * np.linalg.cond(X[:, keep]) ** 2
+
+
 @pytest.mark.parametrize("m,n,pre,l2", [(1, 1, 0, 0), (8, 5, 0, 0), (8, 5, 2, 0), (40, 40, 0, 0), (40, 40, 16, 0),
                                         (120, 97, 0, 0), (120, 97, 33, 0), (126, 126, 42, 0), (150, 150, 0, 0),
                                         (201, 180, 0, 0), (150, 150, 0, 1), (160, 160, 16, 1), (216, 216, 72, 1),
