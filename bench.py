@@ -67,6 +67,56 @@ def copy_check(nbytes):
     assert bool((dst == 1.0).all())
 
 
+def measured_peaks():
+    """The chip's own ceilings, measured with the library's probes on the
+    same stream as everything else: the FP64 matrix-core rate of back-to-back
+    independent MFMAs with no memory traffic (2048 workgroups, eight per CU),
+    the HBM bandwidth of a 1 GiB contiguous copy (read + write), and the GEMM
+    kernel's own rate on one 8192^3 FP64 product.  Medians of five timed
+    launches after two untimed ones."""
+    import torch
+
+    from paper_2410_11596_amd import binding
+
+    def timed(fn, reps=5, warm=2):
+        for _ in range(warm):
+            fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return float(np.median(ts))
+
+    blocks, iters = 2048, 32
+    sink = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
+    flops = binding.dev_mfma_probe(sink, blocks, 1)  # builds the kernel; flops of one round
+    flops = flops * iters
+    t_mfma = timed(lambda: binding.dev_mfma_probe(sink, blocks, iters))
+    assert bool(torch.isfinite(sink).all())
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    t_copy = timed(lambda: binding.dev_stream_probe(src, dst, n))
+    assert bool((dst == 1.0).all())
+    del src, dst
+    m = 8192
+    a = torch.rand(m, m, dtype=torch.float64, device="cuda")
+    b = torch.rand(m, m, dtype=torch.float64, device="cuda")
+    c = torch.empty(m, m, dtype=torch.float64, device="cuda")
+    t_gemm = timed(lambda: binding.dev_gemm(a, b, c, m, m, m, m, m, m), reps=3, warm=1)
+    del a, b, c
+    return {"fp64_mfma_tflops": flops / t_mfma / 1e12, "hbm_copy_gbps": 2 * 8 * n / t_copy / 1e9,
+            "gemm_f64_8192_tflops": 2.0 * m ** 3 / t_gemm / 1e12,
+            "probes": "hctm_dev_mfma_probe (2048 workgroups x 4 waves, 1024 rounds of 8 independent "
+                      "16x16x4 FP64 MFMAs each), hctm_dev_stream_probe (1 GiB copy, one 16-byte non-temporal load "
+                      "and store per thread), "
+                      "hctm_dev_gemm 8192^3; medians of 5 (GEMM: 3) timed launches"}
+
+
 def event_pair_overhead(n=200):
     """Mean duration of an empty HIP event pair on the current stream, right
     after a small kernel (the fixed cost inside every timed launch)."""
@@ -604,6 +654,8 @@ def main():
                     help="requests of the one-at-a-time plain-form baseline (default: all of the serving run)")
     ap.add_argument("--serve-max-iter", type=int, default=60, help="iteration cap of a served solve")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving comparison and print its JSON")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip measuring the chip's own MFMA rate and copy bandwidth")
     ap.add_argument("--copy-check", type=int, default=0, metavar="BYTES",
                     help="before timing, copy BYTES three times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -698,6 +750,10 @@ def main():
             "gemm_share_of_step": kernel_s / tz_prof,
             "profiled_pass_ms_per_step": 1e3 * tz_prof / args.steps,
         }
+        if not args.no_peaks:
+            mp = measured_peaks()
+            out["roofline"]["measured_peaks"] = mp
+            out["roofline"]["frac_of_measured_mfma"] = achieved / mp["fp64_mfma_tflops"]
     if not args.no_late:
         out["late_iterations"] = late_iterations(A, args.chi, args.warmup + args.steps, args.steps)
     if not args.no_dense:

@@ -32,6 +32,17 @@ int hctm_dev_gemm_bf16x3(const double* A, const double* B, double* C, int M, int
                          int ldc, int ta, int tb, double alpha, double beta, const double* cscale, double* scratch,
                          long long scratch_doubles, void* stream);
 
+/* Probes of the chip's own ceilings (reported beside the published peaks).
+ * hctm_dev_mfma_probe: blocks workgroups of four waves, each wave issuing
+ * 32 * iters rounds of eight independent FP64 16 x 16 x 4 matrix-core products
+ * with no memory traffic; sink (device, blocks * 256 doubles) receives the
+ * sums so that the work is kept; *flops (host, may be NULL) = the flops
+ * executed.  The caller times the launch on its stream.
+ * hctm_dev_stream_probe: out[0..n) = in[0..n) (device, 16-byte aligned,
+ * not overlapping) with 16-byte loads and stores; CTM_E_ARG if misaligned. */
+int hctm_dev_mfma_probe(double* sink, int blocks, int iters, double* flops, void* stream);
+int hctm_dev_stream_probe(const double* in, double* out, long long n, void* stream);
+
 /* Strided copy of a dense box of rank r <= 6: out[sum x_j ostr_j] =
  * in[sum x_j istr_j] (the permute-and-reshape step between block products). */
 int hctm_dev_copy(const double* in, double* out, int r, const int* dims, const long long* istr,

@@ -32,7 +32,7 @@ EXPORTS = [
     "hotrg_energy", "hotrg_track_rdm1", "hotrg_rdm1", "hotrg_num_records",
     "hotrg_record", "hotrg_last_error", "hotrg_free",
     "hctm_dev_gemm", "hctm_dev_gemm_f32", "hctm_dev_gemm_bf16x3", "hctm_dev_copy", "hctm_dev_chol_inv", "hctm_dev_jacobi", "hctm_dev_jacobi_log_doubles",
-    "hctm_dev_jacobi_noalloc",
+    "hctm_dev_jacobi_noalloc", "hctm_dev_mfma_probe", "hctm_dev_stream_probe",
 ]
 
 
@@ -131,6 +131,8 @@ def lib():
                                                                    ctypes.c_longlong, vp], ctypes.c_int),
         "hctm_dev_gemm_bf16x3": ([vp, vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.c_double, vp, vp,
                                                                       ctypes.c_longlong, vp], ctypes.c_int),
+        "hctm_dev_mfma_probe": ([vp, ctypes.c_int, ctypes.c_int, dp, vp], ctypes.c_int),
+        "hctm_dev_stream_probe": ([vp, vp, ctypes.c_longlong, vp], ctypes.c_int),
         "ctm_set_precision": ([ctx, ctypes.c_int], ctypes.c_int),
         "ctm_server_create": ([P(ctypes.c_void_p), ctypes.c_size_t, ctypes.c_int], ctypes.c_int),
         "ctm_server_submit": ([ctypes.c_void_p, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -447,6 +449,21 @@ def dev_gemm(A, B, C, M, N, K, lda, ldb, ldc, ta=0, tb=0, alpha=1.0, beta=0.0, c
     p = precision or ("fp32" if f32 else "fp64")
     f = {"fp64": lib().hctm_dev_gemm, "fp32": lib().hctm_dev_gemm_f32, "bf16x3": lib().hctm_dev_gemm_bf16x3}[p]
     _check(f(_ptr(A), _ptr(B), _ptr(C), M, N, K, lda, ldb, ldc, ta, tb, alpha, beta, cs, sp, sn, _stream_ptr(torch)))
+
+
+def dev_mfma_probe(sink, blocks, iters):
+    """Enqueue the FP64 matrix-core issue probe on torch's current stream;
+    returns the flops it executes (time it with events on that stream)."""
+    torch = _torch()
+    f = ctypes.c_double(0.0)
+    _check(lib().hctm_dev_mfma_probe(_ptr(sink), blocks, iters, ctypes.byref(f), _stream_ptr(torch)))
+    return f.value
+
+
+def dev_stream_probe(src, dst, n):
+    """Enqueue dst[:n] = src[:n] (16-byte accesses) on torch's current stream."""
+    torch = _torch()
+    _check(lib().hctm_dev_stream_probe(_ptr(src), _ptr(dst), n, _stream_ptr(torch)))
 
 
 def dev_copy(src, dst, dims, istr, ostr, in_offset=0, out_offset=0):

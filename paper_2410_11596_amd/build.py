@@ -15,8 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhctm.so")
 
-SOURCES = ["gemm.hip", "perm.hip", "linalg.hip", "tensor.hip", "ctm.cpp", "ctm_complex.cpp", "api.cpp", "serve.cpp",
-           "hotrg.cpp"]
+SOURCES = ["gemm.hip", "perm.hip", "linalg.hip", "tensor.hip", "peak.hip", "ctm.cpp", "ctm_complex.cpp", "api.cpp",
+           "serve.cpp", "hotrg.cpp"]
 ARCH = os.environ.get("HCTM_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3",

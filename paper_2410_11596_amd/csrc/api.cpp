@@ -1,5 +1,6 @@
 // C ABI of libhctm.so (declared in include/hctm.h and include/hctm_testing.h).
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -469,6 +470,23 @@ int hctm_dev_gemm_bf16x3(const double* A, const double* B, double* C, int M, int
                          int ldc, int ta, int tb, double alpha, double beta, const double* cscale, double* scratch,
                          long long scratch_doubles, void* stream) {
   return dev_gemm(A, B, C, M, N, K, lda, ldb, ldc, ta, tb, alpha, beta, cscale, scratch, scratch_doubles, stream, 2);
+}
+
+int hctm_dev_mfma_probe(double* sink, int blocks, int iters, double* flops, void* stream) {
+  return guarded(nullptr, [&] {
+    if (blocks < 1 || iters < 1) throw hctm::Error(CTM_E_ARG, "blocks and iters must be positive");
+    const double f = hctm::mfma_probe(sink, blocks, iters, reinterpret_cast<hipStream_t>(stream));
+    if (flops) *flops = f;
+  });
+}
+
+int hctm_dev_stream_probe(const double* in, double* out, long long n, void* stream) {
+  return guarded(nullptr, [&] {
+    if (n < 0) throw hctm::Error(CTM_E_ARG, "negative size");
+    if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15)
+      throw hctm::Error(CTM_E_ARG, "stream probe buffers must be 16-byte aligned");
+    hctm::stream_probe(in, out, n, reinterpret_cast<hipStream_t>(stream));
+  });
 }
 
 int hctm_dev_copy(const double* in, double* out, int r, const int* dims, const long long* istr, const long long* ostr,

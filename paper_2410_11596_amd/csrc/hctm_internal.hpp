@@ -51,6 +51,14 @@ struct GemmObserver {
 void gemm(const std::vector<GemmDesc>& probs, hipStream_t s, double* scratch = nullptr, long long scratch_cap = 0,
           GemmObserver* obs = nullptr);
 
+// ---------------------------------------------------------------- probes ----
+// FP64 MFMA issue probe: blocks workgroups of four waves, 32 * iters rounds
+// of eight independent 16 x 16 x 4 products each; sink gets blocks * 256
+// doubles.  Returns the flops it executes.
+double mfma_probe(double* sink, int blocks, int iters, hipStream_t s);
+// out[0..n) = in[0..n) with 16-byte accesses (in and out 16-byte aligned).
+void stream_probe(const double* in, double* out, long long n, hipStream_t s);
+
 // -------------------------------------------------------------- permute ----
 // Strided copy of one dense block: out[sum_j x_j ostr_j] = in[sum_j x_j istr_j]
 // for x in the box dims[0..r).  Used for every leg permutation of a

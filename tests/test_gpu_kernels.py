@@ -175,6 +175,26 @@ def test_cholesky_inverse(hc, n):
     assert np.abs(Q.T @ Q - np.eye(n)).max() < 1e-11 * np.linalg.cond(X) ** 2
 
 
+def test_peak_probes(hc):
+    """The chip-ceiling probes: the MFMA probe reports the flops it issues
+    and leaves finite positive sums; the stream probe copies exactly
+    (odd length: the last element by a plain copy); misaligned buffers are
+    an argument error."""
+    sink = torch.zeros(8 * 256, dtype=torch.float64, device="cuda")
+    assert hc.dev_mfma_probe(sink, 8, 3) == 8 * 4 * 3 * 32 * 8 * 2048
+    torch.cuda.synchronize()
+    s = sink.cpu().numpy()
+    assert np.all(np.isfinite(s)) and np.all(s > 0)
+    n = 100001
+    src = torch.from_numpy(np.random.default_rng(5).standard_normal(n)).cuda()
+    dst = torch.zeros_like(src)
+    hc.dev_stream_probe(src, dst, n)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    with pytest.raises(Exception):
+        hc.dev_stream_probe(src[1:], dst[1:], 10)
+
+
 @pytest.mark.parametrize("n,dead", [(20, 3), (100, 57), (128, 127), (128, 64), (96, 0)])
 def test_cholesky_inverse_dead_pivot(hc, n, dead):
     """A zero row and column of G (a dead pivot inside or at the edge of an
