@@ -455,6 +455,8 @@ def dev_mfma_probe(sink, blocks, iters):
     """Enqueue the FP64 matrix-core issue probe on torch's current stream;
     returns the flops it executes (time it with events on that stream)."""
     torch = _torch()
+    if sink.dtype != torch.float64 or not sink.is_cuda or sink.numel() < blocks * 256:
+        raise ValueError("sink: a float64 device tensor of at least blocks * 256 elements")
     f = ctypes.c_double(0.0)
     _check(lib().hctm_dev_mfma_probe(_ptr(sink), blocks, iters, ctypes.byref(f), _stream_ptr(torch)))
     return f.value
@@ -463,6 +465,9 @@ def dev_mfma_probe(sink, blocks, iters):
 def dev_stream_probe(src, dst, n):
     """Enqueue dst[:n] = src[:n] (16-byte accesses) on torch's current stream."""
     torch = _torch()
+    for x in (src, dst):
+        if x.dtype != torch.float64 or not x.is_cuda or x.numel() < n:
+            raise ValueError("src, dst: float64 device tensors of at least n elements")
     _check(lib().hctm_dev_stream_probe(_ptr(src), _ptr(dst), n, _stream_ptr(torch)))
 
 
