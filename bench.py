@@ -613,6 +613,7 @@ def cpu_baseline(D, chi, split, seed=0, z2_repeats=3):
         ctmrg.left_move(env, rz.a, chi, rz.tau, rz.par_q)
         tz.append(time.perf_counter() - t0)
     t_z2 = float(np.median(tz))
+    small = small_config_oracle_times()
     return {
         "value": 1.0 / (4.0 * t_dense),
         "unit": "CTMRG iterations/s",
@@ -624,7 +625,37 @@ def cpu_baseline(D, chi, split, seed=0, z2_repeats=3):
         "z2_form": {"value": 1.0 / (4.0 * t_z2), "unit": "CTMRG iterations/s",
                     "sample": f"median of {z2_repeats} left moves of the oracle's Z2 form on such environments "
                               f"split {split[0]}+{split[1]}: {', '.join(f'{t:.2f}' for t in tz)} s"},
+        "small_configs": small,
     }
+
+
+def small_config_oracle_times(warm=3):
+    """Seconds per iteration of the oracle's solve (i.i.d. seed 0) at
+    D = 2, chi = 16 and D = 4, chi = 64, both forms, after warm iterations
+    (the bonds at chi): the next iteration with every host thread, the one
+    after it with the BLAS/LAPACK pools held to one thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ctmrg
+
+    from paper_2410_11596_amd import inputs
+
+    out = []
+    for D, chi in ((2, 16), (4, 64)):
+        A = inputs.iid_tensor(2, D, 0)
+        for form in ("dense", "z2"):
+            r = ctmrg.Run(chi, form, A=A)
+            r.step(warm)
+            t0 = time.perf_counter()
+            r.step(1)
+            t_all = time.perf_counter() - t0
+            with threadpool_limits(1):
+                t0 = time.perf_counter()
+                r.step(1)
+                t_one = time.perf_counter() - t0
+            out.append({"D": D, "chi": chi, "form": form, "s_per_iteration": t_all,
+                        "s_per_iteration_one_thread": t_one, "threads": len(os.sched_getaffinity(0))})
+    return out
 
 
 def main():
