@@ -588,6 +588,26 @@ def _oracle_saturated_env(ctmrg, basis, run, D, chi, split, seed):
     return ctmrg.Env(ts, [pb.copy() for _ in range(4)] if run.form == "z2" else None)
 
 
+def small_configs(steps, warmup):
+    """The small shapes of the parity tests, timed like the headline one: the
+    Z2 and plain forms at D = 2, chi = 16 and D = 4, chi = 64 (i.i.d. seed 0,
+    FP64), warmup untimed iterations, then steps timed.  At these sizes a
+    step is bound by launches and host checks, not by the matrix cores."""
+    from paper_2410_11596_amd import inputs
+
+    out = []
+    for D, chi in ((2, 16), (4, 64)):
+        A = inputs.iid_tensor(2, D, 0)
+        row = {"D": D, "chi": chi, "iterations_timed": [warmup + 1, warmup + steps]}
+        for form in ("z2", "dense"):
+            t, st, _, _ = time_form(A, chi, form, steps, warmup, profile=False)
+            row[form] = {"value": steps / t, "unit": "CTMRG iterations/s", "ms_per_step": 1e3 * t / steps,
+                         "iteration_ms": st["iteration_ms"]}
+        row["z2_over_dense"] = row["z2"]["value"] / row["dense"]["value"]
+        out.append(row)
+    return out
+
+
 def cpu_baseline(D, chi, split, seed=0, z2_repeats=3):
     """The oracle as it stands, on the host cores: one left move of its plain
     (dense) form -- the authority -- on a seeded random environment with every
@@ -672,6 +692,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-block-product run")
     ap.add_argument("--no-late", action="store_true", help="skip the later-iterations timing of the same solve")
     ap.add_argument("--no-c4v", action="store_true", help="skip the C4v-scheme comparison")
+    ap.add_argument("--no-small", action="store_true", help="skip the D = 2 and D = 4 timings")
     ap.add_argument("--no-complex", action="store_true", help="skip the complex-tensor timing")
     ap.add_argument("--no-large", action="store_true", help="skip the D = 8, chi = 256 run")
     ap.add_argument("--no-hotrg", action="store_true", help="skip the HOTRG Z2/plain comparison")
@@ -818,6 +839,8 @@ def main():
                                                  args.warmup, _golden("perturbed"))
     if not args.no_large:
         out["large_d8_chi256"] = large_shape()
+    if not args.no_small:
+        out["small_configs"] = small_configs(args.steps, args.warmup)
     if not args.no_c4v:
         out["c4v"] = c4v_scheme(args.D, args.chi, args.steps, args.warmup)
     if not args.no_complex:
