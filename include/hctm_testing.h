@@ -21,6 +21,17 @@ int hctm_dev_gemm(const double* A, const double* B, double* C, int M, int N, int
                   int ta, int tb, double alpha, double beta, const double* cscale, double* scratch,
                   long long scratch_doubles, void* stream);
 
+/* op(A) op(B) (M x N, FP64) with a scattered output, the form the enlarged
+ * corners use to write their product straight into a permuted layout: with
+ * row = i0 T + i1 and col = i2 R + i3, element (row, col) of
+ * alpha op(A) op(B) + beta C is stored at
+ * C + i0 strides[0] + i1 strides[1] + i2 strides[2] + i3 strides[3]
+ * (strides: host array of 4).  T must divide M and R divide N; the caller's
+ * strides must map distinct elements to distinct addresses inside C. */
+int hctm_dev_gemm_scatter(const double* A, const double* B, double* C, int M, int N, int K, int lda, int ldb,
+                          int ta, int tb, double alpha, double beta, int T, int R, const long long* strides,
+                          void* stream);
+
 /* The same with the operands rounded to FP32 and FP32 matrix-core products
  * and accumulation (CTM_PREC_FP32); C, alpha, beta and cscale stay FP64. */
 int hctm_dev_gemm_f32(const double* A, const double* B, double* C, int M, int N, int K, int lda, int ldb, int ldc,

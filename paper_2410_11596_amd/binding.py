@@ -32,7 +32,7 @@ EXPORTS = [
     "hotrg_energy", "hotrg_track_rdm1", "hotrg_rdm1", "hotrg_num_records",
     "hotrg_record", "hotrg_last_error", "hotrg_free",
     "hctm_dev_gemm", "hctm_dev_gemm_f32", "hctm_dev_gemm_bf16x3", "hctm_dev_copy", "hctm_dev_chol_inv", "hctm_dev_jacobi", "hctm_dev_jacobi_log_doubles",
-    "hctm_dev_jacobi_noalloc", "hctm_dev_mfma_probe", "hctm_dev_stream_probe",
+    "hctm_dev_jacobi_noalloc", "hctm_dev_mfma_probe", "hctm_dev_stream_probe", "hctm_dev_gemm_scatter",
 ]
 
 
@@ -132,6 +132,9 @@ def lib():
         "hctm_dev_gemm_bf16x3": ([vp, vp, vp] + [ctypes.c_int] * 8 + [ctypes.c_double, ctypes.c_double, vp, vp,
                                                                       ctypes.c_longlong, vp], ctypes.c_int),
         "hctm_dev_mfma_probe": ([vp, ctypes.c_int, ctypes.c_int, dp, vp], ctypes.c_int),
+        "hctm_dev_gemm_scatter": ([vp, vp, vp] + [ctypes.c_int] * 7 + [ctypes.c_double, ctypes.c_double,
+                                                                      ctypes.c_int, ctypes.c_int,
+                                                                      P(ctypes.c_longlong), vp], ctypes.c_int),
         "hctm_dev_stream_probe": ([vp, vp, ctypes.c_longlong, vp], ctypes.c_int),
         "ctm_set_precision": ([ctx, ctypes.c_int], ctypes.c_int),
         "ctm_server_create": ([P(ctypes.c_void_p), ctypes.c_size_t, ctypes.c_int], ctypes.c_int),
@@ -449,6 +452,15 @@ def dev_gemm(A, B, C, M, N, K, lda, ldb, ldc, ta=0, tb=0, alpha=1.0, beta=0.0, c
     p = precision or ("fp32" if f32 else "fp64")
     f = {"fp64": lib().hctm_dev_gemm, "fp32": lib().hctm_dev_gemm_f32, "bf16x3": lib().hctm_dev_gemm_bf16x3}[p]
     _check(f(_ptr(A), _ptr(B), _ptr(C), M, N, K, lda, ldb, ldc, ta, tb, alpha, beta, cs, sp, sn, _stream_ptr(torch)))
+
+
+def dev_gemm_scatter(A, B, C, M, N, K, lda, ldb, T, R, strides, ta=0, tb=0, alpha=1.0, beta=0.0):
+    """alpha op(A) op(B) + beta C with element (i0 T + i1, i2 R + i3) stored at
+    C + sum_q i_q strides[q]."""
+    torch = _torch()
+    s = (ctypes.c_longlong * 4)(*[int(x) for x in strides])
+    _check(lib().hctm_dev_gemm_scatter(_ptr(A), _ptr(B), _ptr(C), M, N, K, lda, ldb, ta, tb, alpha, beta, T, R, s,
+                                       _stream_ptr(torch)))
 
 
 def dev_mfma_probe(sink, blocks, iters):

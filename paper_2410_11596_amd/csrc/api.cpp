@@ -472,6 +472,33 @@ int hctm_dev_gemm_bf16x3(const double* A, const double* B, double* C, int M, int
   return dev_gemm(A, B, C, M, N, K, lda, ldb, ldc, ta, tb, alpha, beta, cscale, scratch, scratch_doubles, stream, 2);
 }
 
+int hctm_dev_gemm_scatter(const double* A, const double* B, double* C, int M, int N, int K, int lda, int ldb,
+                          int ta, int tb, double alpha, double beta, int T, int R, const long long* strides,
+                          void* stream) {
+  return guarded(nullptr, [&] {
+    if (M < 1 || N < 1 || K < 1 || T < 1 || R < 1 || M % T != 0 || N % R != 0 || !strides)
+      throw hctm::Error(CTM_E_ARG, "sizes must be positive with T dividing M and R dividing N");
+    hctm::GemmDesc d{};
+    d.A = A;
+    d.B = B;
+    d.C = C;
+    d.M = M;
+    d.N = N;
+    d.K = K;
+    d.lda = lda;
+    d.ldb = ldb;
+    d.ldc = N;
+    d.ta = ta;
+    d.tb = tb;
+    d.alpha = alpha;
+    d.beta = beta;
+    d.sc_T = T;
+    d.sc_R = R;
+    for (int q = 0; q < 4; ++q) d.sc_s[q] = strides[q];
+    hctm::gemm({d}, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
 int hctm_dev_mfma_probe(double* sink, int blocks, int iters, double* flops, void* stream) {
   return guarded(nullptr, [&] {
     if (blocks < 1 || iters < 1) throw hctm::Error(CTM_E_ARG, "blocks and iters must be positive");

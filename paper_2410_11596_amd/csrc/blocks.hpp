@@ -194,6 +194,59 @@ inline void plan_contract(const BT& A, const BT& B, BT& C, double alpha, double 
   }
 }
 
+// out = (A B) with its four legs permuted (out leg j = leg perm[j] of the
+// product, row split nr_out), written by the products themselves: the
+// product's layout is planned at C (never written; capacity checks only),
+// each dense box of the permutation becomes one product over the rows and
+// columns of its box with a scattered output.  Only for rank-2 by rank-2
+// row/column legs; false (nothing planned) otherwise.
+inline bool plan_contract_permuted(const BT& A, const BT& B, BT& C, BT& out, const int* perm, int nr_out,
+                                   std::vector<GemmDesc>& g) {
+  std::vector<GemmDesc> whole;
+  plan_contract(A, B, C, 1.0, 0.0, whole);
+  const Layout& Lc = C.L;
+  if (Lc.r != 4 || Lc.nr != 2) return false;
+  Layout L;
+  L.r = 4;
+  L.nr = nr_out;
+  L.tp = Lc.tp;
+  for (int j = 0; j < 4; ++j) L.leg[j] = Lc.leg[perm[j]];
+  L.finalize();
+  out.L = L;
+  std::vector<CopyJob> jobs;
+  plan_permute(C, out, perm, jobs);
+  std::vector<GemmDesc> parts;
+  for (const CopyJob& cj : jobs) {
+    // the product whose output block holds this box
+    const GemmDesc* src = nullptr;
+    for (const GemmDesc& d : whole)
+      if (cj.in >= d.C && cj.in < d.C + (long long)d.M * d.ldc) src = &d;
+    if (!src) return false;
+    const long long rel = cj.in - src->C;
+    const long long row0 = rel / src->ldc, col0 = rel % src->ldc;
+    long long dim[4], is[4], os[4];  // per leg of the product
+    for (int j = 0; j < 4; ++j) {
+      dim[perm[j]] = cj.dims[j];
+      is[perm[j]] = cj.istr[j];
+      os[perm[j]] = cj.ostr[j];
+    }
+    // the box is row-major in the product block: rows (leg 0, leg 1), columns (leg 2, leg 3)
+    if (is[1] != src->ldc || is[0] != dim[1] * src->ldc || is[3] != 1 || is[2] != dim[3]) return false;
+    GemmDesc d = *src;
+    d.A = src->A + row0 * src->lda;
+    d.B = src->B + col0;
+    d.C = cj.out;
+    d.M = (int)(dim[0] * dim[1]);
+    d.N = (int)(dim[2] * dim[3]);
+    d.sc_T = (int)dim[1];
+    d.sc_R = (int)dim[3];
+    for (int q = 0; q < 4; ++q) d.sc_s[q] = os[q];
+    if (d.M > 0 && d.N > 0) parts.push_back(d);
+  }
+  g.insert(g.end(), parts.begin(), parts.end());
+  return true;
+}
+
 // Copy between a plain dense array (row-major over legs, each leg with the
 // even states first) and the blocks of a layout.  pstride[i] is the plain
 // stride of the layout's leg i.  to_blocks = true packs, false unpacks.

@@ -475,6 +475,14 @@ void Ctm::quadrant(int s, int j) {
   BT Yp{Layout(), big2_, big_cap_};
   permute(Y, Yp, {0, 3, 2, 1}, 2);                       // [w t | u l]
   BT Qp{Layout(), big1_, big_cap_};
+  // [w t | d r] written straight as [w d | t r] (one product per box of
+  // the permutation), else formed and permuted
+  std::vector<GemmDesc> g;
+  const int perm[4] = {0, 2, 1, 3};
+  if (plan_contract_permuted(Yp, a_rot(s, j), Qp, quad(s, j), perm, 2, g)) {
+    launch_gemms(g);
+    return;
+  }
   contract(Yp, a_rot(s, j), Qp);                         // [w t | d r]
   permute(Qp, quad(s, j), {0, 2, 1, 3}, 2);              // [w d | t r]
 }

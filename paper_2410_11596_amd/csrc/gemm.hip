@@ -46,6 +46,8 @@ struct Prob {
   double alpha, beta;
   int M, N, K, lda, ldb, ldc, ta, tb;
   int tiles_m, tiles_n, ksplit, kchunk, tile_start;
+  int sc_T, sc_R;  // scattered output (GemmDesc), 0: row-major C with ldc
+  long long sc_s[4];
 };
 
 struct Group {
@@ -300,13 +302,24 @@ __device__ __forceinline__ void gemm_tile(const Group& g, CT* As, CT* Bs) {
       const int col = n0 + wn + j * 16 + li;
       if (col >= P.N) continue;
       const double cs = P.cscale ? P.cscale[col] : 1.0;
+      // column part of the output address
+      long long cpart = col;
+      if (P.sc_T) {
+        const int cq = col / P.sc_R;
+        cpart = cq * P.sc_s[2] + (col - cq * P.sc_R) * P.sc_s[3];
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = m0 + wm + i * 16 + Mfma<CT>::row(lk, v);
         if (row >= P.M) continue;
         double val = P.alpha * (double)acc[i][j][v] * cs;
         if (P.rscale) val *= P.rscale[row];
-        double* c = P.C + (long long)row * P.ldc + col;
+        long long rpart = (long long)row * P.ldc;
+        if (P.sc_T) {
+          const int rq = row / P.sc_T;
+          rpart = rq * P.sc_s[0] + (row - rq * P.sc_T) * P.sc_s[1];
+        }
+        double* c = P.C + rpart + cpart;
         if (P.beta != 0.0) val += P.beta * *c;
         *c = val;
       }
@@ -453,9 +466,12 @@ void gemm_one_type(const std::vector<GemmDesc>& probs, int prec, hipStream_t s, 
     p.tb = d.tb;
     p.tiles_m = (d.M + bm - 1) / bm;
     p.tiles_n = (d.N + bn - 1) / bn;
+    p.sc_T = d.sc_T > 0 && d.sc_R > 0 ? d.sc_T : 0;
+    p.sc_R = d.sc_R;
+    for (int q = 0; q < 4; ++q) p.sc_s[q] = d.sc_s[q];
     // split K when the call has too few output tiles and this K is long
     int ks = 1;
-    if (cfg == 1 && t64 < 4 * kFill && scratch) {
+    if (cfg == 1 && t64 < 4 * kFill && scratch && !p.sc_T) {
       const long long want = (4 * kFill + t64 - 1) / t64;  // about 4 workgroups per CU
       const long long maxk = d.K / 64;  // at least 64 of K per slice
       ks = (int)std::max<long long>(1, std::min(want, maxk));

@@ -175,6 +175,33 @@ def test_cholesky_inverse(hc, n):
     assert np.abs(Q.T @ Q - np.eye(n)).max() < 1e-11 * np.linalg.cond(X) ** 2
 
 
+@pytest.mark.parametrize("a0,a1,a2,a3,K,beta", [(5, 7, 3, 9, 11, 0.0), (72, 21, 21, 15, 648, 0.0),
+                                                (60, 84, 15, 21, 100, 0.5), (1, 130, 2, 70, 33, 0.0)])
+def test_gemm_scatter_is_permuted_product(hc, a0, a1, a2, a3, K, beta):
+    """A product whose rows are legs (i0, i1) and columns (i2, i3), written
+    straight into the layout [i0 i2 | i1 i3]: the same as forming it and
+    permuting (bitwise: the same products, only stored elsewhere); large
+    shapes take the 128 x 64 tile, small ones the 64 x 64 one (never split)."""
+    rng = np.random.default_rng(a0 + a1 + a2 + a3 + K)
+    M, N = a0 * a1, a2 * a3
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    C0 = rng.standard_normal((a0, a2, a1, a3))
+    dA, dB = _dev(A), _dev(B)
+    dC = _dev(C0)
+    hc.dev_gemm_scatter(dA, dB, dC, M, N, K, K, N, a1, a3, [a2 * a1 * a3, a3, a1 * a3, 1], alpha=1.5, beta=beta)
+    ref_flat = torch.zeros((M, N), dtype=torch.float64, device="cuda")
+    hc.dev_gemm(dA, dB, ref_flat, M, N, K, K, N, N, 0, 0, 1.5, 0.0)
+    torch.cuda.synchronize()
+    ref = ref_flat.cpu().numpy().reshape(a0, a1, a2, a3).transpose(0, 2, 1, 3)
+    if beta != 0.0:
+        ref = ref + beta * C0
+        got = dC.cpu().numpy().reshape(a0, a2, a1, a3)
+        assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+    else:
+        assert np.array_equal(dC.cpu().numpy().reshape(a0, a2, a1, a3), ref)
+
+
 def test_peak_probes(hc):
     """The chip-ceiling probes: the MFMA probe reports the flops it issues
     and leaves finite positive sums; the stream probe copies exactly
