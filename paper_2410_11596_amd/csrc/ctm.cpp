@@ -471,9 +471,18 @@ void Ctm::quadrant(int s, int j) {
   BT T4s{Layout(), mid2_, mid_cap_};
   permute(T4, T4s, {0, 1, 2}, 2);                        // [w l | c]
   BT Y{Layout(), big1_, big_cap_};
-  contract(T4s, X, Y);                                   // [w l | u t]
   BT Yp{Layout(), big2_, big_cap_};
-  permute(Y, Yp, {0, 3, 2, 1}, 2);                       // [w t | u l]
+  // [w l | u t] written straight as [w t | u l] (the swap of l and t: each
+  // lane's stores are short runs along l that fill whole lines in L2), else
+  // formed and permuted
+  std::vector<GemmDesc> gy;
+  const int pswap[4] = {0, 3, 2, 1};
+  if (plan_contract_permuted(T4s, X, Y, Yp, pswap, 2, gy)) {
+    launch_gemms(gy);
+  } else {
+    contract(T4s, X, Y);                                   // [w l | u t]
+    permute(Y, Yp, {0, 3, 2, 1}, 2);                       // [w t | u l]
+  }
   BT Qp{Layout(), big1_, big_cap_};
   // [w t | d r] written straight as [w d | t r] (one product per box of
   // the permutation), else formed and permuted
