@@ -206,6 +206,10 @@ inline bool plan_contract_permuted(const BT& A, const BT& B, BT& C, BT& out, con
   plan_contract(A, B, C, 1.0, 0.0, whole);
   const Layout& Lc = C.L;
   if (Lc.r != 4 || Lc.nr != 2) return false;
+  // an empty contracted sector would take the plain C = 0 path of gemm(),
+  // which knows nothing of the scattered layout
+  for (const GemmDesc& d : whole)
+    if (d.K <= 0) return false;
   Layout L;
   L.r = 4;
   L.nr = nr_out;

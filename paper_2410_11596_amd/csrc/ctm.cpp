@@ -371,6 +371,39 @@ void Ctm::contract(const BT& A, const BT& B, BT& C) {
   launch_gemms(g);
 }
 
+// (T4 P_a) a of the edge renormalisation as [w e | r k], from T4s [w l | c]
+// (in a mid buffer) and P_a as [c | u k] (in big2_): G = T4s P_a [w l | u k]
+// is written straight as [w k | u l], then H = G a [w k | e r] straight as
+// [w e | r k]; where a product cannot be written permuted it is formed in
+// one big buffer and permuted into the other (an input it overwrites is
+// consumed by then).
+BT Ctm::edge_product(const BT& T4s, const BT& Pas, const BT& a) {
+  const int pg[4] = {0, 3, 2, 1}, ph[4] = {0, 2, 3, 1};
+  BT G{Layout(), big1_, big_cap_};
+  BT Gp{Layout(), big1_, big_cap_};  // P_a (big2_) is read while Gp is written
+  if (!contract_permuted(T4s, Pas, G, Gp, pg, 2)) {
+    Gp.p = big2_;
+    contract(T4s, Pas, G);                   // [w l | u k]
+    permute(G, Gp, {0, 3, 2, 1}, 2);         // [w k | u l]
+  }
+  double* other = Gp.p == big1_ ? big2_ : big1_;
+  BT H{Layout(), other, big_cap_};
+  BT Hp{Layout(), other, big_cap_};
+  if (!contract_permuted(Gp, a, H, Hp, ph, 2)) {
+    Hp.p = Gp.p;
+    contract(Gp, a, H);                      // [w k | e r]
+    permute(H, Hp, {0, 2, 3, 1}, 2);         // [w e | r k]
+  }
+  return Hp;
+}
+
+bool Ctm::contract_permuted(const BT& A, const BT& B, BT& C, BT& out, const int* perm, int nr_out) {
+  std::vector<GemmDesc> g;
+  if (!plan_contract_permuted(A, B, C, out, perm, nr_out, g)) return false;
+  launch_gemms(g);
+  return true;
+}
+
 void Ctm::normalise(BT& t) {
   norm2(t.p, (size_t)t.L.size, misc_, part_, st_);
   scale_inv(t.p, (size_t)t.L.size, misc_, st_);
@@ -475,23 +508,16 @@ void Ctm::quadrant(int s, int j) {
   // [w l | u t] written straight as [w t | u l] (the swap of l and t: each
   // lane's stores are short runs along l that fill whole lines in L2), else
   // formed and permuted
-  std::vector<GemmDesc> gy;
   const int pswap[4] = {0, 3, 2, 1};
-  if (plan_contract_permuted(T4s, X, Y, Yp, pswap, 2, gy)) {
-    launch_gemms(gy);
-  } else {
+  if (!contract_permuted(T4s, X, Y, Yp, pswap, 2)) {
     contract(T4s, X, Y);                                   // [w l | u t]
     permute(Y, Yp, {0, 3, 2, 1}, 2);                       // [w t | u l]
   }
   BT Qp{Layout(), big1_, big_cap_};
   // [w t | d r] written straight as [w d | t r] (one product per box of
   // the permutation), else formed and permuted
-  std::vector<GemmDesc> g;
   const int perm[4] = {0, 2, 1, 3};
-  if (plan_contract_permuted(Yp, a_rot(s, j), Qp, quad(s, j), perm, 2, g)) {
-    launch_gemms(g);
-    return;
-  }
+  if (contract_permuted(Yp, a_rot(s, j), Qp, quad(s, j), perm, 2)) return;
   contract(Yp, a_rot(s, j), Qp);                         // [w t | d r]
   permute(Qp, quad(s, j), {0, 2, 1, 3}, 2);              // [w d | t r]
 }
@@ -1254,14 +1280,7 @@ void Ctm::move(int r) {
       permute(T4, T4s, {0, 1, 2}, 2);            // [w l | c]
       BT Pas{Layout(), big2_, big_cap_};
       permute(Pa_up, Pas, {0, 1, 2}, 1);         // [c | u k]
-      BT G{Layout(), big1_, big_cap_};
-      contract(T4s, Pas, G);                     // [w l | u k]
-      BT Gp{Layout(), big2_, big_cap_};
-      permute(G, Gp, {0, 3, 2, 1}, 2);           // [w k | u l]
-      BT H{Layout(), big1_, big_cap_};
-      contract(Gp, a_rot(s, r), H);              // [w k | e r]
-      BT Hp{Layout(), big2_, big_cap_};
-      permute(H, Hp, {0, 2, 3, 1}, 2);           // [w e | r k]
+      BT Hp = edge_product(T4s, Pas, a_rot(s, r));  // [w e | r k]
       // the old C1, C4, T4 of site s are no longer read
       BT& C1n = env(t, 2 * r);
       BT& C4n = env(t, 2 * r + 6);
@@ -1371,14 +1390,7 @@ void Ctm::move_c4v() {
   permute(T4, T4s, {0, 1, 2}, 2);        // [w l | c]
   BT Pas{Layout(), big2_, big_cap_};
   permute(Pa, Pas, {0, 1, 2}, 1);        // [c | u k]
-  BT G{Layout(), big1_, big_cap_};
-  contract(T4s, Pas, G);                 // [w l | u k]
-  BT Gp{Layout(), big2_, big_cap_};
-  permute(G, Gp, {0, 3, 2, 1}, 2);       // [w k | u l]
-  BT H{Layout(), big1_, big_cap_};
-  contract(Gp, a_rot(s, 0), H);          // [w k | e r]
-  BT Hp{Layout(), big2_, big_cap_};
-  permute(H, Hp, {0, 2, 3, 1}, 2);       // [w e | r k]
+  BT Hp = edge_product(T4s, Pas, a_rot(s, 0));  // [w e | r k]
   contract(Pb, Hp, T4);                  // [k | r k]
   normalise(C);
   normalise(T4);

@@ -140,6 +140,11 @@ class Ctm {
   void launch_gemms(std::vector<GemmDesc>& g);
   void permute(const BT& in, BT& out, std::initializer_list<int> perm, int nr_out);
   void contract(const BT& A, const BT& B, BT& C);
+  // out = (A B) with legs permuted, written by the products themselves (C:
+  // the product's layout, never written); false if not possible (nothing
+  // launched; the caller forms C and permutes it)
+  bool contract_permuted(const BT& A, const BT& B, BT& C, BT& out, const int* perm, int nr_out);
+  BT edge_product(const BT& T4s, const BT& Pas, const BT& a);
   void normalise(BT& t);
   int site(int x, int y) const;             // wrapped site index y*Lx + x
   int site_of(int r, int X, int Y) const;   // site at frame-r coordinates

@@ -441,6 +441,7 @@ void gemm_one_type(const std::vector<GemmDesc>& probs, int prec, hipStream_t s, 
   for (const GemmDesc& d : probs) {
     if (d.M <= 0 || d.N <= 0) continue;
     if (d.K <= 0) {
+      if (d.sc_T > 0) throw Error(1, "gemm: a scattered output needs K > 0");
       const long long n = (long long)d.M * d.N;
       hipLaunchKernelGGL(scale_c_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d.C, d.M, d.N, d.ldc,
                          d.beta);

@@ -43,7 +43,8 @@ struct GemmDesc {
   // is stored at C + (row / sc_T) sc_s[0] + (row % sc_T) sc_s[1]
   // + (col / sc_R) sc_s[2] + (col % sc_R) sc_s[3] (ldc unused), i.e. a product
   // whose rows and columns are two legs each, written straight into a layout
-  // with those four legs permuted.  Such a product is not split over K.
+  // with those four legs permuted.  Such a product is not split over K and
+  // must have K > 0.
   int sc_T, sc_R;
   long long sc_s[4];
 };
