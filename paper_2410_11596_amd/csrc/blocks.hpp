@@ -194,16 +194,16 @@ inline void plan_contract(const BT& A, const BT& B, BT& C, double alpha, double 
   }
 }
 
-// out = (A B) with its four legs permuted (out leg j = leg perm[j] of the
-// product, row split nr_out), written by the products themselves: the
+// out = alpha (A B) + beta out with its four legs permuted (out leg j = leg
+// perm[j] of the product, row split nr_out), written by the products: the
 // product's layout is planned at C (never written; capacity checks only),
 // each dense box of the permutation becomes one product over the rows and
 // columns of its box with a scattered output.  Only for rank-2 by rank-2
 // row/column legs; false (nothing planned) otherwise.
 inline bool plan_contract_permuted(const BT& A, const BT& B, BT& C, BT& out, const int* perm, int nr_out,
-                                   std::vector<GemmDesc>& g) {
+                                   std::vector<GemmDesc>& g, double alpha = 1.0, double beta = 0.0) {
   std::vector<GemmDesc> whole;
-  plan_contract(A, B, C, 1.0, 0.0, whole);
+  plan_contract(A, B, C, alpha, beta, whole);
   const Layout& Lc = C.L;
   if (Lc.r != 4 || Lc.nr != 2) return false;
   // an empty contracted sector would take the plain C = 0 path of gemm(),

@@ -145,6 +145,11 @@ class Ctm {
   // launched; the caller forms C and permutes it)
   bool contract_permuted(const BT& A, const BT& B, BT& C, BT& out, const int* perm, int nr_out);
   BT edge_product(const BT& T4s, const BT& Pas, const BT& a);
+  // (Ar + i Ai)(Br + i Bi) with legs permuted, written by the products into
+  // outr and, right after it, outi (vbuf, vcap: room for the product's
+  // layout, never written); false if not possible (nothing launched)
+  bool cmul_permuted(const BT& Ar, const BT& Ai, const BT& Br, const BT& Bi, double* vbuf, long long vcap, BT& outr,
+                     BT& outi, const int* perm, int nr_out);
   void normalise(BT& t);
   int site(int x, int y) const;             // wrapped site index y*Lx + x
   int site_of(int r, int X, int Y) const;   // site at frame-r coordinates

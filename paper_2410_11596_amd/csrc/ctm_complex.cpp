@@ -49,6 +49,22 @@ void Ctm::cmul(const BT& Ar, const BT& Ai, const BT& Br, const BT& Bi, BT& Cr, B
   launch_gemms(g);
 }
 
+bool Ctm::cmul_permuted(const BT& Ar, const BT& Ai, const BT& Br, const BT& Bi, double* vbuf, long long vcap,
+                        BT& outr, BT& outi, const int* perm, int nr_out) {
+  const long long cap = outr.capacity;
+  std::vector<GemmDesc> g0, g1;
+  BT V{Layout(), vbuf, vcap};
+  if (!plan_contract_permuted(Ar, Br, V, outr, perm, nr_out, g0)) return false;
+  outi.p = outr.p + outr.L.size;
+  outi.capacity = cap - outr.L.size;
+  if (!plan_contract_permuted(Ar, Bi, V, outi, perm, nr_out, g0)) return false;
+  if (!plan_contract_permuted(Ai, Bi, V, outr, perm, nr_out, g1, -1.0, 1.0)) return false;
+  if (!plan_contract_permuted(Ai, Br, V, outi, perm, nr_out, g1, 1.0, 1.0)) return false;
+  launch_gemms(g0);
+  launch_gemms(g1);
+  return true;
+}
+
 void Ctm::cpermute(const BT& inr, const BT& ini, BT& outr, BT& outi, std::initializer_list<int> perm, int nr_out) {
   const long long cap = outr.capacity;
   permute(inr, outr, perm, nr_out);
@@ -206,13 +222,20 @@ void Ctm::cquadrant(int j) {
   cmul(env_[iC], env_i_[iC], env_[iT1], env_i_[iT1], Xr, Xi);              // [c | u t]
   BT T4r{Layout(), mid2_, mid_cap_}, T4i;
   cpermute(env_[iT4], env_i_[iT4], T4r, T4i, {0, 1, 2}, 2);               // [w l | c]
-  BT Yr{Layout(), big1_, big_cap_}, Yi;
-  cmul(T4r, T4i, Xr, Xi, Yr, Yi);                                          // [w l | u t]
+  // both products written straight into their permuted layouts where
+  // possible (the real form's enlarged corner does the same)
+  const int pswap[4] = {0, 3, 2, 1}, pq[4] = {0, 2, 1, 3};
   BT Ypr{Layout(), big2_, big_cap_}, Ypi;
-  cpermute(Yr, Yi, Ypr, Ypi, {0, 3, 2, 1}, 2);                             // [w t | u l]
-  BT Qr{Layout(), big1_, big_cap_}, Qi;
-  cmul(Ypr, Ypi, a_rot(0, j), a_rot_i_[j % 4], Qr, Qi);                    // [w t | d r]
-  cpermute(Qr, Qi, quad(0, j), quad_i_[j % 4], {0, 2, 1, 3}, 2);          // [w d | t r]
+  if (!cmul_permuted(T4r, T4i, Xr, Xi, big1_, big_cap_, Ypr, Ypi, pswap, 2)) {
+    BT Yr{Layout(), big1_, big_cap_}, Yi;
+    cmul(T4r, T4i, Xr, Xi, Yr, Yi);                                        // [w l | u t]
+    cpermute(Yr, Yi, Ypr, Ypi, {0, 3, 2, 1}, 2);                           // [w t | u l]
+  }
+  if (!cmul_permuted(Ypr, Ypi, a_rot(0, j), a_rot_i_[j % 4], big1_, big_cap_, quad(0, j), quad_i_[j % 4], pq, 2)) {
+    BT Qr{Layout(), big1_, big_cap_}, Qi;
+    cmul(Ypr, Ypi, a_rot(0, j), a_rot_i_[j % 4], Qr, Qi);                  // [w t | d r]
+    cpermute(Qr, Qi, quad(0, j), quad_i_[j % 4], {0, 2, 1, 3}, 2);        // [w d | t r]
+  }
 }
 
 // ---------------------------------------------------------------- move ----
@@ -343,14 +366,25 @@ void Ctm::cmove(int r) {
   cpermute(env_[iT4], env_i_[iT4], T4r, T4i, {0, 1, 2}, 2);         // [w l | c]
   BT Pasr{Layout(), big2_, big_cap_}, Pasi;
   cpermute(Pa, Pai, Pasr, Pasi, {0, 1, 2}, 1);                      // [c | u k]
-  BT Gr{Layout(), big1_, big_cap_}, Gi;
-  cmul(T4r, T4i, Pasr, Pasi, Gr, Gi);                                // [w l | u k]
-  BT Gpr{Layout(), big2_, big_cap_}, Gpi;
-  cpermute(Gr, Gi, Gpr, Gpi, {0, 3, 2, 1}, 2);                      // [w k | u l]
-  BT Hr{Layout(), big1_, big_cap_}, Hi;
-  cmul(Gpr, Gpi, a_rot(0, r), a_rot_i_[r % 4], Hr, Hi);             // [w k | e r]
-  BT Hpr{Layout(), big2_, big_cap_}, Hpi;
-  cpermute(Hr, Hi, Hpr, Hpi, {0, 2, 3, 1}, 2);                      // [w e | r k]
+  // G = T4 P_a [w l | u k] as [w k | u l], then H = G a [w k | e r] as
+  // [w e | r k], written by the products where possible (P_a, in big2_, is
+  // read while G goes to big1_; G is read while H goes to big2_)
+  const int pg[4] = {0, 3, 2, 1}, ph[4] = {0, 2, 3, 1};
+  BT Gpr{Layout(), big1_, big_cap_}, Gpi;
+  if (!cmul_permuted(T4r, T4i, Pasr, Pasi, big1_, big_cap_, Gpr, Gpi, pg, 2)) {
+    Gpr.p = big2_;
+    BT Gr{Layout(), big1_, big_cap_}, Gi;
+    cmul(T4r, T4i, Pasr, Pasi, Gr, Gi);                              // [w l | u k]
+    cpermute(Gr, Gi, Gpr, Gpi, {0, 3, 2, 1}, 2);                    // [w k | u l]
+  }
+  double* other = Gpr.p == big1_ ? big2_ : big1_;
+  BT Hpr{Layout(), other, big_cap_}, Hpi;
+  if (!cmul_permuted(Gpr, Gpi, a_rot(0, r), a_rot_i_[r % 4], other, big_cap_, Hpr, Hpi, ph, 2)) {
+    Hpr.p = Gpr.p;
+    BT Hr{Layout(), other, big_cap_}, Hi;
+    cmul(Gpr, Gpi, a_rot(0, r), a_rot_i_[r % 4], Hr, Hi);           // [w k | e r]
+    cpermute(Hr, Hi, Hpr, Hpi, {0, 2, 3, 1}, 2);                    // [w e | r k]
+  }
   cmul(Pb, Pbi, X2r, X2i, env_[iC1], env_i_[iC1]);                  // [k | t]
   cmul(Zpr, Zpi, Pa, Pai, env_[iC4], env_i_[iC4]);                  // [r | k]
   cmul(Pb, Pbi, Hpr, Hpi, env_[iT4], env_i_[iT4]);                  // [k | r k]
