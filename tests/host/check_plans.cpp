@@ -1,10 +1,13 @@
-// Host-only check of the block planners (no GPU): a contraction written
+// Host-only check of the block planners (no GPU).  The per-sector products
+// (plan_contract) and the block permutations (plan_permute) must agree with
+// dense arithmetic on the full index space.  A contraction written
 // straight into a permuted layout (plan_contract_permuted) must put every
 // element where forming the product and permuting it (plan_contract +
 // plan_permute) puts it.  Both sides are evaluated on the host with a plain
 // triple loop in the same summation order, so the outputs must agree bit
 // for bit, and every element of the permuted tensor must be written once.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <random>
@@ -39,8 +42,116 @@ static void host_copy(const CopyJob& j) {
   }
 }
 
+// dense array (row-major over the legs, each leg's even states first) of a
+// block tensor; entries outside its blocks are zero
+static std::vector<double> to_dense(const BT& x) {
+  const Layout& L = x.L;
+  long long n = 1;
+  for (int i = 0; i < L.r; ++i) n *= L.leg[i].n();
+  std::vector<double> d(n, 0.0);
+  L.for_blocks([&](const int* p) {
+    long long st[kMaxRank];
+    const long long base = L.box(p, st);
+    long long cnt = 1;
+    for (int i = 0; i < L.r; ++i) cnt *= L.leg[i].d(p[i]);
+    for (long long e = 0; e < cnt; ++e) {
+      long long rem = e, src = base, dst = 0;
+      int idx[kMaxRank];
+      for (int i = L.r - 1; i >= 0; --i) {
+        const int dim = L.leg[i].d(p[i]);
+        idx[i] = (int)(rem % dim);
+        rem /= dim;
+        src += idx[i] * st[i];
+      }
+      for (int i = 0; i < L.r; ++i) dst = dst * L.leg[i].n() + (p[i] ? L.leg[i].e : 0) + idx[i];
+      d[dst] = x.p[src];
+    }
+  });
+  return d;
+}
+
+// the block planners against dense arithmetic: C = A B per sector equals the
+// dense contraction over the shared leg, and a permutation of the blocks
+// equals the dense transposition (total parities 0 and 1)
+static int check_against_dense(std::mt19937& rng) {
+  std::uniform_int_distribution<int> dim(0, 3);
+  std::normal_distribution<double> nd;
+  for (int trial = 0; trial < 40; ++trial) {
+    Leg l[5];
+    for (Leg& x : l) {
+      x.e = dim(rng);
+      x.o = dim(rng);
+      if (x.e + x.o == 0) x.o = 1;
+    }
+    const int tpa = trial & 1, tpb = (trial >> 1) & 1;
+    BT A, B;
+    A.L = Layout({l[0], l[1], l[4]}, 2, tpa);
+    B.L = Layout({l[4], l[2], l[3]}, 1, tpb);
+    std::vector<double> a(A.L.size + 1), b(B.L.size + 1), c(8192, 0.0);
+    for (double& x : a) x = nd(rng);
+    for (double& x : b) x = nd(rng);
+    A.p = a.data();
+    B.p = b.data();
+    A.capacity = A.L.size;
+    B.capacity = B.L.size;
+    BT C{Layout(), c.data(), (long long)c.size()};
+    std::vector<GemmDesc> g;
+    plan_contract(A, B, C, 1.0, 0.0, g);
+    for (const GemmDesc& d : g) host_gemm_plain(d);
+    const std::vector<double> da = to_dense(A), db = to_dense(B), dc = to_dense(C);
+    const int n0 = l[0].n(), n1 = l[1].n(), n2 = l[2].n(), n3 = l[3].n(), nk = l[4].n();
+    for (int i0 = 0; i0 < n0; ++i0)
+      for (int i1 = 0; i1 < n1; ++i1)
+        for (int i2 = 0; i2 < n2; ++i2)
+          for (int i3 = 0; i3 < n3; ++i3) {
+            double s = 0.0;
+            for (int k = 0; k < nk; ++k)
+              s += da[((long long)i0 * n1 + i1) * nk + k] * db[((long long)k * n2 + i2) * n3 + i3];
+            const double got = dc[(((long long)i0 * n1 + i1) * n2 + i2) * n3 + i3];
+            if (std::abs(got - s) > 1e-12 * (1.0 + std::abs(s))) {
+              std::printf("FAIL: block contraction differs from the dense one\n");
+              return 1;
+            }
+          }
+    // permutations of C against dense transposition
+    int perm[4] = {0, 1, 2, 3};
+    const int n[4] = {n0, n1, n2, n3};
+    do {
+      for (int nr = 0; nr <= 4; ++nr) {
+        std::vector<double> o(8192, 0.0);
+        BT O{Layout(), o.data(), (long long)o.size()};
+        Layout Lo;
+        Lo.r = 4;
+        Lo.nr = nr;
+        Lo.tp = C.L.tp;
+        for (int j = 0; j < 4; ++j) Lo.leg[j] = C.L.leg[perm[j]];
+        Lo.finalize();
+        O.L = Lo;
+        std::vector<CopyJob> jobs;
+        plan_permute(C, O, perm, jobs);
+        for (const CopyJob& j : jobs) host_copy(j);
+        const std::vector<double> dO = to_dense(O);
+        int idx[4];
+        for (idx[0] = 0; idx[0] < n0; ++idx[0])
+          for (idx[1] = 0; idx[1] < n1; ++idx[1])
+            for (idx[2] = 0; idx[2] < n2; ++idx[2])
+              for (idx[3] = 0; idx[3] < n3; ++idx[3]) {
+                long long at = 0;
+                for (int j = 0; j < 4; ++j) at = at * n[perm[j]] + idx[perm[j]];
+                if (dO[at] != dc[(((long long)idx[0] * n1 + idx[1]) * n2 + idx[2]) * n3 + idx[3]]) {
+                  std::printf("FAIL: block permutation differs from the dense transposition\n");
+                  return 1;
+                }
+              }
+      }
+    } while (std::next_permutation(perm, perm + 4));
+  }
+  return 0;
+}
+
 int main() {
   std::mt19937 rng(12345);
+  if (check_against_dense(rng)) return 1;
   std::uniform_int_distribution<int> dim(0, 3);
   std::normal_distribution<double> nd;
   int planned = 0, refused = 0, cases = 0;

@@ -1,11 +1,14 @@
 """Host-only checks of the block planners (CPU, no GPU): tests/host/*.cpp are
 compiled with the host C++ compiler against the library's headers and run.
 
-check_plans.cpp: a contraction written straight into a permuted layout (the
-enlarged corners and the edge renormalisation) stores every element where
-forming the product and permuting it would, bit for bit, each element once,
-over all 24 leg orders and row splits of random Z2 leg sizes; sectors with an
-empty contraction are left to the separate copy."""
+check_plans.cpp: the Z2 block layout against dense arithmetic (per-sector
+products equal the dense contraction over the shared leg, block permutations
+equal the dense transposition, for total parities 0 and 1 and every leg
+order and row split), and a contraction written straight into a permuted
+layout (the enlarged corners and the edge renormalisation) stores every
+element where forming the product and permuting it would, bit for bit, each
+element once; sectors with an empty contraction are left to the separate
+copy."""
 import os
 import shutil
 import subprocess
