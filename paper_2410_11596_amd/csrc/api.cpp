@@ -492,9 +492,14 @@ int hctm_dev_gemm_scatter(const double* A, const double* B, double* C, int M, in
     d.tb = tb;
     d.alpha = alpha;
     d.beta = beta;
-    d.sc_T = T;
-    d.sc_R = R;
-    for (int q = 0; q < 4; ++q) d.sc_s[q] = strides[q];
+    d.sc_rn = 2;
+    d.sc_cn = 2;
+    d.sc_rd[0] = T;
+    d.sc_cd[0] = R;
+    d.sc_rs[0] = strides[0];
+    d.sc_rs[1] = strides[1];
+    d.sc_cs[0] = strides[2];
+    d.sc_cs[1] = strides[3];
     hctm::gemm({d}, reinterpret_cast<hipStream_t>(stream));
   });
 }

@@ -194,27 +194,29 @@ inline void plan_contract(const BT& A, const BT& B, BT& C, double alpha, double 
   }
 }
 
-// out = alpha (A B) + beta out with its four legs permuted (out leg j = leg
+// out = alpha (A B) + beta out with its legs permuted (out leg j = leg
 // perm[j] of the product, row split nr_out), written by the products: the
 // product's layout is planned at C (never written; capacity checks only),
 // each dense box of the permutation becomes one product over the rows and
-// columns of its box with a scattered output.  Only for rank-2 by rank-2
-// row/column legs; false (nothing planned) otherwise.
+// columns of its box with a scattered output.  For products with one to
+// three row legs and one to three column legs; false (nothing planned)
+// otherwise, or when a sector's contraction is empty.
 inline bool plan_contract_permuted(const BT& A, const BT& B, BT& C, BT& out, const int* perm, int nr_out,
                                    std::vector<GemmDesc>& g, double alpha = 1.0, double beta = 0.0) {
   std::vector<GemmDesc> whole;
   plan_contract(A, B, C, alpha, beta, whole);
   const Layout& Lc = C.L;
-  if (Lc.r != 4 || Lc.nr != 2) return false;
+  const int r = Lc.r, nrc = Lc.nr, ncc = Lc.r - Lc.nr;
+  if (nrc < 1 || nrc > 3 || ncc < 1 || ncc > 3) return false;
   // an empty contracted sector would take the plain C = 0 path of gemm(),
   // which knows nothing of the scattered layout
   for (const GemmDesc& d : whole)
     if (d.K <= 0) return false;
   Layout L;
-  L.r = 4;
+  L.r = r;
   L.nr = nr_out;
   L.tp = Lc.tp;
-  for (int j = 0; j < 4; ++j) L.leg[j] = Lc.leg[perm[j]];
+  for (int j = 0; j < r; ++j) L.leg[j] = Lc.leg[perm[j]];
   L.finalize();
   out.L = L;
   std::vector<CopyJob> jobs;
@@ -228,23 +230,39 @@ inline bool plan_contract_permuted(const BT& A, const BT& B, BT& C, BT& out, con
     if (!src) return false;
     const long long rel = cj.in - src->C;
     const long long row0 = rel / src->ldc, col0 = rel % src->ldc;
-    long long dim[4], is[4], os[4];  // per leg of the product
-    for (int j = 0; j < 4; ++j) {
+    long long dim[kMaxRank], is[kMaxRank], os[kMaxRank];  // per leg of the product
+    for (int j = 0; j < r; ++j) {
       dim[perm[j]] = cj.dims[j];
       is[perm[j]] = cj.istr[j];
       os[perm[j]] = cj.ostr[j];
     }
-    // the box is row-major in the product block: rows (leg 0, leg 1), columns (leg 2, leg 3)
-    if (is[1] != src->ldc || is[0] != dim[1] * src->ldc || is[3] != 1 || is[2] != dim[3]) return false;
+    // the box is row-major in the product block: rows (its row legs, stride
+    // ldc for the last), columns (its column legs, stride 1 for the last)
+    long long rows = 1, cols = 1;
+    for (int i = nrc - 1; i >= 0; --i) {
+      if (is[i] != rows * src->ldc) return false;
+      rows *= dim[i];
+    }
+    for (int i = r - 1; i >= nrc; --i) {
+      if (is[i] != cols) return false;
+      cols *= dim[i];
+    }
     GemmDesc d = *src;
     d.A = src->A + row0 * src->lda;
     d.B = src->B + col0;
     d.C = cj.out;
-    d.M = (int)(dim[0] * dim[1]);
-    d.N = (int)(dim[2] * dim[3]);
-    d.sc_T = (int)dim[1];
-    d.sc_R = (int)dim[3];
-    for (int q = 0; q < 4; ++q) d.sc_s[q] = os[q];
+    d.M = (int)rows;
+    d.N = (int)cols;
+    d.sc_rn = nrc;
+    d.sc_cn = ncc;
+    for (int q = 0; q < 2; ++q) {
+      d.sc_rd[q] = q + 1 < nrc ? (int)dim[q + 1] : 1;
+      d.sc_cd[q] = q + 1 < ncc ? (int)dim[nrc + q + 1] : 1;
+    }
+    for (int q = 0; q < 3; ++q) {
+      d.sc_rs[q] = q < nrc ? os[q] : 0;
+      d.sc_cs[q] = q < ncc ? os[nrc + q] : 0;
+    }
     if (d.M > 0 && d.N > 0) parts.push_back(d);
   }
   g.insert(g.end(), parts.begin(), parts.end());

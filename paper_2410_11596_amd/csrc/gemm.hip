@@ -46,15 +46,31 @@ struct Prob {
   double alpha, beta;
   int M, N, K, lda, ldb, ldc, ta, tb;
   int tiles_m, tiles_n, ksplit, kchunk, tile_start;
-  int sc_T, sc_R;  // scattered output (GemmDesc), 0: row-major C with ldc
-  long long sc_s[4];
+  // scattered output (GemmDesc); sc_rn == 0: row-major C with ldc
+  int sc_rn, sc_cn;
+  int sc_rd[2], sc_cd[2];
+  long long sc_rs[3], sc_cs[3];
 };
+
+// offset of index x of a run of n legs (row-major, sizes of all but the
+// first in d) with strides s
+__device__ __forceinline__ long long leg_offset(int x, int n, const int* d, const long long* s) {
+  if (n == 1) return (long long)x * s[0];
+  if (n == 2) {
+    const int q = x / d[0];
+    return (long long)q * s[0] + (long long)(x - q * d[0]) * s[1];
+  }
+  const int q = x / d[1];
+  const int i0 = q / d[0];
+  return (long long)i0 * s[0] + (long long)(q - i0 * d[0]) * s[1] + (long long)(x - q * d[1]) * s[2];
+}
 
 struct Group {
   Prob p[kMaxGroup];
   int n;
   int total;
 };
+static_assert(sizeof(Group) <= 4096, "a launch's problem list must fit the kernel arguments");
 
 // Load a BK x ROWS slab of op(X) (k-major) into registers.
 template <int ROWS>
@@ -303,22 +319,14 @@ __device__ __forceinline__ void gemm_tile(const Group& g, CT* As, CT* Bs) {
       if (col >= P.N) continue;
       const double cs = P.cscale ? P.cscale[col] : 1.0;
       // column part of the output address
-      long long cpart = col;
-      if (P.sc_T) {
-        const int cq = col / P.sc_R;
-        cpart = cq * P.sc_s[2] + (col - cq * P.sc_R) * P.sc_s[3];
-      }
+      const long long cpart = P.sc_rn ? leg_offset(col, P.sc_cn, P.sc_cd, P.sc_cs) : col;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = m0 + wm + i * 16 + Mfma<CT>::row(lk, v);
         if (row >= P.M) continue;
         double val = P.alpha * (double)acc[i][j][v] * cs;
         if (P.rscale) val *= P.rscale[row];
-        long long rpart = (long long)row * P.ldc;
-        if (P.sc_T) {
-          const int rq = row / P.sc_T;
-          rpart = rq * P.sc_s[0] + (row - rq * P.sc_T) * P.sc_s[1];
-        }
+        const long long rpart = P.sc_rn ? leg_offset(row, P.sc_rn, P.sc_rd, P.sc_rs) : (long long)row * P.ldc;
         double* c = P.C + rpart + cpart;
         if (P.beta != 0.0) val += P.beta * *c;
         *c = val;
@@ -441,7 +449,7 @@ void gemm_one_type(const std::vector<GemmDesc>& probs, int prec, hipStream_t s, 
   for (const GemmDesc& d : probs) {
     if (d.M <= 0 || d.N <= 0) continue;
     if (d.K <= 0) {
-      if (d.sc_T > 0) throw Error(1, "gemm: a scattered output needs K > 0");
+      if (d.sc_rn > 0) throw Error(1, "gemm: a scattered output needs K > 0");
       const long long n = (long long)d.M * d.N;
       hipLaunchKernelGGL(scale_c_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d.C, d.M, d.N, d.ldc,
                          d.beta);
@@ -467,12 +475,21 @@ void gemm_one_type(const std::vector<GemmDesc>& probs, int prec, hipStream_t s, 
     p.tb = d.tb;
     p.tiles_m = (d.M + bm - 1) / bm;
     p.tiles_n = (d.N + bn - 1) / bn;
-    p.sc_T = d.sc_T > 0 && d.sc_R > 0 ? d.sc_T : 0;
-    p.sc_R = d.sc_R;
-    for (int q = 0; q < 4; ++q) p.sc_s[q] = d.sc_s[q];
+    const bool sc = d.sc_rn >= 1 && d.sc_rn <= 3 && d.sc_cn >= 1 && d.sc_cn <= 3;
+    if (d.sc_rn != 0 && !sc) throw Error(1, "gemm: a scattered output takes one to three legs each side");
+    p.sc_rn = sc ? d.sc_rn : 0;
+    p.sc_cn = sc ? d.sc_cn : 0;
+    for (int q = 0; q < 2; ++q) {
+      p.sc_rd[q] = d.sc_rd[q];
+      p.sc_cd[q] = d.sc_cd[q];
+    }
+    for (int q = 0; q < 3; ++q) {
+      p.sc_rs[q] = d.sc_rs[q];
+      p.sc_cs[q] = d.sc_cs[q];
+    }
     // split K when the call has too few output tiles and this K is long
     int ks = 1;
-    if (cfg == 1 && t64 < 4 * kFill && scratch && !p.sc_T) {
+    if (cfg == 1 && t64 < 4 * kFill && scratch && !p.sc_rn) {
       const long long want = (4 * kFill + t64 - 1) / t64;  // about 4 workgroups per CU
       const long long maxk = d.K / 64;  // at least 64 of K per slice
       ks = (int)std::max<long long>(1, std::min(want, maxk));

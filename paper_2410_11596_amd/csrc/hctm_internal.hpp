@@ -39,14 +39,15 @@ struct GemmDesc {
   int prec;              // 0: FP64; 1: operands rounded to FP32, FP32 MFMA and accumulation;
                          // 2: BF16x3 (operands split into BF16 hi + lo, hi*hi + hi*lo + lo*hi
                          //    on BF16 MFMA with FP32 accumulation)
-  // Optional scattered output (sc_T > 0): element (row, col) of the product
-  // is stored at C + (row / sc_T) sc_s[0] + (row % sc_T) sc_s[1]
-  // + (col / sc_R) sc_s[2] + (col % sc_R) sc_s[3] (ldc unused), i.e. a product
-  // whose rows and columns are two legs each, written straight into a layout
-  // with those four legs permuted.  Such a product is not split over K and
-  // must have K > 0.
-  int sc_T, sc_R;
-  long long sc_s[4];
+  // Optional scattered output (sc_rn > 0): the rows of the product are sc_rn
+  // legs (row-major; the sizes of all but the first in sc_rd) and the columns
+  // sc_cn legs (sizes in sc_cd), each of one to three; element (row, col) is
+  // stored at C + sum of leg index * stride (sc_rs, sc_cs; ldc unused).  So a
+  // product is written straight into a layout with its legs permuted.  Such
+  // a product is not split over K and must have K > 0.
+  int sc_rn, sc_cn;
+  int sc_rd[2], sc_cd[2];
+  long long sc_rs[3], sc_cs[3];
 };
 // Optional observer of the kernels gemm() launches, called on the host right
 // before (phase 0) and after (phase 1) each launch: kind 0 a GEMM kernel

@@ -516,11 +516,28 @@ void Hotrg::eig_subspace(std::vector<EigJob>& jobs, uint64_t salt) {
 }
 
 // out[u,x,d,y] = sum U[(l1 l2),x] upper[u,l1,m,r1] lower[m,l2,d,r2] U[(r1 r2),y]
+// The two products before a permutation are written straight into the
+// permuted layout where possible: the product's own layout is only planned
+// (in big1_, never written); the first goes to big2_ as the permutation
+// would, the second to big1_.
 void Hotrg::coarse(const BT& upper, const BT& lower, BT& out) {
   permute(upper, s1_, {0, 2, 3, 1}, 3);  // [u m r1 | l1]
   permute(U_, s2_, {0, 1, 2}, 1);        // [l1 | l2 x]
-  contract(s1_, s2_, big1_);             // [u m r1 | l2 x]
-  permute(big1_, big2_, {0, 2, 4, 1, 3}, 3);  // [u r1 x | m l2]
+  const int p1[5] = {0, 2, 4, 1, 3}, p2[5] = {0, 2, 3, 1, 4};
+  std::vector<GemmDesc> g;
+  if (plan_contract_permuted(s1_, s2_, big1_, big2_, p1, 3, g)) {
+    gemm(g, st_, gscratch_, gscratch_cap_);  // [u m r1 | l2 x] as [u r1 x | m l2]
+  } else {
+    contract(s1_, s2_, big1_);             // [u m r1 | l2 x]
+    permute(big1_, big2_, {0, 2, 4, 1, 3}, 3);  // [u r1 x | m l2]
+  }
+  g.clear();
+  BT Y{Layout(), big1_.p, big1_.capacity};
+  if (plan_contract_permuted(big2_, lower, big1_, Y, p2, 3, g)) {
+    gemm(g, st_, gscratch_, gscratch_cap_);  // [u r1 x | d r2] as [u x d | r1 r2]
+    contract(Y, U_, out);                    // [u x d | y]
+    return;
+  }
   contract(big2_, lower, big1_);         // [u r1 x | d r2]
   permute(big1_, big2_, {0, 2, 3, 1, 4}, 3);  // [u x d | r1 r2]
   contract(big2_, U_, out);              // [u x d | y]

@@ -42,6 +42,19 @@ static void host_copy(const CopyJob& j) {
   }
 }
 
+// offset of index x of a run of n legs (row-major, sizes of all but the
+// first in dd) with strides s: written out independently of the kernel's
+static long long scatter_offset(int x, int n, const int* dd, const long long* s) {
+  long long off = 0;
+  for (int i = n - 1; i >= 0; --i) {
+    const int size = i == 0 ? x + 1 : dd[i - 1];
+    const int idx = i == 0 ? x : x % size;
+    off += (long long)idx * s[i];
+    if (i > 0) x /= size;
+  }
+  return off;
+}
+
 // dense array (row-major over the legs, each leg's even states first) of a
 // block tensor; entries outside its blocks are zero
 static std::vector<double> to_dense(const BT& x) {
@@ -149,102 +162,128 @@ static int check_against_dense(std::mt19937& rng) {
   return 0;
 }
 
+// every leg order and row split of the product of A and B: written straight
+// into the permuted layout against formed and permuted, bit for bit, each
+// element of the permuted tensor once; returns 1 on a mismatch
+static int check_permuted(const BT& A, const BT& B, int r, int& cases, int& planned, int& refused) {
+  int perm[kMaxRank];
+  for (int j = 0; j < r; ++j) perm[j] = j;
+  do {
+    for (int nr = 1; nr < r; ++nr) {
+      ++cases;
+      // reference: form C, then permute it
+      std::vector<double> cbuf(8192), ref(8192, 0.0), got(8192, 0.0);
+      BT C{Layout(), cbuf.data(), (long long)cbuf.size()};
+      std::vector<GemmDesc> g;
+      plan_contract(A, B, C, 1.0, 0.0, g);
+      bool empty_k = false;
+      for (const GemmDesc& d : g) {
+        if (d.K <= 0) empty_k = true;
+        host_gemm_plain(d);
+      }
+      BT R{Layout(), ref.data(), (long long)ref.size()};
+      Layout Lo;
+      Lo.r = r;
+      Lo.nr = nr;
+      Lo.tp = C.L.tp;
+      for (int j = 0; j < r; ++j) Lo.leg[j] = C.L.leg[perm[j]];
+      Lo.finalize();
+      R.L = Lo;
+      std::vector<CopyJob> jobs;
+      plan_permute(C, R, perm, jobs);
+      for (const CopyJob& j : jobs) host_copy(j);
+      // planned: products written straight into the permuted layout
+      std::vector<double> vbuf(8192);
+      BT V{Layout(), vbuf.data(), (long long)vbuf.size()};
+      BT O{Layout(), got.data(), (long long)got.size()};
+      std::vector<GemmDesc> parts;
+      const bool ok = plan_contract_permuted(A, B, V, O, perm, nr, parts);
+      if (ok == empty_k) {
+        std::printf("FAIL: planned %d with an empty contraction %d\n", (int)ok, (int)empty_k);
+        return 1;
+      }
+      if (!ok) {
+        ++refused;
+        continue;
+      }
+      ++planned;
+      std::vector<int> writes(got.size(), 0);
+      for (const GemmDesc& d : parts) {
+        if (d.sc_rn < 1 || d.sc_rn > 3 || d.sc_cn < 1 || d.sc_cn > 3) {
+          std::printf("FAIL: bad scatter descriptor\n");
+          return 1;
+        }
+        for (int rr = 0; rr < d.M; ++rr)
+          for (int c = 0; c < d.N; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < d.K; ++k) s += d.A[(long long)rr * d.lda + k] * d.B[(long long)k * d.ldb + c];
+            const long long at = scatter_offset(rr, d.sc_rn, d.sc_rd, d.sc_rs) +
+                                 scatter_offset(c, d.sc_cn, d.sc_cd, d.sc_cs);
+            double* p = d.C + at;
+            if (p < got.data() || p >= got.data() + O.L.size) {
+              std::printf("FAIL: store outside the permuted tensor\n");
+              return 1;
+            }
+            *p = s;
+            ++writes[p - got.data()];
+          }
+      }
+      if (!(O.L.r == R.L.r && O.L.size == R.L.size)) {
+        std::printf("FAIL: layouts differ\n");
+        return 1;
+      }
+      for (long long e = 0; e < O.L.size; ++e)
+        if (writes[e] != 1 || got[e] != ref[e]) {
+          std::printf("FAIL: element %lld written %d times, %g against %g\n", e, writes[e], got[e], ref[e]);
+          return 1;
+        }
+    }
+  } while (std::next_permutation(perm, perm + r));
+  return 0;
+}
+
 int main() {
   std::mt19937 rng(12345);
   if (check_against_dense(rng)) return 1;
-  std::uniform_int_distribution<int> dim(0, 3);
+  std::uniform_int_distribution<int> dim3(0, 3), dim2(0, 2);
   std::normal_distribution<double> nd;
   int planned = 0, refused = 0, cases = 0;
-  for (int trial = 0; trial < 60; ++trial) {
-    Leg l[5];
-    for (Leg& x : l) {
-      x.e = dim(rng);
-      x.o = dim(rng);
-      if (x.e + x.o == 0) x.e = 1;
-    }
-    // A [l0 l1 | k], B [k | l2 l3], C = A B [l0 l1 | l2 l3]
-    BT A, B;
-    A.L = Layout({l[0], l[1], l[4]}, 2);
-    B.L = Layout({l[4], l[2], l[3]}, 1);
-    std::vector<double> a(A.L.size + 1), b(B.L.size + 1);
-    for (double& x : a) x = nd(rng);
-    for (double& x : b) x = nd(rng);
-    A.p = a.data();
-    A.capacity = A.L.size;
-    B.p = b.data();
-    B.capacity = B.L.size;
-    int perm[4] = {0, 1, 2, 3};
-    do {
-      for (int nr = 1; nr <= 3; ++nr) {
-        ++cases;
-        // reference: form C, then permute it
-        std::vector<double> cbuf(4096), ref(4096, 0.0), got(4096, 0.0);
-        BT C{Layout(), cbuf.data(), (long long)cbuf.size()};
-        std::vector<GemmDesc> g;
-        plan_contract(A, B, C, 1.0, 0.0, g);
-        bool empty_k = false;
-        for (const GemmDesc& d : g) {
-          if (d.K <= 0) empty_k = true;
-          host_gemm_plain(d);
-        }
-        BT R{Layout(), ref.data(), (long long)ref.size()};
-        Layout Lo;
-        Lo.r = 4;
-        Lo.nr = nr;
-        Lo.tp = C.L.tp;
-        for (int j = 0; j < 4; ++j) Lo.leg[j] = C.L.leg[perm[j]];
-        Lo.finalize();
-        R.L = Lo;
-        std::vector<CopyJob> jobs;
-        plan_permute(C, R, perm, jobs);
-        for (const CopyJob& j : jobs) host_copy(j);
-        // planned: products written straight into the permuted layout
-        std::vector<double> vbuf(4096);
-        BT V{Layout(), vbuf.data(), (long long)vbuf.size()};
-        BT O{Layout(), got.data(), (long long)got.size()};
-        std::vector<GemmDesc> parts;
-        const bool ok = plan_contract_permuted(A, B, V, O, perm, nr, parts);
-        if (ok == empty_k) {
-          std::printf("FAIL: planned %d with an empty contraction %d\n", (int)ok, (int)empty_k);
-          return 1;
-        }
-        if (!ok) {
-          ++refused;
-          continue;
-        }
-        ++planned;
-        std::vector<int> writes(got.size(), 0);
-        for (const GemmDesc& d : parts) {
-          if (d.sc_T <= 0 || d.sc_R <= 0 || d.M % d.sc_T || d.N % d.sc_R) {
-            std::printf("FAIL: bad scatter descriptor\n");
-            return 1;
-          }
-          for (int r = 0; r < d.M; ++r)
-            for (int c = 0; c < d.N; ++c) {
-              double s = 0.0;
-              for (int k = 0; k < d.K; ++k) s += d.A[(long long)r * d.lda + k] * d.B[(long long)k * d.ldb + c];
-              const long long at = (r / d.sc_T) * d.sc_s[0] + (r % d.sc_T) * d.sc_s[1] +
-                                   (c / d.sc_R) * d.sc_s[2] + (c % d.sc_R) * d.sc_s[3];
-              double* p = d.C + at;
-              if (p < got.data() || p >= got.data() + O.L.size) {
-                std::printf("FAIL: store outside the permuted tensor\n");
-                return 1;
-              }
-              *p = s;
-              ++writes[p - got.data()];
-            }
-        }
-        if (!(O.L.r == R.L.r && O.L.size == R.L.size)) {
-          std::printf("FAIL: layouts differ\n");
-          return 1;
-        }
-        for (long long e = 0; e < O.L.size; ++e)
-          if (writes[e] != 1 || got[e] != ref[e]) {
-            std::printf("FAIL: element %lld written %d times, %g against %g\n", e, writes[e], got[e], ref[e]);
-            return 1;
-          }
+  // row legs | column legs of the product: 2|2 (enlarged corners, edge),
+  // 3|2 and 2|3 (HOTRG's coarse step), 1|3 and 3|1
+  const int shapes[5][2] = {{2, 2}, {3, 2}, {2, 3}, {1, 3}, {3, 1}};
+  for (int sh = 0; sh < 5; ++sh) {
+    const int nra = shapes[sh][0], ncb = shapes[sh][1], r = nra + ncb;
+    const int trials = r == 4 ? 60 : 12;
+    for (int trial = 0; trial < trials; ++trial) {
+      Leg l[kMaxRank + 1];
+      for (int i = 0; i <= r; ++i) {
+        l[i].e = r == 4 ? dim3(rng) : dim2(rng);
+        l[i].o = r == 4 ? dim3(rng) : dim2(rng);
+        if (l[i].e + l[i].o == 0) l[i].e = 1;
       }
-    } while (std::next_permutation(perm, perm + 4));
+      // A [rows | k], B [k | cols]; leg r is the contracted one
+      BT A, B;
+      A.L.r = nra + 1;
+      A.L.nr = nra;
+      for (int i = 0; i < nra; ++i) A.L.leg[i] = l[i];
+      A.L.leg[nra] = l[r];
+      A.L.tp = 0;
+      A.L.finalize();
+      B.L.r = ncb + 1;
+      B.L.nr = 1;
+      B.L.leg[0] = l[r];
+      for (int i = 0; i < ncb; ++i) B.L.leg[1 + i] = l[nra + i];
+      B.L.tp = 0;
+      B.L.finalize();
+      std::vector<double> a(A.L.size + 1), b(B.L.size + 1);
+      for (double& x : a) x = nd(rng);
+      for (double& x : b) x = nd(rng);
+      A.p = a.data();
+      A.capacity = A.L.size;
+      B.p = b.data();
+      B.capacity = B.L.size;
+      if (check_permuted(A, B, r, cases, planned, refused)) return 1;
+    }
   }
   std::printf("ok: %d cases, %d planned, %d left to the separate copy\n", cases, planned, refused);
   return 0;
