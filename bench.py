@@ -681,8 +681,8 @@ def small_config_oracle_times(warm=3):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20, help="timed iterations (the window is warmup+1 .. warmup+steps)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed iterations before the window")
     ap.add_argument("--dense-steps", type=int, default=None,
                     help="timed iterations of the plain form (default: --steps, the same window as the Z2 form)")
     ap.add_argument("--D", type=int, default=6)
