@@ -380,3 +380,75 @@ def test_product_state_corner_spectra_are_one_state(form):
     for s in o._spec:
         assert abs(s[0] - 1.0) < 1e-14 and np.abs(s[1:]).max() < 1e-14
     assert max(o.deltas) < 1e-14
+
+
+# ------------------------------------------------------------ truncation ----
+def _halves_by_einsum(env, a):
+    """Upper and lower halves of the 4x4 patch, cut open at the west and east.
+
+    Written as two single contractions of the eight environment tensors and
+    two copies of a each, with every index named, so that they share nothing
+    with the oracle's quadrant-by-quadrant route.  Hu[(w,d),(e,f)] is the
+    upper half, Hd[(e,f),(w,d)] the lower one; w, e are the chi legs of the
+    two cut T tensors, d, f the legs of the cut double-layer tensors.
+    """
+    C1, T1, C2, T2, C3, T3, C4, T4 = env.t
+    hu = np.einsum("cx,xut,wlc,uldr,tvy,yz,zse,vrfs->wdef", C1, T1, T4, a, T1, C2, T2, a, optimize=True)
+    hd = np.einsum("egh,hi,ijm,fnjg,mkp,pq,qow,dokn->efwd", T2, C3, T3, a, T3, C4, T4, a, optimize=True)
+    nw = hu.shape[0] * hu.shape[1]
+    ne = hu.shape[2] * hu.shape[3]
+    return hu.reshape(nw, ne), hd.reshape(ne, nw)
+
+
+@pytest.mark.parametrize("form", ["dense", "z2"])
+@pytest.mark.parametrize("chi,tau", [(12, 1e-12), (30, 1e-12), (40, 1e-3)])
+def test_truncation_is_the_best_rank_k_cut(form, chi, tau):
+    """Sec. II A truncation at finite chi, against a dense SVD of the whole loop.
+
+    On a warmed-up, truncated environment (D = 3, so the cut of 12 x 9 = 108
+    is cut down), the projectors of the west cut must give
+    * P_b P_a = 1 on the kept states;
+    * H_d P_a P_b H_u = the best rank-k approximation of M = H_d H_u, with the
+      Frobenius error sqrt(sum of the discarded s^2) (Eckart-Young), where the
+      halves come from an independent contraction;
+    * k = min(chi, #{s > tau s_max}) over the singular values of the whole M,
+      and the recorded spectrum equal to that SVD's, divided by its largest;
+    * in the Z2 form, kept states that live in one parity sector each.
+    A dropped or swapped projector factor, a wrong S power, keeping the wrong
+    states or a mislabelled cut parity each fails one of these.
+    """
+    A = inputs.iid_tensor(2, 3, 4)
+    run = ctmrg.Run(12, form, A=A).step(3)
+    env = run.env.copy()
+    Q = ctmrg.quadrants(env, run.a)
+    pars = None
+    if form == "z2":
+        top, right, bottom, left = env.par
+        pars = ctmrg._cut_parities(left, top, right, bottom, run.par_q)
+    Pa3, Pb3, kcount, rec = ctmrg.cut_projectors(*Q, chi, tau, pars)
+    k = Pa3.shape[2]
+    Pa = Pa3.reshape(-1, k)
+    Pb = Pb3.reshape(k, -1)
+
+    Hu, Hd = _halves_by_einsum(env, run.a)
+    M = Hd @ Hu
+    Wm, s, Vt = np.linalg.svd(M)
+    assert k == max(1, min(chi, int(np.sum(s > tau * s[0]))))
+    assert sum(kcount) == k
+    assert np.allclose(rec["spectrum"][:k], s[:k] / s[0], rtol=1e-9, atol=1e-13)
+
+    assert np.abs(Pb @ Pa - np.eye(k)).max() < 1e-9
+    approx = Hd @ Pa @ Pb @ Hu
+    err = np.linalg.norm(M - approx)
+    want = np.sqrt(np.sum(s[k:] ** 2))
+    assert abs(err - want) <= 1e-8 * s[0] + 1e-6 * want
+    if k < len(s) and s[k] < s[k - 1] * (1 - 1e-6):
+        best = (Wm[:, :k] * s[:k]) @ Vt[:k]
+        assert np.abs(approx - best).max() < 1e-8 * s[0]
+
+    if form == "z2":
+        pW = pars[0]
+        newpar = np.array([0] * kcount[0] + [1] * kcount[1])
+        # every kept column of P_a and row of P_b is zero off its own sector
+        assert np.all(Pa[pW[:, None] != newpar[None, :]] == 0)
+        assert np.all(Pb[newpar[:, None] != pW[None, :]] == 0)
