@@ -452,3 +452,37 @@ def test_truncation_is_the_best_rank_k_cut(form, chi, tau):
         # every kept column of P_a and row of P_b is zero off its own sector
         assert np.all(Pa[pW[:, None] != newpar[None, :]] == 0)
         assert np.all(Pb[newpar[:, None] != pW[None, :]] == 0)
+
+
+# ------------------------------------------------------ symmetry error ----
+def _blocks(D, seed, total):
+    """Random real 4-leg tensor in the eigenbasis of S with only the blocks of
+    the given total parity (0 even, 1 odd), and its Frobenius norm."""
+    p = basis.leg_parity(D)
+    x = np.random.default_rng(seed).standard_normal((D * D,) * 4)
+    x = np.where(basis.parity_mask([p] * 4) == (total == 0), x, 0.0)
+    return x, np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_s_err_known_values(D):
+    """Sec. III A's S_err on tensors built with a known split into the parts
+    that the bra-ket swap keeps and flips.  In the eigenbasis of S the swap
+    on all four legs is the sign (-1)^(total parity), so a tensor with even
+    blocks X and odd blocks Y has e^dag = X - Y and S_err = |Y| / |X|; for
+    complex e = X + iY' (X, Y' even) the conjugation flips the sign of Y'
+    instead, and for e = X + iY (Y odd) swap and conjugation cancel, S_err
+    = 0.  A missing conjugate, a normalisation by |e| or a swap on only
+    some legs fails one of these."""
+    U = basis.hermitian_basis(D)
+    X, nx = _blocks(D, 1, 0)
+    Y, ny = _blocks(D, 2, 1)
+    Y2, ny2 = _blocks(D, 3, 0)
+    c = 0.37
+    e = basis.unrotate(X + c * Y, U)
+    assert abs(ctmrg.s_err_of(e) - c * ny / nx) < 1e-14
+    e = basis.unrotate(X, U) + 1j * c * basis.unrotate(Y2, U)
+    assert abs(ctmrg.s_err_of(e) - c * ny2 / nx) < 1e-14
+    e = basis.unrotate(X, U) + 1j * c * basis.unrotate(Y, U)
+    assert ctmrg.s_err_of(e) < 1e-14
+    assert ctmrg.s_err_of(basis.unrotate(X, U)) < 1e-14
