@@ -88,6 +88,24 @@ def test_workspace_size_grows_with_chi_and_cell(L):
     assert rc == 0 and big < 16 * 2**30
 
 
+def test_workspace_size_at_the_limits(L):
+    """The largest accepted sizes give finite sizes that keep growing (no
+    overflow of the size arithmetic), one past them is rejected, and the
+    smallest problem is accepted."""
+    rc, one = _ws(L, 1, 1, 1)
+    assert rc == 0 and one > 0
+    rc, a = _ws(L, 2, 8, 4096)
+    assert rc == 0
+    rc, b = _ws(L, 16, 8, 4096)
+    assert rc == 0 and b > a
+    rc, c = _ws(L, 16, 8, 4096, Lx=4, Ly=4)
+    assert rc == 0 and c > b and c < 2**62
+    assert _ws(L, 2, 8, 4097)[0] == binding.CTM_E_ARG
+    assert _ws(L, 2, 8, 4096, Lx=5)[0] == binding.CTM_E_ARG
+    # one GPU's 288 GB holds a D = 6 solve up to chi of about 1500
+    assert _ws(L, 2, 6, 1500)[1] < 288e9 < _ws(L, 2, 6, 1600)[1]
+
+
 @pytest.mark.parametrize("d,D,chi", [(0, 2, 8), (17, 2, 8), (2, 0, 8), (2, 9, 8), (2, 2, 0), (2, 2, 5000)])
 def test_size_checks(L, d, D, chi):
     rc, _ = _ws(L, d, D, chi)
