@@ -3,7 +3,8 @@ reference.
 
 The HIP CTMRG runs on perturbed product states (a 1x1 cell in both forms, a
 3x2 cell of six different tensors, a complex tensor in the real
-representation of Sec. II C) and is compared with the oracle after the same
+representation of Sec. II C, a C4v-symmetric tensor in the C4v scheme) and
+is compared with the oracle after the same
 iterations (1e-10 on RDM entries, energies and ln kappa) and with the
 infinite cylinder of the oracle's pins (the leading eigenvectors of its row
 transfer matrix), which shares nothing with either CTMRG.  The cylinder
@@ -12,7 +13,7 @@ bounds are the oracle pins' own, since the GPU adds at most 1e-10 to them.
 import numpy as np
 import pytest
 
-from oracle import cell, complex_z2, ctmrg
+from oracle import c4v, cell, complex_z2, ctmrg
 from paper_2410_11596_amd import inputs
 from test_oracle_cylinder import _cylinder_cell, _cylinder_of
 
@@ -92,3 +93,21 @@ def test_complex_perturbed_product_state():
     assert np.abs(g.rdm1() - r1).max() < 2e-10
     assert np.abs(g.rdm2("h") - rh).max() < 2e-10
     assert np.abs(g.rdm2("v") - rv).max() < 2e-10
+
+
+@pytest.mark.parametrize("form", ["dense", "z2"])
+def test_c4v_perturbed_product_state(form):
+    A = inputs.product_state([1.0, 0.0], 2) + 0.2 * inputs.c4v_iid_tensor(2, 2, 5)
+    print(f"C4v perturbed product D=2 chi=8 form={form}", flush=True)
+    g = _gpu(A, 8, form=form, c4v=True).step(20)
+    o = c4v.C4vRun(8, form, A=A).step(20)
+    h = ctmrg.heisenberg_bond()
+    assert np.abs(g.rdm1() - o.rho1()).max() < TOL
+    assert np.abs(g.rdm2("h") - o.rho2("h")).max() < TOL
+    assert abs(g.energy(h) - o.energy(h)) < TOL
+    assert abs(g.log_kappa() - o.log_kappa()) < TOL
+    f, r1, rh, rv = _cylinder_of(A, 7)
+    assert abs(g.log_kappa() - f) < 5e-11 + TOL
+    assert np.abs(g.rdm1() - r1).max() < 2e-10 + TOL
+    assert np.abs(g.rdm2("h") - rh).max() < 5e-10 + TOL
+    assert np.abs(g.rdm2("v") - rv).max() < 5e-10 + TOL
