@@ -107,7 +107,12 @@ typedef struct {
 /* Fill *o with the defaults above. */
 int ctm_opts_default(ctm_opts* o);
 
-/* Device bytes a context with these sizes needs (for ctm_opts.workspace). */
+/* Device bytes a context with these sizes needs (for ctm_opts.workspace):
+ * the double layers and the environment tensors C, T of Sec. II A for every
+ * site, the enlarged corners, and the work arrays of the truncations.  It
+ * grows as (chi D^2)^2.  Errors: CTM_E_ARG for sizes or options that ctm_init
+ * would refuse; a size too large for the device is not an error here (the
+ * allocation in ctm_init reports CTM_E_NOMEM). */
 int ctm_workspace_size(int d, int D, int chi, const ctm_opts* o, size_t* bytes);
 
 /*
@@ -139,7 +144,10 @@ int ctm_step(ctm_ctx* c, int n_iter);
 
 /* Precision of the block products of the following ctm_step calls
  * (CTM_PREC_FP64, CTM_PREC_FP32 or CTM_PREC_BF16X3); the environment is
- * kept. */
+ * kept.  The paper computes in FP64 throughout; the lower precisions are an
+ * option of this library for the products of Sec. II A, with FP64 iterations
+ * afterwards to reach the FP64 fixed point.  Errors: CTM_E_ARG for another
+ * value, or for FP32 or BF16X3 on a complex-tensor context (FP64 only). */
 int ctm_set_precision(ctm_ctx* c, int precision);
 
 /*
@@ -155,12 +163,16 @@ int ctm_converged(ctm_ctx* c, double tol, int* converged, double* delta);
 
 /*
  * Current spectrum of corner `corner` (0 C1 up-left, 1 C2 up-right, 2 C3
- * down-right, 3 C4 down-left) of site (x, y): the singular values of both
+ * down-right, 3 C4 down-left; the corner matrices of Sec. II A, Fig. 1d) of
+ * site (x, y): the singular values of both
  * sectors merged in descending order, divided by their sum, zero padded;
  * *n = its length max(chi, D^2).  s: host array of cap >= *n doubles, or
  * NULL to query *n.  These are the vectors ctm_converged compares.
  */
 int ctm_corner_spectrum(ctm_ctx* c, int x, int y, int corner, double* s, int cap, int* n);
+/* (The paper names no convergence measure; the change of these spectra is
+ * the one used here.  Errors: CTM_E_ARG for a bad site or corner, or
+ * cap < *n with s not NULL.  Synchronises.) */
 
 /*
  * Health of the truncations run so far (Sec. II B, point (3); Sec. III A):
@@ -223,28 +235,35 @@ int ctm_energy(ctm_ctx* c, const double* h, double* e);
 int ctm_workspace_size_complex(int d, int D, int chi, const ctm_opts* o, size_t* bytes);
 
 /* Create a context for the complex tensor A = A_re + i A_im (host, d*D^4
- * doubles each, legs [s,u,l,d,r], copied).  Requires 1 <= d <= 8,
+ * doubles each, legs [s,u,l,d,r], copied), whose double layer has the
+ * real/imaginary block structure of Sec. II C.  Requires 1 <= d <= 8,
  * 1 <= D <= 8, 1 <= chi <= 4096, finite entries; ctm_opts as for ctm_init
  * with form CTM_FORM_Z2, a 1 x 1 cell, c4v = 0 and CTM_PREC_FP64 (else
  * CTM_E_ARG). */
 int ctm_init_complex(ctm_ctx** out, const double* A_re, const double* A_im, int d, int D, int chi,
                      const ctm_opts* o);
 
-/* Hermitian one-site RDM of a complex-tensor context, rho = rho_re + i rho_im
+/* Hermitian one-site RDM (Sec. II C; Hermitian by construction as Sec. II B
+ * point (3) promises for the symmetric basis) of a complex-tensor context,
+ * rho = rho_re + i rho_im
  * (host, d*d each, row-major), trace one: the entries on and above the
  * diagonal from the environment, the others their conjugates.  (x, y) must
  * be (0, 0).  Synchronises. */
 int ctm_rdm_1site_complex(ctm_ctx* c, int x, int y, double* rho_re, double* rho_im);
 
-/* Hermitian two-site RDM [(s1 s2)][(s1' s2')] of a complex-tensor context
+/* Hermitian two-site RDM (Sec. II C, as ctm_rdm_1site_complex)
+ * [(s1 s2)][(s1' s2')] of a complex-tensor context
  * (host, d^4 each), dir 0 horizontal, 1 vertical; (x, y) must be (0, 0).
  * Synchronises. */
 int ctm_rdm_2site_complex(ctm_ctx* c, int x, int y, int dir, double* rho_re, double* rho_im);
 
-/* Release everything; NULL is accepted. */
+/* Release everything; NULL is accepted.  (Resource handling of this
+ * library; no passage of the paper.) */
 void ctm_free(ctm_ctx* c);
 
-/* Message of the last error on this context (never NULL). */
+/* Message of the last error on this context, or of the calling thread's last
+ * failed ctm_init for NULL (never NULL).  (Error handling of this library;
+ * no passage of the paper.) */
 const char* ctm_last_error(const ctm_ctx* c);
 
 /* ---- diagnostics used by the tests ------------------------------------ */
@@ -258,21 +277,27 @@ int ctm_env_epsilon(ctm_ctx* c, int x, int y, double* eps);
  * the largest over the sites. */
 int ctm_s_err(ctm_ctx* c, double* s_err);
 
-/* ln of the partition function per site, kappa = Z11 Z00 / (Z10 Z01);
- * 1 x 1 cell only (CTM_E_ARG otherwise). */
+/* ln of the partition function per site of the double-layer network of
+ * Sec. II A (Fig. 1), kappa = Z11 Z00 / (Z10 Z01) from the converged
+ * environment: Z11 the 3x3 patch with the centre tensor, Z00 the four
+ * corners alone, Z10 and Z01 the patches with one row or one column of
+ * edges.  The paper prints no formula for it; this is the standard one.
+ * 1 x 1 cell only (CTM_E_ARG otherwise).  Synchronises. */
 int ctm_log_kappa(ctm_ctx* c, double* ln_kappa);
 
-/* Number of truncations run so far (one per cut: a move of an Lx x Ly cell
- * truncates Lx*Ly cuts). */
+/* Number of truncations (the SVD cuts of Sec. II A) run so far, one per
+ * cut: a move of an Lx x Ly cell truncates Lx*Ly cuts. */
 int ctm_num_records(ctm_ctx* c, int* n);
 
-/* Status bits of truncation m: 1 (2) the even (odd) sector's subspace
+/* Status bits of truncation m (the per-sector SVDs of Sec. II B point
+ * (3)): 1 (2) the even (odd) sector's subspace
  * iteration reached its cap without passing the residual test, 4 the chi cut
  * split a near-degenerate multiplet (see ctm_svd_health). */
 int ctm_record_status(ctm_ctx* c, int m, int* status);
 
 /*
- * Record of truncation m (0-based, in the order run): the kept singular
+ * Record of truncation m (0-based, in the order run; Sec. II A truncation,
+ * per sector as in Sec. II B point (3)): the kept singular
  * values of the decomposed matrix, merged over both sectors in descending
  * order and divided by the largest, and the kept sector sizes.  s: host array
  * of at least cap doubles.  info (may be NULL): 8 ints, the frame of the move
@@ -286,7 +311,8 @@ int ctm_record(ctm_ctx* c, int m, double* s, int cap, int* n, int* k_even, int* 
 
 /* Current boundary bond on side 0..3 (top, right, bottom, left) of site
  * (x, y): the bond of the edge tensor's first leg (T1's left, T2's up, T3's
- * right, T4's down leg), its even and odd sizes. */
+ * right, T4's down leg), its even and odd sizes (the Z2 sectors of
+ * Sec. II B; the plain form reports all states as even). */
 int ctm_sector_dims(ctm_ctx* c, int x, int y, int side, int* chi_even, int* chi_odd);
 
 /* GPU seconds of the last ctm_step call per phase of the moves:
@@ -296,14 +322,17 @@ int ctm_sector_dims(ctm_ctx* c, int x, int y, int side, int* chi_even, int* chi_
  * *n = 5. */
 int ctm_timing(ctm_ctx* c, double* t, int cap, int* n);
 
-/* Profile mode only (ctm_opts.profile = 1): algorithmic FP64 GEMM flops
+/* Measurement of the block products whose cost Sec. III B compares (no
+ * passage defines it).  Profile mode only (ctm_opts.profile = 1):
+ * algorithmic FP64 GEMM flops
  * (2*M*N*K per block product), the summed durations in seconds of the GEMM
  * kernel launches (a HIP event right before and right after each) and their
  * number since the last reset; reset != 0 clears them (and the reduction
  * figures below). */
 int ctm_gemm_stats(ctm_ctx* c, double* flops, double* seconds, long long* launches, int reset);
 
-/* Profile mode only: the summed durations and the number of the split-K
+/* Measurement, as ctm_gemm_stats.  Profile mode only: the summed
+ * durations and the number of the split-K
  * reductions that follow GEMM launches whose K was split over workgroups. */
 int ctm_gemm_reduce_stats(ctm_ctx* c, double* seconds, long long* launches);
 

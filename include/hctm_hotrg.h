@@ -64,26 +64,31 @@ int hotrg_opts_default(hotrg_opts* o);
 
 /*
  * Create a context: copies A (host, d*D^4 doubles, legs [s,u,l,d,r]) and
- * forms the double layer (in the rotated basis in the Z2 form) as the
- * initial tensor, divided by its norm.  Requires 1 <= d <= 16, 1 <= D <= 6,
+ * forms the double layer (Sec. II A, Fig. 1b; in the eigenbasis of the swap
+ * in the Z2 form, Sec. II B) as the initial tensor, divided by its norm.  Requires 1 <= d <= 16, 1 <= D <= 6,
  * 1 <= chi, max(chi, D^2) <= 64; finite A.  *out is NULL on failure.
  */
 int hotrg_init(hotrg_ctx** out, const double* A, int d, int D, int chi, const hotrg_opts* o);
 
-/* Run n >= 0 steps.  A step fails with CTM_E_ARG (before any GPU work of
+/* Run n >= 0 coarse-graining steps (Sec. II A; per parity sector in the Z2
+ * form, Sec. II B point (3)).  A step fails with CTM_E_ARG (before any GPU work of
  * that step) if a sector of a Gram matrix exceeds 4096 rows, the limit of
  * the eigensolver (only the plain form at chi = 64 reaches it exactly). */
 int hotrg_step(hotrg_ctx* c, int n);
 
-/* ln Z per site of the torus of 2^k sites after k steps.  Synchronises. */
+/* ln Z per site of the torus of 2^k sites after k steps (the formula in the
+ * file comment; the paper prints none, it is the standard one).
+ * Synchronises. */
 int hotrg_log_z(hotrg_ctx* c, double* lnz);
 
-/* Probe mode only: z_b = Z_b / Z, z_abs = Z_|b| / Z and err = |z_b| / |z_abs|
- * (any pointer may be NULL).  Synchronises. */
+/* Probe mode only (the symmetry probe of Sec. III A, Fig. 3):
+ * z_b = Z_b / Z, z_abs = Z_|b| / Z and err = |z_b| / |z_abs| (any pointer
+ * may be NULL).  Synchronises. */
 int hotrg_sym_error(hotrg_ctx* c, double* err, double* z_b, double* z_abs);
 
 /*
- * Bond energy: h (host, d^2 x d^2 doubles, row-major, h[(s1 s2),(s1' s2')],
+ * Bond energy (Sec. III: the Heisenberg model's energy is the observable the
+ * paper reports): h (host, d^2 x d^2 doubles, row-major, h[(s1 s2),(s1' s2')],
  * site 1 above site 2 on a vertical bond, ket indices s, bra indices s') is
  * written as sum_{a,b} |a><b| (x) O_ab with O_ab[s2,s2'] = h[(a s2),(b s2')]
  * (in the Z2 form regrouped into symmetric and antisymmetric pairs, the
@@ -99,7 +104,8 @@ int hotrg_set_bond(hotrg_ctx* c, const double* h);
 int hotrg_energy(hotrg_ctx* c, double* e);
 
 /*
- * One-site RDM: carries the impurities a[|s><s'|] (in the Z2 form only the
+ * One-site RDM (Hermitian by construction in the Z2 form, Sec. II B point
+ * (3)): carries the impurities a[|s><s'|] (in the Z2 form only the
  * symmetric parts (|s><s'| + |s'><s|)/2, s <= s', whose double layers are
  * even: the RDM is symmetric by construction).  Must be called before the
  * first step; d <= 4.
@@ -109,7 +115,7 @@ int hotrg_track_rdm1(hotrg_ctx* c);
 /* rho[s][s'] (host, d*d), trace one, after hotrg_track_rdm1.  Synchronises. */
 int hotrg_rdm1(hotrg_ctx* c, double* rho);
 
-/* Number of steps run. */
+/* Number of steps run (one truncation each, Sec. II A). */
 int hotrg_num_records(hotrg_ctx* c, int* n);
 
 /*
@@ -122,10 +128,10 @@ int hotrg_record(hotrg_ctx* c, int i, double* spectrum, int cap, int* n, int* k_
                  double* discarded);
 
 /* Last error message of c (or of the calling thread's last failed init for
- * NULL). */
+ * NULL).  (Error handling of this library; no passage of the paper.) */
 const char* hotrg_last_error(const hotrg_ctx* c);
 
-/* Release everything; NULL is accepted. */
+/* Release everything; NULL is accepted.  (Resource handling; no passage.) */
 void hotrg_free(hotrg_ctx* c);
 
 #ifdef __cplusplus

@@ -16,6 +16,11 @@
  * solve runs the same code on its own context as it would alone, so its
  * results do not depend on what else runs (bit for bit).
  *
+ * The paper has no serving component: each solve is the CTMRG of Sec. II A
+ * (in the eigenbasis of Sec. II B for CTM_FORM_Z2) run to the convergence
+ * test of ctm_converged, and the calls below are the queueing, memory and
+ * thread handling around such solves, defined by this library alone.
+ *
  * All functions return CTM_OK or an error code of hctm.h.  One server may be
  * used from several host threads.
  */

@@ -43,7 +43,8 @@ int hctm_dev_gemm_bf16x3(const double* A, const double* B, double* C, int M, int
                          int ldc, int ta, int tb, double alpha, double beta, const double* cscale, double* scratch,
                          long long scratch_doubles, void* stream);
 
-/* Probes of the chip's own ceilings (reported beside the published peaks).
+/* Probes of the chip's own ceilings (reported beside the published peaks;
+ * measurement only, no passage of the paper).
  * hctm_dev_mfma_probe: blocks workgroups of four waves, each wave issuing
  * 32 * iters rounds of eight independent FP64 16 x 16 x 4 matrix-core products
  * with no memory traffic; sink (device, blocks * 256 doubles) receives the
@@ -55,15 +56,19 @@ int hctm_dev_mfma_probe(double* sink, int blocks, int iters, double* flops, void
 int hctm_dev_stream_probe(const double* in, double* out, long long n, void* stream);
 
 /* Strided copy of a dense box of rank r <= 6: out[sum x_j ostr_j] =
- * in[sum x_j istr_j] (the permute-and-reshape step between block products). */
+ * in[sum x_j istr_j] (the permute-and-reshape step between the block
+ * products of Sec. II B). */
 int hctm_dev_copy(const double* in, double* out, int r, const int* dims, const long long* istr,
                   const long long* ostr, void* stream);
 
-/* Rinv = R^-1 with G + rel*max(diag G)*I = R^T R (R upper triangular);
+/* CholeskyQR step of the truncated SVD (the SVD of Sec. II A, done per
+ * sector as in Sec. II B point (3), by subspace iteration here):
+ * Rinv = R^-1 with G + rel*max(diag G)*I = R^T R (R upper triangular);
  * G (n x n) is overwritten; info[0] = 0 unless a pivot was not positive. */
 int hctm_dev_chol_inv(double* G, double* Rinv, int n, double rel, int* info, void* stream);
 
-/* One-sided Jacobi SVD of X (m x n, row-major, overwritten by U*Sigma in
+/* The small SVD of the truncation (Sec. II A, per sector as in Sec. II B
+ * point (3)): one-sided Jacobi SVD of X (m x n, row-major, overwritten by U*Sigma in
  * column order); sv = singular values descending, perm = their columns,
  * sweeps[0] = sweeps used (negative: no convergence within max_sweeps).
  * If V is not NULL (X square), V (n x n, row-major) receives the product of
