@@ -181,3 +181,47 @@ def test_rho1_symmetric_in_z2_and_forms_agree():
     v = np.array([0.6, -0.8])
     r = hotrg.Run(8, "z2", A=inputs.product_state(v, 2), rdm1=True).step(4).rho1()
     assert np.abs(r - np.outer(v, v)).max() < 1e-14
+
+
+@pytest.mark.parametrize("form", ["dense", "z2"])
+@pytest.mark.parametrize("chi", [6, 12])
+def test_isometry_is_the_best_rank_k_cut(form, chi):
+    """One truncated HOTRG step (H2, H3) against a plain SVD of both
+    matricisations of the joined tensor M: U has orthonormal columns; the
+    discarded weight of each side is ||M - U U^T M||^2 with that side's U,
+    and equals the sum of the squared singular values past the kept count
+    (Eckart-Young), k = min(chi, #{s^2 > tau s_max^2}); the side taken is
+    the one that discards less (the left one on a tie); the kept spectrum is
+    that side's s^2 / s_max^2; in the Z2 form every column of U lies in one
+    parity sector.  A Gram matrix of the wrong side, keeping the wrong
+    eigenvectors or taking the worse side fails one of these."""
+    A = inputs.iid_tensor(2, 2, 6)
+    r = hotrg.Run(chi, form, A=A).step(2)
+    M = hotrg.join_vertical(r.T, r.T)
+    ph = r.ph if form == "z2" else None
+    U, side, kept, spec, errs = hotrg.isometry(M, chi, 1e-12, ph)
+    n = M.shape[1] * M.shape[2]
+    k = U.shape[1]
+    assert sum(kept) == k
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-12
+
+    mats = (M.transpose(1, 2, 0, 3, 4, 5).reshape(n, -1), M.transpose(4, 5, 0, 1, 2, 3).reshape(n, -1))
+    want = []
+    for Mm in mats:
+        s = np.linalg.svd(Mm, compute_uv=False)
+        kk = min(chi, int(np.sum(s ** 2 > 1e-12 * s[0] ** 2)))
+        assert kk == k
+        want.append((float(np.sum(s[kk:] ** 2)), s[:kk] ** 2 / s[0] ** 2))
+    total = float(np.sum(mats[0] ** 2))
+    for sd in (0, 1):
+        assert abs(errs[sd] - want[sd][0]) < 1e-10 * total
+    assert want[0][0] > 1e-8 * total and want[1][0] > 1e-8 * total  # both sides truncate
+    best = 0 if want[0][0] <= want[1][0] + 1e-10 * total else 1
+    assert side == best
+    assert np.allclose(spec, want[side][1], rtol=1e-9, atol=1e-14)
+    Mm = mats[side]
+    assert abs(np.sum((Mm - U @ (U.T @ Mm)) ** 2) - want[side][0]) < 1e-10 * total
+    if form == "z2":
+        pf = ((ph[:, None] + ph[None, :]) % 2).reshape(-1)
+        newp = np.array([0] * kept[0] + [1] * kept[1])
+        assert np.all(U[pf[:, None] != newp[None, :]] == 0)
