@@ -442,6 +442,30 @@ def _stream_ptr(torch):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _need(t, lo, hi, name):
+    """t must be a float64 device tensor whose elements cover [lo, hi): the
+    kernels behind these hooks take raw pointers and cannot check."""
+    torch = _torch()
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise ValueError(f"{name}: a float64 device tensor")
+    if hi > lo and (lo < 0 or hi > t.numel()):
+        raise ValueError(f"{name}: the call reaches elements [{lo}, {hi}) of a tensor of {t.numel()}")
+
+
+def _span(rows, cols, ld):
+    """Elements spanned by a row-major rows x cols operand with leading dimension ld."""
+    return 0 if rows <= 0 or cols <= 0 else (rows - 1) * ld + cols
+
+
+def _box(offset, dims, strides):
+    """[lowest, highest + 1) of the offsets offset + sum x_j strides_j, 0 <= x_j < dims_j."""
+    if any(d <= 0 for d in dims):
+        return 0, 0
+    lo = offset + sum((d - 1) * s for d, s in zip(dims, strides) if s < 0)
+    hi = offset + sum((d - 1) * s for d, s in zip(dims, strides) if s > 0)
+    return lo, hi + 1
+
+
 def dev_gemm(A, B, C, M, N, K, lda, ldb, ldc, ta=0, tb=0, alpha=1.0, beta=0.0, cscale=None, scratch=None,
              f32=False, precision=None):
     """precision: 'fp64' (default), 'fp32' or 'bf16x3' (f32=True is 'fp32')."""
@@ -451,6 +475,13 @@ def dev_gemm(A, B, C, M, N, K, lda, ldb, ldc, ta=0, tb=0, alpha=1.0, beta=0.0, c
     sn = scratch.numel() if scratch is not None else 0
     p = precision or ("fp32" if f32 else "fp64")
     f = {"fp64": lib().hctm_dev_gemm, "fp32": lib().hctm_dev_gemm_f32, "bf16x3": lib().hctm_dev_gemm_bf16x3}[p]
+    _need(A, 0, _span(K, M, lda) if ta else _span(M, K, lda), "A")
+    _need(B, 0, _span(N, K, ldb) if tb else _span(K, N, ldb), "B")
+    _need(C, 0, _span(M, N, ldc), "C")
+    if cscale is not None:
+        _need(cscale, 0, max(N, 0), "cscale")
+    if scratch is not None:
+        _need(scratch, 0, 0, "scratch")
     _check(f(_ptr(A), _ptr(B), _ptr(C), M, N, K, lda, ldb, ldc, ta, tb, alpha, beta, cs, sp, sn, _stream_ptr(torch)))
 
 
@@ -458,6 +489,10 @@ def dev_gemm_scatter(A, B, C, M, N, K, lda, ldb, T, R, strides, ta=0, tb=0, alph
     """alpha op(A) op(B) + beta C with element (i0 T + i1, i2 R + i3) stored at
     C + sum_q i_q strides[q]."""
     torch = _torch()
+    _need(A, 0, _span(K, M, lda) if ta else _span(M, K, lda), "A")
+    _need(B, 0, _span(N, K, ldb) if tb else _span(K, N, ldb), "B")
+    if T >= 1 and R >= 1 and M % T == 0 and N % R == 0:  # else the library refuses the call
+        _need(C, *_box(0, [M // T, T, N // R, R], [int(x) for x in strides]), "C")
     s = (ctypes.c_longlong * 4)(*[int(x) for x in strides])
     _check(lib().hctm_dev_gemm_scatter(_ptr(A), _ptr(B), _ptr(C), M, N, K, lda, ldb, ta, tb, alpha, beta, T, R, s,
                                        _stream_ptr(torch)))
@@ -489,6 +524,8 @@ def dev_copy(src, dst, dims, istr, ostr, in_offset=0, out_offset=0):
     d = (ctypes.c_int * r)(*dims)
     i = (ctypes.c_longlong * r)(*istr)
     o = (ctypes.c_longlong * r)(*ostr)
+    _need(src, *_box(in_offset, dims, istr), "src")
+    _need(dst, *_box(out_offset, dims, ostr), "dst")
     ip = ctypes.c_void_p(src.data_ptr() + 8 * in_offset)
     op = ctypes.c_void_p(dst.data_ptr() + 8 * out_offset)
     _check(lib().hctm_dev_copy(ip, op, r, d, i, o, _stream_ptr(torch)))

@@ -230,3 +230,15 @@ def test_hotrg_argument_checks_before_touching_a_device(L):
     assert L.hotrg_step(None, 1) == binding.CTM_E_ARG
     assert L.hotrg_log_z(None, None) == binding.CTM_E_ARG
     L.hotrg_free(None)
+
+
+def test_hook_extents():
+    """The extents the binding checks before a raw-pointer test hook runs."""
+    assert binding._span(50, 60, 90) == 49 * 90 + 60
+    assert binding._span(0, 60, 90) == 0 and binding._span(70, 0, 90) == 0
+    assert binding._box(0, [2, 3], [3, 1]) == (0, 6)
+    assert binding._box(5, [4], [-1]) == (2, 6)
+    assert binding._box(0, [3, 0], [1, 1]) == (0, 0)
+    # the scattered product's box: [M/T, T, N/R, R] over a permuted (a0, a2, a1, a3) array
+    a0, a1, a2, a3 = 3, 4, 5, 6
+    assert binding._box(0, [a0, a1, a2, a3], [a2 * a1 * a3, a3, a1 * a3, 1]) == (0, a0 * a1 * a2 * a3)
