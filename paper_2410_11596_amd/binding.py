@@ -442,12 +442,12 @@ def _stream_ptr(torch):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _need(t, lo, hi, name):
-    """t must be a float64 device tensor whose elements cover [lo, hi): the
+def _need(t, lo, hi, name, dtype="float64"):
+    """t must be a device tensor of dtype whose elements cover [lo, hi): the
     kernels behind these hooks take raw pointers and cannot check."""
     torch = _torch()
-    if t.dtype != torch.float64 or not t.is_cuda:
-        raise ValueError(f"{name}: a float64 device tensor")
+    if t.dtype != getattr(torch, dtype) or not t.is_cuda:
+        raise ValueError(f"{name}: a {dtype} device tensor")
     if hi > lo and (lo < 0 or hi > t.numel()):
         raise ValueError(f"{name}: the call reaches elements [{lo}, {hi}) of a tensor of {t.numel()}")
 
@@ -533,11 +533,29 @@ def dev_copy(src, dst, dims, istr, ostr, in_offset=0, out_offset=0):
 
 def dev_chol_inv(G, Rinv, n, rel, info):
     torch = _torch()
+    _need(G, 0, max(n, 0) ** 2, "G")
+    _need(Rinv, 0, max(n, 0) ** 2, "Rinv")
+    _need(info, 0, 1, "info", "int32")
     _check(lib().hctm_dev_chol_inv(_ptr(G), _ptr(Rinv), n, rel, _ptr(info), _stream_ptr(torch)))
+
+
+def _jacobi_need(X, m, n, max_sweeps, sv, perm, sweeps, V, pre):
+    mn = max(m, 0) * max(n, 0)
+    _need(X, 0, mn, "X")
+    _need(sv, 0, max(n, 0), "sv")
+    _need(perm, 0, max(n, 0), "perm", "int32")
+    _need(sweeps, 0, 2 if 2 <= pre < n else 1, "sweeps", "int32")
+    if V is not None:
+        _need(V, 0, max(n, 0) ** 2, "V")
 
 
 def dev_jacobi(X, m, n, tol, max_sweeps, sv, perm, sweeps, V=None, vlog=None, pre=0, work=None):
     torch = _torch()
+    _jacobi_need(X, m, n, max_sweeps, sv, perm, sweeps, V, pre)
+    if vlog is not None:
+        _need(vlog, 0, jacobi_log_doubles(n, max_sweeps), "vlog")
+    if work is not None:
+        _need(work, 0, max(m, 0) * max(n, 0), "work")
     vp = _ptr(V) if V is not None else None
     lp = _ptr(vlog) if vlog is not None else None
     wp = _ptr(work) if work is not None else None
@@ -549,6 +567,7 @@ def dev_jacobi_noalloc(X, m, n, tol, max_sweeps, sv, perm, sweeps, V=None, pre=0
     """hctm_dev_jacobi_noalloc: the Jacobi SVD with its scratch in the
     library's static device buffer (no allocation)."""
     torch = _torch()
+    _jacobi_need(X, m, n, max_sweeps, sv, perm, sweeps, V, pre)
     vp = _ptr(V) if V is not None else None
     _check(lib().hctm_dev_jacobi_noalloc(_ptr(X), m, n, tol, max_sweeps, pre, _ptr(sv), _ptr(perm), _ptr(sweeps), vp,
                                          _stream_ptr(torch)))
