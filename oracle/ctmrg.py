@@ -23,6 +23,14 @@ Readings where the paper is silent (it simplifies to C4v and gives no move):
   * the initial environment traces the boundary legs with a vector b
     (b = sum_k |k k> for a double layer, i.e. the open boundary).
 
+Pins (tests/test_oracle_pins.py, tests/test_oracle_cylinder.py): exact
+finite patches, the Ising model's closed forms, product states, one
+truncated cut against a dense SVD (Eckart-Young), and converged fixed points
+of short-ranged correlated states against infinite cylinders.  Parity
+unpinned: the finite-chi fixed point on i.i.d. tensors, for which neither a
+closed form nor a fast-converging cylinder exists; it rests on the
+agreement of the plain and Z2 forms and on the pins above.
+
 Tensor legs (counter-clockwise, sites at (x, y) with y downwards):
   a[u,l,d,r]; C1[d,r] T1[l,d,r] C2[l,d] T2[u,l,d] C3[u,l] T3[r,u,l]
   C4[r,u] T4[d,r,u].  Bond parities (Z2 form) are kept per side of the
