@@ -28,8 +28,9 @@ finite patches, the Ising model's closed forms, product states, one
 truncated cut against a dense SVD (Eckart-Young), and converged fixed points
 of short-ranged correlated states against infinite cylinders.  Parity
 unpinned: the finite-chi fixed point on i.i.d. tensors, for which neither a
-closed form nor a fast-converging cylinder exists; it rests on the
-agreement of the plain and Z2 forms and on the pins above.
+closed form nor a fast-converging cylinder exists (at D = 2 a cylinder
+bounds it only to 2e-4); it rests on the agreement of the plain and Z2
+forms and on the pins above.
 
 Tensor legs (counter-clockwise, sites at (x, y) with y downwards):
   a[u,l,d,r]; C1[d,r] T1[l,d,r] C2[l,d] T2[u,l,d] C3[u,l] T3[r,u,l]
