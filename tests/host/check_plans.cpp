@@ -1,6 +1,8 @@
 // Host-only check of the block planners (no GPU).  The per-sector products
 // (plan_contract) and the block permutations (plan_permute) must agree with
-// dense arithmetic on the full index space.  A contraction written
+// dense arithmetic on the full index space, and packing between a plain
+// array and the blocks (plan_pack) must keep exactly the entries of the
+// tensor's total parity.  A contraction written
 // straight into a permuted layout (plan_contract_permuted) must put every
 // element where forming the product and permuting it (plan_contract +
 // plan_permute) puts it.  Both sides are evaluated on the host with a plain
@@ -162,6 +164,72 @@ static int check_against_dense(std::mt19937& rng) {
   return 0;
 }
 
+// plan_pack between a plain array and the blocks, for every rank 1..4, row
+// split and total parity, the plain array both row-major and with its legs
+// stored in reverse order: packing keeps exactly the entries whose leg
+// parities add up to the total parity (a leg's index is odd from its even
+// count on), read back by an index walk of its own; unpacking into a zeroed
+// array gives the masked plain array back
+static int check_pack(std::mt19937& rng) {
+  std::uniform_int_distribution<int> dim(0, 3);
+  std::normal_distribution<double> nd;
+  for (int trial = 0; trial < 60; ++trial) {
+    const int r = 1 + trial % 4;
+    for (int nr = 0; nr <= r; ++nr)
+      for (int tp = 0; tp <= 1; ++tp)
+        for (int rev = 0; rev <= 1; ++rev) {
+          BT t;
+          t.L.r = r;
+          t.L.nr = nr;
+          t.L.tp = tp;
+          for (int i = 0; i < r; ++i) {
+            t.L.leg[i].e = dim(rng);
+            t.L.leg[i].o = dim(rng);
+            if (t.L.leg[i].n() == 0) t.L.leg[i].o = 1;
+          }
+          t.L.finalize();
+          int n[kMaxRank];
+          long long total = 1;
+          for (int i = 0; i < r; ++i) total *= (n[i] = t.L.leg[i].n());
+          // plain strides: row-major over the legs, or over the legs reversed
+          long long ps[kMaxRank];
+          long long s = 1;
+          for (int k = 0; k < r; ++k) {
+            const int i = rev ? k : r - 1 - k;
+            ps[i] = s;
+            s *= n[i];
+          }
+          std::vector<double> plain(total), blocks(t.L.size + 1, 0.0), back(total, 0.0);
+          for (double& x : plain) x = nd(rng);
+          t.p = blocks.data();
+          t.capacity = t.L.size;
+          std::vector<CopyJob> jobs;
+          plan_pack(plain.data(), ps, t, true, jobs);
+          for (const CopyJob& j : jobs) host_copy(j);
+          const std::vector<double> dense = to_dense(t);  // row-major over the legs
+          std::vector<CopyJob> back_jobs;
+          plan_pack(back.data(), ps, t, false, back_jobs);
+          for (const CopyJob& j : back_jobs) host_copy(j);
+          for (long long e = 0; e < total; ++e) {
+            long long rem = e, at = 0;
+            int par = 0;
+            for (int i = r - 1; i >= 0; --i) {
+              const int x = (int)(rem % n[i]);
+              rem /= n[i];
+              at += x * ps[i];
+              par += x >= t.L.leg[i].e;
+            }
+            const double want = (par % 2 == tp) ? plain[at] : 0.0;
+            if (dense[e] != want || back[at] != want) {
+              std::printf("FAIL: plan_pack (rank %d, split %d, parity %d, reversed %d)\n", r, nr, tp, rev);
+              return 1;
+            }
+          }
+        }
+  }
+  return 0;
+}
+
 // every leg order and row split of the product of A and B: written straight
 // into the permuted layout against formed and permuted, bit for bit, each
 // element of the permuted tensor once; returns 1 on a mismatch
@@ -245,6 +313,7 @@ static int check_permuted(const BT& A, const BT& B, int r, int& cases, int& plan
 int main() {
   std::mt19937 rng(12345);
   if (check_against_dense(rng)) return 1;
+  if (check_pack(rng)) return 1;
   std::uniform_int_distribution<int> dim3(0, 3), dim2(0, 2);
   std::normal_distribution<double> nd;
   int planned = 0, refused = 0, cases = 0;

@@ -8,7 +8,9 @@ order and row split), and a contraction written straight into a permuted
 layout (the enlarged corners and the edge renormalisation) stores every
 element where forming the product and permuting it would, bit for bit, each
 element once; sectors with an empty contraction are left to the separate
-copy."""
+copy; packing between a plain array and the blocks keeps exactly the
+entries of the tensor's total parity, for plain arrays stored row-major and
+with their legs reversed."""
 import os
 import shutil
 import subprocess
