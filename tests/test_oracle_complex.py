@@ -135,3 +135,38 @@ def test_real_representation_equals_plain_complex(D, chi, iters):
     assert abs(z.energy() - p.energy()) < 1e-10
     assert np.abs(r1 - r1.conj().T).max() < 1e-15
     assert z.s_err() < 1e-14
+
+
+@pytest.mark.parametrize("chi", [6, 14])
+def test_truncated_cut_is_the_best_rank_k_cut(chi):
+    """One cut of the real representation (reading: M decomposed through the
+    real R = D^-1 M D) against a complex SVD of the whole loop: with the
+    halves contracted independently from the complex tensors, P_b P_a = 1,
+    ||M - H_d P_a P_b H_u|| is the discarded weight (Eckart-Young), k =
+    min(chi, #{s > tau s_max}) and the recorded spectrum is M's.  A sign of
+    D^-1 M D, or of the imaginary part of V or W, fails these."""
+    from test_oracle_pins import _halves_by_einsum
+
+    A = _ctensor(2, 3, 21)
+    run = complex_z2.Run(12, A).step(3)
+    env = run.env
+    top, right, bottom, left = env.par
+    pq = run.par_q
+    pW = ((left[:, None] + pq[None, :]) % 2).reshape(-1)
+    pE = ((right[:, None] + pq[None, :]) % 2).reshape(-1)
+    Q = complex_z2.quadrants(env.t, run.at)
+    Pa, Pb, rec = complex_z2.cut_projectors(*Q, chi, 1e-12, pW, pE)
+    k = Pa.shape[2]
+    Pa = complex_z2.from_rep(Pa).reshape(-1, k)
+    Pb = complex_z2.from_rep(Pb).reshape(k, -1)
+
+    plain = ctmrg.Env([complex_z2.from_rep(x) for x in env.t])
+    Hu, Hd = _halves_by_einsum(plain, complex_z2.from_rep(run.at))
+    M = Hd @ Hu
+    s = np.linalg.svd(M, compute_uv=False)
+    assert k == max(1, min(chi, int(np.sum(s > 1e-12 * s[0]))))
+    assert np.allclose(rec["spectrum"][:k], s[:k] / s[0], rtol=1e-9, atol=1e-13)
+    assert np.abs(Pb @ Pa - np.eye(k)).max() < 1e-9
+    err = np.linalg.norm(M - Hd @ Pa @ Pb @ Hu)
+    want = np.sqrt(np.sum(s[k:] ** 2))
+    assert abs(err - want) <= 1e-8 * s[0] + 1e-6 * want
