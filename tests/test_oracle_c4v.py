@@ -65,3 +65,32 @@ def test_dense_and_z2_forms_agree(D, chi):
         k = sum(rz["kept"])
         assert k == sum(rp["kept"])
         assert np.allclose(rz["spectrum"][:k], rp["spectrum"][:k], rtol=1e-8, atol=1e-13)
+
+
+@pytest.mark.parametrize("form", ["dense", "z2"])
+@pytest.mark.parametrize("chi", [10, 25])
+def test_truncation_keeps_the_largest_moduli(form, chi):
+    """One C4v truncation (Sec. II A, reading R16) against an eigendecomposition
+    of the enlarged corner contracted independently: the corner is symmetric;
+    the kept count is min(chi, #{|lambda| > tau |lambda|_max}) over both
+    sectors and the recorded spectrum is the largest moduli; the new corner
+    P^T Q P is diagonal with those moduli (normalised).  Keeping by value
+    instead of modulus, or one sector only, fails these."""
+    A = inputs.c4v_iid_tensor(2, 3, 1)
+    run = c4v.C4vRun(12, form, A=A).step(3)
+    env = run.env.copy()
+    C1, T1, _, _, _, _, _, T4 = env.t
+    Q = np.einsum("cx,xut,wlc,uldr->wdtr", C1, T1, T4, run.a)
+    n = Q.shape[0] * Q.shape[1]
+    M = Q.reshape(n, n)
+    assert np.abs(M - M.T).max() < 1e-12 * np.abs(M).max()
+    lam = np.linalg.eigvalsh(M)
+    assert lam.min() < 0 < lam.max()  # both signs occur, so value and modulus orders differ
+    mod = np.sort(np.abs(lam))[::-1]
+    rec = c4v.c4v_move(env, run.a, chi, 1e-12, run.par_q)
+    k = sum(rec["kept"])
+    assert k == min(chi, int(np.sum(mod > 1e-12 * mod[0])))
+    assert np.allclose(rec["spectrum"][:k], mod[:k] / mod[0], rtol=1e-9, atol=1e-13)
+    Cn = env.t[0]
+    assert np.abs(Cn - np.diag(np.diag(Cn))).max() < 1e-10
+    assert np.allclose(np.sort(np.abs(np.diag(Cn)))[::-1], mod[:k] / np.linalg.norm(mod[:k]), rtol=1e-8, atol=1e-13)
