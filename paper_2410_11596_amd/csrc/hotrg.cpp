@@ -494,7 +494,11 @@ void Hotrg::eig_subspace(std::vector<EigJob>& jobs, uint64_t salt) {
         const double* h = host_ + 5000 + 400 * i;
         const int* inf = reinterpret_cast<const int*>(h + 390);
         if (inf[0] < 0) throw Error(4, "HOTRG: the Jacobi step of the Rayleigh-Ritz projection did not converge");
-        if (inf[2] != 0) throw Error(4, "HOTRG: CholeskyQR of the subspace broke down");
+        // inf[2] counts the columns that CholeskyQR dropped as numerically
+        // dependent, which happens when a Gram sector's rank is below the
+        // block (near a product state).  They are zero columns of Q: their
+        // Ritz values are zero and fall below the cutoff, as in the CTMRG
+        // truncation, so they are not an error.
         double rmax = 0.0;
         for (int c = 0; c < J->kc; ++c) rmax = std::max(rmax, h[200 + c]);
         const double lam1 = h[0];

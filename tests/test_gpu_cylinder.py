@@ -1,19 +1,20 @@
 """GPU parity on correlated states, against the oracle and an independent
 reference.
 
-The HIP CTMRG runs on perturbed product states (a 1x1 cell in both forms, a
-3x2 cell of six different tensors, a complex tensor in the real
-representation of Sec. II C, a C4v-symmetric tensor in the C4v scheme) and
-is compared with the oracle after the same
-iterations (1e-10 on RDM entries, energies and ln kappa) and with the
-infinite cylinder of the oracle's pins (the leading eigenvectors of its row
-transfer matrix), which shares nothing with either CTMRG.  The cylinder
-bounds are the oracle pins' own, since the GPU adds at most 1e-10 to them.
+The HIP path runs on perturbed product states: CTMRG on a 1x1 cell in both
+forms, on a 3x2 cell of six different tensors, on a complex tensor in the
+real representation of Sec. II C and on a C4v-symmetric tensor in the C4v
+scheme, and HOTRG for the free energy.  Each is compared with the oracle
+after the same iterations (1e-10 on RDM entries, energies, ln kappa and
+ln Z) and with the infinite cylinder of the oracle's pins (the leading
+eigenvectors of its row transfer matrix), which shares nothing with either.
+The cylinder bounds are the oracle pins' own, since the GPU adds at most
+1e-10 to them.
 """
 import numpy as np
 import pytest
 
-from oracle import c4v, cell, complex_z2, ctmrg
+from oracle import c4v, cell, complex_z2, ctmrg, hotrg
 from paper_2410_11596_amd import inputs
 from test_oracle_cylinder import _cylinder_cell, _cylinder_of
 
@@ -111,3 +112,17 @@ def test_c4v_perturbed_product_state(form):
     assert np.abs(g.rdm1() - r1).max() < 2e-10 + TOL
     assert np.abs(g.rdm2("h") - rh).max() < 5e-10 + TOL
     assert np.abs(g.rdm2("v") - rv).max() < 5e-10 + TOL
+
+
+@pytest.mark.parametrize("form", ["dense", "z2"])
+def test_hotrg_perturbed_product_state(form):
+    from paper_2410_11596_amd import HOTRG
+
+    A = inputs.perturbed_product(2, 2, 0, eps=0.05)
+    print(f"HOTRG perturbed product D=2 chi=12 form={form}", flush=True)
+    g = HOTRG(A, 12, form=form)
+    g.step(30)
+    o = hotrg.Run(12, form, A=A).step(30)
+    assert abs(g.log_z() - o.log_z()) < TOL
+    f = _cylinder_of(A, 7)[0]
+    assert abs(g.log_z() - f) < 2e-7 + TOL
