@@ -73,7 +73,11 @@ int hotrg_init(hotrg_ctx** out, const double* A, int d, int D, int chi, const ho
 /* Run n >= 0 coarse-graining steps (Sec. II A; per parity sector in the Z2
  * form, Sec. II B point (3)).  A step fails with CTM_E_ARG (before any GPU work of
  * that step) if a sector of a Gram matrix exceeds 4096 rows, the limit of
- * the eigensolver (only the plain form at chi = 64 reaches it exactly). */
+ * the eigensolver (only the plain form at chi = 64 reaches it exactly), and
+ * with CTM_E_NUMERIC (context poisoned) if the Jacobi step of a Rayleigh-Ritz
+ * projection does not converge.  A Gram sector whose rank is below the
+ * subspace block is not an error: its missing directions have eigenvalue
+ * zero and fall below the cutoff. */
 int hotrg_step(hotrg_ctx* c, int n);
 
 /* ln Z per site of the torus of 2^k sites after k steps (the formula in the
